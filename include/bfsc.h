@@ -1,0 +1,248 @@
+/*
+ * bfsc -- lossless compression of BFS frontiers on one MI355X (gfx950).
+ *
+ * C-ABI of libbfsc.so.  The operations follow the BFS-with-compression
+ * algorithm of Romera, "Optimizing Communication by Compression for Multi-GPU
+ * Scalable Breadth-First Searches" (arXiv 1704.00513): each BFS level expands
+ * the frontier (the SpMV step of the "Our Baseline algorithm" section), the
+ * newly reached vertices are split by owning rank (the row exchange,
+ * ALLTOALLV), and every outgoing sorted vertex list is compressed before the
+ * exchange and decompressed after it ("Communication before and after
+ * compression" section and its detailed integration algorithm).  Nothing here
+ * sends data between GPUs: one GPU processes its share, segment by segment.
+ *
+ * Conventions (all entry points):
+ *  - Pointers named *_dev or documented as "device" are device memory of the
+ *    context's GPU, allocated and owned by the caller.  Host pointers are
+ *    documented as such.  The library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call only enqueues work on `stream` and returns; nothing waits for
+ *    the GPU except bfsc_sync_status and the functions documented as
+ *    synchronous.
+ *  - Return value: BFSC_OK, or an error detected on the host before anything
+ *    was enqueued (BFSC_E_INVAL for bad arguments, BFSC_E_HIP when a HIP call
+ *    fails).  Errors found by kernels (damaged stream, output capacity,
+ *    unsorted input) are latched in the context and reported by
+ *    bfsc_sync_status; output contents are then unspecified.
+ *  - Calls on one context must be serialised by the caller (one stream at a
+ *    time).  Workspaces are per call unless documented otherwise.
+ *  - Sizes of device arrays that a kernel reads from device memory (frontier
+ *    lengths, segment offsets) are never read back by the host, so every
+ *    entry point can be captured into a HIP graph.
+ *
+ * Stream format of one compressed segment (little-endian 32-bit words):
+ *   header    16 B : n (IDs), lo, hi (the segment's ID range [lo, hi)), magic 0x31434642
+ *   directory 8 B per block of 128 IDs: first (= v0 - lo), class u8, param u8, aux u16
+ *   group tab 4 B per 16 blocks: payload word offset of block 16g in this segment
+ *   payloads  a whole number of words per block, in block order
+ * Block classes: 0 = dense bitmap of the span after v0 (param 0, aux = span,
+ * span <= 4096); 1..33 = delta bit-packing at width class-1 (param = width,
+ * the binary packing of the compression-techniques section, delta coding with
+ * eq. (6)/(7) widths); 34 = PFOR, patched coding with exceptions (eqs. (8),
+ * (9); param = b, aux = E | h << 8): low b bits of every delta, E exception
+ * positions as bytes, then the E high parts at h bits.  Bit i of a packed
+ * field stream is bit (i mod 32) of word i/32.  Segments of a batch are
+ * concatenated, word aligned; their byte offsets are kept out of band.
+ */
+#ifndef BFSC_H
+#define BFSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfsc_ctx bfsc_ctx;
+
+enum {
+    BFSC_OK = 0,
+    BFSC_E_INVAL = 1,        /* bad argument, or (from the GPU) unsorted / out-of-range IDs */
+    BFSC_E_CAPACITY = 2,     /* output buffer too small */
+    BFSC_E_CORRUPT = 3,      /* damaged compressed stream */
+    BFSC_E_HIP = 4,          /* a HIP runtime call failed */
+    BFSC_E_UNIMPLEMENTED = 5
+};
+
+/* Codec choice per block. */
+enum {
+    BFSC_SEL_PLAIN_BP = 0,   /* bit-packing at the minimal width (the paper's S4-BP128-like plain method) */
+    BFSC_SEL_EXHAUSTIVE = 1, /* fewest payload words among bitmap / all widths / PFOR */
+    BFSC_SEL_LEARNED = 2     /* MLP prediction, resolved to a valid class (exhaustive fallback) */
+};
+
+/* Operations for bfsc_workspace_size. */
+enum {
+    BFSC_OP_BFS = 0,
+    BFSC_OP_SELECT = 1,
+    BFSC_OP_ENCODE = 2,
+    BFSC_OP_DECODE = 3,
+    BFSC_OP_FEATURES = 4,
+    BFSC_OP_MLP = 5
+};
+
+/* One GPU's CSR partition: a row range with global column IDs; on one GPU
+ * the whole graph (the replicated-CSR layout of the baseline algorithm).
+ * row_ptr u64[n_vertices+1] and col_idx u32[n_arcs] are device pointers;
+ * each row's neighbours need not be sorted. */
+typedef struct {
+    uint32_t n_vertices;
+    uint64_t n_arcs;
+    const uint64_t *row_ptr;
+    const uint32_t *col_idx;
+} bfsc_csr;
+
+/* A batch of segments to compress (device pointers):
+ *   ids       u32[max_ids]     the segments' IDs back to back; each segment
+ *                              strictly increasing and inside [seg_lo, seg_hi)
+ *   seg_off   u64[nseg+1]      segment r is ids[seg_off[r] .. seg_off[r+1])
+ *   seg_lo/hi u32[nseg]        each segment's vertex-ID range (its destination)
+ *   seg_level i32[nseg] / NULL BFS level of each segment (a selector feature)
+ * max_ids (host value) bounds seg_off[nseg]; it sizes grids and workspaces. */
+typedef struct {
+    const uint32_t *ids;
+    const uint64_t *seg_off;
+    const uint32_t *seg_lo;
+    const uint32_t *seg_hi;
+    const int32_t *seg_level;
+    uint32_t nseg;
+    uint64_t max_ids;
+} bfsc_batch;
+
+/* Adam settings for the selector's training step. */
+typedef struct {
+    float lr, beta1, beta2, eps;
+} bfsc_adam;
+
+/* Launch shapes of the codec kernels (chosen by bfsc_autotune or set). */
+typedef struct {
+    uint32_t enc_waves;      /* waves per workgroup, encode (1..16) */
+    uint32_t enc_wg_per_cu;  /* resident workgroups per CU for the persistent grid */
+    uint32_t dec_waves;
+    uint32_t dec_wg_per_cu;
+} bfsc_tune;
+
+/* Creates a context on HIP device `device`: queries the device, allocates
+ * the error word and the selector's parameters (device memory owned by the
+ * context).  Synchronous.  *out is NULL on failure. */
+int bfsc_create(bfsc_ctx **out, int device);
+int bfsc_destroy(bfsc_ctx *ctx);
+
+/* Bytes of workspace an operation needs for a batch of at most max_ids IDs
+ * in nseg segments (BFSC_OP_MLP: max_ids = samples per call; BFSC_OP_BFS is
+ * sized by bfsc_bfs_workspace_size instead).  The caller
+ * allocates it (any alignment of at least 256 B) and passes it as `ws`. */
+int bfsc_workspace_size(const bfsc_ctx *ctx, int op, uint64_t max_ids, uint32_t nseg,
+                        size_t *bytes);
+
+/* Bytes of BFS workspace for graph g (visited and next-level bitmaps, the
+ * compaction counters and the queue of high-degree adjacency chunks). */
+int bfsc_bfs_workspace_size(const bfsc_csr *g, size_t *bytes);
+
+/* Initialises a traversal from `root`: level[] = -1 and parent[] = -1 except
+ * level[root] = 0, parent[root] = root; frontier[0] = root and
+ * *frontier_len_dev = 1; clears the visited state kept in `ws`.  The same
+ * `ws` (bfsc_bfs_workspace_size bytes) must be passed to every bfsc_bfs_level call of the
+ * traversal. */
+int bfsc_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *level,
+                  int32_t *parent, uint32_t *frontier, uint32_t *frontier_len_dev,
+                  void *ws, void *stream);
+
+/* One top-down BFS level (the SpMV step t = A (x) f, then t masked by the
+ * visited list, of the baseline algorithm): every unvisited neighbour w of
+ * the frontier gets level[w] = cur_level + 1 and a parent u in the frontier
+ * with (u, w) an arc (any such u may win).  Writes the new frontier
+ * next[0 .. *next_len_dev) sorted ascending (capacity n_vertices).
+ * frontier (u32, length *frontier_len_dev on the device) must be the previous
+ * level's output. */
+int bfsc_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *frontier,
+                   const uint32_t *frontier_len_dev, int32_t *level, int32_t *parent,
+                   uint32_t *next, uint32_t *next_len_dev, void *ws, void *stream);
+
+/* Splits a sorted frontier ids[0 .. *n_dev) by destination vertex range:
+ * seg_off[r] = number of IDs below bounds[r] for r < nseg, seg_off[nseg] =
+ * *n_dev.  bounds u32[nseg+1] non-decreasing.  No data is copied (the row
+ * split of the ALLTOALLV exchange).  All pointers device. */
+int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds,
+                   uint32_t nseg, uint64_t *seg_off, void *stream);
+
+/* Chooses a class per block (0 bitmap, 1..33 bit-pack width 0..32, 34 PFOR)
+ * for every 128-ID block of every segment, in segment order: classes u8,
+ * capacity ceil(max_ids/128) + nseg.  BFSC_SEL_LEARNED resolves the MLP's
+ * prediction to a valid class (bitmap -> exhaustive if the span is too wide,
+ * any width -> the minimal width, PFOR kept); blocks that fell back are
+ * counted in *fallbacks_dev (u64, device, may be NULL; added to). */
+int bfsc_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes,
+                uint64_t *fallbacks_dev, void *ws, void *stream);
+
+/* Upper bound of the compressed size of any batch of n_ids IDs in nseg
+ * segments (host arithmetic). */
+int bfsc_encode_bound(uint64_t n_ids, uint32_t nseg, size_t *bytes);
+
+/* Compresses a batch (the compress step before each exchange of the
+ * BFS-with-compression algorithm).  classes: u8 per block as produced by
+ * bfsc_select, or NULL to choose with `mode` inside the encoder.  Writes the
+ * segments back to back into out (capacity out_cap bytes) and
+ * seg_byte_off u64[nseg+1] (device): segment r occupies
+ * out[seg_byte_off[r] .. seg_byte_off[r+1]).  Overflow latches
+ * BFSC_E_CAPACITY; unsorted or out-of-range IDs latch BFSC_E_INVAL. */
+int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int mode,
+                uint8_t *out, size_t out_cap, uint64_t *seg_byte_off, void *ws, void *stream);
+
+/* Decompresses nseg segments (the decompress step after each exchange).
+ * in: the compressed bytes; seg_byte_off u64[nseg+1] their boundaries.
+ * Writes the IDs back to back into out_ids (capacity out_cap IDs) and
+ * out_off u64[nseg+1] (segment r -> out_ids[out_off[r] .. out_off[r+1])).
+ * Validates while decoding; a damaged stream latches BFSC_E_CORRUPT and never
+ * reads or writes outside the given buffers.  max_ids bounds the total. */
+int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
+                void *ws, void *stream);
+
+/* Selector features: 8 fp16 values per block (bit patterns as u16, row
+ * major [block][8]): n/128, bitlen(min delta)/32, bitlen(max delta)/32,
+ * bitlen(floor(span/m))/32, bitlen(span)/32, fp16(fp32(n)/fp32(span+1)),
+ * min(level,63)/64, bitlen(segment length)/32. */
+int bfsc_features(bfsc_ctx *ctx, const bfsc_batch *b, uint16_t *feat, void *ws, void *stream);
+
+/* Selector network 8 -> 64 -> 64 -> 35 (ReLU), fp32 master parameters in the
+ * order W1[64][8] b1[64] W2[64][64] b2[64] W3[35][64] b3[35] (7,011 floats).
+ * set/get copy host <-> context and are synchronous; set resets Adam state. */
+int bfsc_mlp_param_count(void);
+int bfsc_mlp_set_weights(bfsc_ctx *ctx, const float *host_params);
+int bfsc_mlp_get_weights(bfsc_ctx *ctx, float *host_params);
+
+/* Logits f32[n][35] for fp16 features X u16[n][8] (device): weights rounded
+ * to fp16, hidden layers fp16(relu(W h + b)), fp32 accumulation. */
+int bfsc_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, void *ws,
+                     void *stream);
+
+/* Gradient f32[7011] (device) of the mean softmax cross-entropy over
+ * (X u16[n][8], y u8[n]), straight-through at the fp16 rounding points;
+ * *loss_dev (f32, device, may be NULL) receives the loss. */
+int bfsc_mlp_grad(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n, float *grads,
+                  float *loss_dev, void *ws, void *stream);
+
+/* One Adam step on the context's parameters from the gradient of a batch. */
+int bfsc_mlp_train_step(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n,
+                        const bfsc_adam *opt, float *loss_dev, void *ws, void *stream);
+
+/* Launch shapes: read, set, or measure on a sample batch (synchronous; the
+ * sample must be valid input; ws sized for BFSC_OP_ENCODE of the sample). */
+int bfsc_get_tune(const bfsc_ctx *ctx, bfsc_tune *out);
+int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t);
+int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *stream);
+
+/* Waits for `stream`, reads and clears the latched kernel error word:
+ * returns BFSC_OK or the first error class found (CORRUPT > CAPACITY > INVAL). */
+int bfsc_sync_status(bfsc_ctx *ctx, void *stream);
+
+/* Static string for a status code. */
+const char *bfsc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFSC_H */

@@ -536,7 +536,8 @@ static int decode_segment(const uint8_t *seg, uint64_t bytes, uint32_t *out, uin
             if (bb > 32 || bb + h > 32 || (uint64_t)10 * E > m) return ST_CORRUPT;
             uint64_t lw = ceil_div((uint64_t)m * bb, 32), qw = ceil_div(E, 4);
             wc = lw + qw + ceil_div((uint64_t)E * h, 32);
-            if (pw + wc > avail) return ST_CORRUPT;
+            /* no block payload is larger than the block's raw 128 words */
+            if (wc > BLK || pw + wc > avail) return ST_CORRUPT;
             uint64_t d[BLK];
             for (uint32_t j = 1; j <= m; ++j) d[j] = get_bits(words + pw, (uint64_t)(j - 1) * bb, bb);
             int64_t last = -1;

@@ -1,0 +1,286 @@
+// C-ABI entry points of libbfsc.so: argument checks on the host, workspace
+// carving, and kernel launches on the caller's stream (declared in bfsc.h).
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.hpp"
+
+using namespace bfsc;
+
+namespace bfsc {
+size_t bfs_ws_bytes_arcs(uint32_t V, uint64_t n_arcs);
+int launch_round16(bfsc_ctx *ctx, hipStream_t s);
+}
+
+#define HIP_OK(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) return BFSC_E_HIP;   \
+    } while (0)
+
+static inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+static int set_device(const bfsc_ctx *ctx) {
+    return hipSetDevice(ctx->device) == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+static bool batch_ok(const bfsc_batch *b) {
+    return b && b->ids && b->seg_off && b->seg_lo && b->seg_hi && b->nseg > 0 &&
+           b->max_ids < (1ull << 40);
+}
+
+extern "C" {
+
+int bfsc_create(bfsc_ctx **out, int device) {
+    if (!out) return BFSC_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BFSC_E_INVAL;
+    HIP_OK(hipSetDevice(device));
+    bfsc_ctx *c = new (std::nothrow) bfsc_ctx();
+    if (!c) return BFSC_E_HIP;
+    memset(c, 0, sizeof(*c));
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return BFSC_E_HIP; }
+    c->n_cu = prop.multiProcessorCount;
+    const size_t np = kNParams;
+    if (hipMalloc((void **)&c->err, 256) != hipSuccess ||
+        hipMalloc((void **)&c->mlp_params, np * 4) != hipSuccess ||
+        hipMalloc((void **)&c->adam_m, np * 4) != hipSuccess ||
+        hipMalloc((void **)&c->adam_v, np * 4) != hipSuccess ||
+        hipMalloc((void **)&c->mlp_grad, np * 4) != hipSuccess ||
+        hipMalloc((void **)&c->mlp_w16, np * 2) != hipSuccess) {
+        bfsc_destroy(c);
+        return BFSC_E_HIP;
+    }
+    if (hipMemset(c->err, 0, 256) != hipSuccess || hipMemset(c->mlp_params, 0, np * 4) != hipSuccess ||
+        hipMemset(c->adam_m, 0, np * 4) != hipSuccess || hipMemset(c->adam_v, 0, np * 4) != hipSuccess ||
+        hipMemset(c->mlp_w16, 0, np * 2) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        bfsc_destroy(c);
+        return BFSC_E_HIP;
+    }
+    c->tune.enc_waves = 4;
+    c->tune.enc_wg_per_cu = 8;
+    c->tune.dec_waves = 4;
+    c->tune.dec_wg_per_cu = 8;
+    *out = c;
+    return BFSC_OK;
+}
+
+int bfsc_destroy(bfsc_ctx *ctx) {
+    if (!ctx) return BFSC_E_INVAL;
+    hipSetDevice(ctx->device);
+    hipFree(ctx->err);
+    hipFree(ctx->mlp_params);
+    hipFree(ctx->adam_m);
+    hipFree(ctx->adam_v);
+    hipFree(ctx->mlp_grad);
+    hipFree(ctx->mlp_w16);
+    delete ctx;
+    return BFSC_OK;
+}
+
+int bfsc_workspace_size(const bfsc_ctx *ctx, int op, uint64_t max_ids, uint32_t nseg, size_t *bytes) {
+    if (!ctx || !bytes) return BFSC_E_INVAL;
+    switch (op) {
+        case BFSC_OP_SELECT:
+        case BFSC_OP_ENCODE:
+        case BFSC_OP_FEATURES:
+            *bytes = plan_layout(nullptr, max_ids, nseg, nullptr);
+            return BFSC_OK;
+        case BFSC_OP_DECODE:
+            *bytes = decode_ws_bytes(max_ids, nseg);
+            return BFSC_OK;
+        case BFSC_OP_MLP:
+            *bytes = mlp_ws_bytes((uint32_t)(max_ids ? max_ids : 1));
+            return BFSC_OK;
+        default:
+            return BFSC_E_INVAL;
+    }
+}
+
+int bfsc_bfs_workspace_size(const bfsc_csr *g, size_t *bytes) {
+    if (!g || !bytes || g->n_vertices == 0) return BFSC_E_INVAL;
+    *bytes = bfs_ws_bytes_arcs(g->n_vertices, g->n_arcs);
+    return BFSC_OK;
+}
+
+int bfsc_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *level, int32_t *parent,
+                  uint32_t *frontier, uint32_t *frontier_len_dev, void *ws, void *stream) {
+    if (!ctx || !g || !level || !parent || !frontier || !frontier_len_dev || !ws) return BFSC_E_INVAL;
+    if (g->n_vertices == 0 || root >= g->n_vertices || g->n_vertices > 0x7FFFFFFFu) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_bfs_init(ctx, g, root, level, parent, frontier, frontier_len_dev, ws, S(stream));
+}
+
+int bfsc_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *frontier,
+                   const uint32_t *frontier_len_dev, int32_t *level, int32_t *parent, uint32_t *next,
+                   uint32_t *next_len_dev, void *ws, void *stream) {
+    if (!ctx || !g || !g->row_ptr || !g->col_idx || !frontier || !frontier_len_dev || !level ||
+        !parent || !next || !next_len_dev || !ws || cur_level < 0)
+        return BFSC_E_INVAL;
+    if (g->n_vertices == 0 || g->n_vertices > 0x7FFFFFFFu) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_bfs_level(ctx, g, cur_level, frontier, frontier_len_dev, level, parent, next,
+                            next_len_dev, ws, S(stream));
+}
+
+int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds, uint32_t nseg,
+                   uint64_t *seg_off, void *stream) {
+    if (!ids || !n_dev || !bounds || !seg_off || nseg == 0) return BFSC_E_INVAL;
+    return launch_partition(ids, n_dev, bounds, nseg, seg_off, S(stream));
+}
+
+int bfsc_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes,
+                uint64_t *fallbacks_dev, void *ws, void *stream) {
+    if (!ctx || !batch_ok(b) || !classes || !ws) return BFSC_E_INVAL;
+    if (mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    Plan p;
+    plan_layout(ws, b->max_ids, b->nseg, &p);
+    int st = launch_plan_prep(b, p, ctx->err, false, S(stream));
+    if (st) return st;
+    return launch_select(ctx, b, mode, classes, fallbacks_dev, nullptr, p, S(stream));
+}
+
+int bfsc_features(bfsc_ctx *ctx, const bfsc_batch *b, uint16_t *feat, void *ws, void *stream) {
+    if (!ctx || !batch_ok(b) || !feat || !ws) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    Plan p;
+    plan_layout(ws, b->max_ids, b->nseg, &p);
+    int st = launch_plan_prep(b, p, ctx->err, false, S(stream));
+    if (st) return st;
+    return launch_select(ctx, b, BFSC_SEL_EXHAUSTIVE, nullptr, nullptr, feat, p, S(stream));
+}
+
+int bfsc_encode_bound(uint64_t n_ids, uint32_t nseg, size_t *bytes) {
+    if (!bytes) return BFSC_E_INVAL;
+    const uint64_t nb = (n_ids + kBlock - 1) / kBlock + nseg;
+    const uint64_t ng = (n_ids + kBlock * kGroup - 1) / (kBlock * kGroup) + nseg;
+    *bytes = (size_t)(16ull * nseg + nb * (8ull + 4ull * kBlock) + 4ull * ng);
+    return BFSC_OK;
+}
+
+int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int mode, uint8_t *out,
+                size_t out_cap, uint64_t *seg_byte_off, void *ws, void *stream) {
+    if (!ctx || !batch_ok(b) || !out || !seg_byte_off || !ws) return BFSC_E_INVAL;
+    if (((uintptr_t)out & 3) || mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    Plan p;
+    plan_layout(ws, b->max_ids, b->nseg, &p);
+    int st = launch_plan_prep(b, p, ctx->err, true, S(stream));
+    if (st) return st;
+    if (mode == BFSC_SEL_LEARNED && !classes) return BFSC_E_INVAL;  // select first, then encode
+    return launch_encode(ctx, b, classes, mode, out, out_cap, seg_byte_off, p, S(stream));
+}
+
+int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off, void *ws,
+                void *stream) {
+    if (!ctx || !in || !seg_byte_off || !out_ids || !out_off || !ws || nseg == 0) return BFSC_E_INVAL;
+    if ((uintptr_t)in & 3) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_decode(ctx, in, seg_byte_off, nseg, max_ids, out_ids, out_cap, out_off, ws, S(stream));
+}
+
+int bfsc_mlp_param_count(void) { return kNParams; }
+
+int bfsc_mlp_set_weights(bfsc_ctx *ctx, const float *host_params) {
+    if (!ctx || !host_params) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    HIP_OK(hipMemcpy(ctx->mlp_params, host_params, kNParams * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemset(ctx->adam_m, 0, kNParams * 4));
+    HIP_OK(hipMemset(ctx->adam_v, 0, kNParams * 4));
+    ctx->adam_t = 0;
+    if (launch_round16(ctx, nullptr)) return BFSC_E_HIP;
+    HIP_OK(hipDeviceSynchronize());
+    return BFSC_OK;
+}
+
+int bfsc_mlp_get_weights(bfsc_ctx *ctx, float *host_params) {
+    if (!ctx || !host_params) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(host_params, ctx->mlp_params, kNParams * 4, hipMemcpyDeviceToHost));
+    return BFSC_OK;
+}
+
+int bfsc_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, void *ws,
+                     void *stream) {
+    (void)ws;
+    if (!ctx || (!X && n) || (!logits && n)) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_mlp_forward(ctx, X, n, logits, S(stream));
+}
+
+int bfsc_mlp_grad(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n, float *grads,
+                  float *loss_dev, void *ws, void *stream) {
+    if (!ctx || !X || !y || !grads || !ws || n == 0) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_mlp_grad(ctx, X, y, n, grads, loss_dev, ws, S(stream));
+}
+
+int bfsc_mlp_train_step(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n,
+                        const bfsc_adam *opt, float *loss_dev, void *ws, void *stream) {
+    if (!ctx || !X || !y || !opt || !ws || n == 0) return BFSC_E_INVAL;
+    if (!(opt->lr > 0.0f) || !(opt->beta1 >= 0.0f && opt->beta1 < 1.0f) ||
+        !(opt->beta2 >= 0.0f && opt->beta2 < 1.0f) || !(opt->eps > 0.0f))
+        return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    int st = launch_mlp_grad(ctx, X, y, n, ctx->mlp_grad, loss_dev, ws, S(stream));
+    if (st) return st;
+    return launch_adam(ctx, ctx->mlp_grad, opt, S(stream));
+}
+
+int bfsc_get_tune(const bfsc_ctx *ctx, bfsc_tune *out) {
+    if (!ctx || !out) return BFSC_E_INVAL;
+    *out = ctx->tune;
+    return BFSC_OK;
+}
+
+static bool waves_ok(uint32_t w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
+
+int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t) {
+    if (!ctx || !t) return BFSC_E_INVAL;
+    if (!waves_ok(t->enc_waves) || !waves_ok(t->dec_waves) || t->enc_wg_per_cu < 1 ||
+        t->enc_wg_per_cu > 64 || t->dec_wg_per_cu < 1 || t->dec_wg_per_cu > 64)
+        return BFSC_E_INVAL;
+    ctx->tune = *t;
+    return BFSC_OK;
+}
+
+int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *stream) {
+    (void)ctx; (void)sample; (void)ws; (void)stream;
+    return BFSC_E_UNIMPLEMENTED;
+}
+
+int bfsc_sync_status(bfsc_ctx *ctx, void *stream) {
+    if (!ctx) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    HIP_OK(hipStreamSynchronize(S(stream)));
+    uint32_t e = 0;
+    HIP_OK(hipMemcpy(&e, ctx->err, 4, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemset(ctx->err, 0, 4));
+    HIP_OK(hipDeviceSynchronize());
+    if (e & kErrCorrupt) return BFSC_E_CORRUPT;
+    if (e & kErrCapacity) return BFSC_E_CAPACITY;
+    if (e & kErrInval) return BFSC_E_INVAL;
+    return BFSC_OK;
+}
+
+const char *bfsc_status_string(int status) {
+    switch (status) {
+        case BFSC_OK: return "ok";
+        case BFSC_E_INVAL: return "invalid argument or input";
+        case BFSC_E_CAPACITY: return "output capacity exceeded";
+        case BFSC_E_CORRUPT: return "corrupt compressed stream";
+        case BFSC_E_HIP: return "HIP runtime error";
+        case BFSC_E_UNIMPLEMENTED: return "not implemented";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

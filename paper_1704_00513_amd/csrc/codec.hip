@@ -1,0 +1,1037 @@
+// Frontier codec kernels for gfx950: batch planning, per-block codec choice,
+// single-pass encode (decoupled look-back for output offsets) and validating
+// decode.  The block formats follow the compression techniques of Romera,
+// arXiv 1704.00513 (delta coding + binary packing in blocks of 128, eqs.
+// (6)-(7); patched coding with exceptions, eqs. (8)-(9); bitmap indexes for
+// dense sets), in this project's own byte layout (described in bfsc.h).
+//
+// Work decomposition: a tile is one group of <= 16 blocks of one segment.
+// One wave handles one 128-ID block at a time, two IDs per lane (lane l holds
+// IDs l and 64+l, so loads and stores are fully coalesced).
+#include "common.hpp"
+
+namespace bfsc {
+
+// ------------------------------------------------------------------ scans
+
+// Exclusive prefix sum over a 1024-thread workgroup (16 waves).
+__device__ uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tmp /*[17]*/, uint32_t *total) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) s_tmp[w] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t i = 0; i < nw; ++i) {
+            uint32_t x = s_tmp[i];
+            s_tmp[i] = acc;
+            acc += x;
+        }
+        s_tmp[16] = acc;
+    }
+    __syncthreads();
+    uint32_t r = s_tmp[w] + incl - v;
+    *total = s_tmp[16];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ plan
+
+struct PlanArgs {
+    const uint64_t *seg_off;
+    const uint32_t *seg_lo;
+    const uint32_t *seg_hi;
+    uint32_t nseg;
+    uint64_t max_ids;
+    Plan p;
+    uint32_t *seg_n;
+    uint32_t *err;
+    int zero_status;
+};
+
+// All workgroups clear the look-back state; workgroup 0 computes the
+// per-segment block / group / tile bases.
+__global__ __launch_bounds__(1024) void k_plan_prep(PlanArgs a) {
+    const uint32_t tid = threadIdx.x;
+    if (a.zero_status) {
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + tid; i < a.p.max_tiles; i += stride)
+            a.p.status[i] = 0;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + tid; i < a.nseg; i += stride)
+            a.p.seg_pw[i] = 0;
+    }
+    if (blockIdx.x != 0) return;
+    __shared__ uint32_t s_tmp[17];
+    uint32_t cb = 0, cg = 0, ct = 0;
+    for (uint32_t base = 0; base < a.nseg; base += blockDim.x) {
+        uint32_t r = base + tid;
+        uint32_t nb = 0, ng = 0, nt = 0;
+        if (r < a.nseg) {
+            uint64_t s = a.seg_off[r], e = a.seg_off[r + 1];
+            uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
+            bool bad = e < s || e > a.max_ids || lo > hi || (e - s) > (uint64_t)(hi - lo);
+            uint32_t n = bad ? 0u : (uint32_t)(e - s);
+            if (bad) raise_err(a.err, kErrInval);
+            a.seg_n[r] = n;
+            nb = cdiv32(n, kBlock);
+            ng = cdiv32(nb, kGroup);
+            nt = ng ? ng : 1u;
+        }
+        uint32_t tb, tg, tt;
+        uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
+        uint32_t xg = wg_excl_scan(ng, s_tmp, &tg);
+        uint32_t xt = wg_excl_scan(nt, s_tmp, &tt);
+        if (r < a.nseg) {
+            a.p.blk_base[r] = cb + xb;
+            a.p.grp_base[r] = cg + xg;
+            a.p.tile_base[r] = ct + xt;
+        }
+        cb += tb;
+        cg += tg;
+        ct += tt;
+    }
+    if (tid == 0) {
+        // inconsistent offsets (totals beyond what max_ids allows) disable
+        // the batch: no tile runs, so nothing is indexed past the workspace
+        const uint64_t max_blocks = (a.max_ids + kBlock - 1) / kBlock + a.nseg;
+        const bool over = ct > a.p.max_tiles || cb > max_blocks;
+        if (over) raise_err(a.err, kErrInval);
+        a.p.blk_base[a.nseg] = cb;
+        a.p.grp_base[a.nseg] = cg;
+        a.p.tile_base[a.nseg] = over ? 0u : ct;
+        a.p.counter[0] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ block analysis
+
+struct BlockInfo {
+    uint32_t cls, param, aux, words, first;
+};
+
+// Deltas and statistics of one block, held by one wave.  Lane l holds value
+// index l (a) and 64+l (b).  Delta index j of value j is v_j - v_{j-1}.
+struct BlockRegs {
+    uint32_t da, db;   // deltas (0 where there is none)
+    uint32_t oa, ob;   // value - v0
+    bool hasa, hasb;   // lane carries delta j = lane / 64+lane
+};
+
+struct BlockStats {
+    uint32_t nk, m, v0, span, dmin, dmax, wmin;
+};
+
+__device__ __forceinline__ void load_block(const uint32_t *ids, uint32_t nk, uint32_t lo,
+                                           uint32_t hi, uint32_t lane, BlockRegs &R,
+                                           BlockStats &S, uint32_t *err) {
+    const bool ina = lane < nk, inb = lane + 64 < nk;
+    const uint32_t va = ina ? ids[lane] : 0u;
+    const uint32_t vb = inb ? ids[64 + lane] : 0u;
+    const uint32_t pa = shfl_up(va, 1);
+    uint32_t pb = shfl_up(vb, 1);
+    const uint32_t a63 = readlane(va, 63);
+    if (lane == 0) pb = a63;
+    R.hasa = ina && lane >= 1;
+    R.hasb = inb;
+    R.da = R.hasa ? va - pa : 0u;
+    R.db = R.hasb ? vb - pb : 0u;
+    const bool bad = (R.hasa && va <= pa) || (R.hasb && vb <= pb) ||
+                     (ina && (va < lo || va >= hi)) || (inb && (vb < lo || vb >= hi));
+    if (ballot(bad) != 0ull && lane == 0) raise_err(err, kErrInval);
+    S.nk = nk;
+    S.m = nk - 1;
+    S.v0 = readlane(va, 0);
+    const uint32_t vlast = nk <= 64 ? readlane(va, nk - 1) : readlane(vb, nk - 65);
+    S.span = vlast - S.v0;
+    S.dmax = wave_max(max(R.da, R.db));
+    uint32_t mn = 0xFFFFFFFFu;
+    if (R.hasa) mn = R.da;
+    if (R.hasb) mn = min(mn, R.db);
+    S.dmin = S.m ? wave_min(mn) : 0u;
+    S.wmin = bitlen32(S.dmax);
+    R.oa = va - S.v0;
+    R.ob = vb - S.v0;
+}
+
+// Best PFOR exception width: fewest payload words with 10 E <= m; ties go
+// to the larger b.  b = wmin (no exceptions) is always allowed.
+__device__ __forceinline__ void pfor_best(const BlockRegs &R, const BlockStats &S, uint32_t &bb,
+                                          uint32_t &E, uint32_t &words) {
+    bb = S.wmin;
+    E = 0;
+    words = cdiv32(S.m * S.wmin, 32);
+    for (int b = (int)S.wmin - 1; b >= 0; --b) {
+        const uint32_t e = popc64(ballot(R.hasa && (R.da >> b) != 0u)) +
+                           popc64(ballot(R.hasb && (R.db >> b) != 0u));
+        if (10u * e > S.m) break;
+        const uint32_t h = e ? S.wmin - (uint32_t)b : 0u;
+        const uint32_t w = cdiv32(S.m * (uint32_t)b, 32) + cdiv32(e, 4) + cdiv32(e * h, 32);
+        if (w < words) {
+            words = w;
+            bb = (uint32_t)b;
+            E = e;
+        }
+    }
+}
+
+__device__ __forceinline__ bool class_valid(const BlockStats &S, uint32_t c) {
+    if (c == kClsBitmap) return S.span <= kBitmapMaxSpan;
+    if (c >= 1 && c <= 33) return c - 1 >= S.wmin;
+    return c == kClsPfor;
+}
+
+// Exhaustive choice: fewest payload words; ties: bit-pack < bitmap < PFOR.
+__device__ __forceinline__ BlockInfo choose(const BlockRegs &R, const BlockStats &S, int mode,
+                                            int given, uint32_t *err) {
+    BlockInfo I;
+    I.first = 0;
+    uint32_t c;
+    if (given >= 0) {
+        c = (uint32_t)given;
+        if (!class_valid(S, c)) {
+            if (threadIdx.x % 64 == 0) raise_err(err, kErrInval);
+            c = 0xFFu;
+        }
+    } else {
+        c = mode == BFSC_SEL_PLAIN_BP ? 1u + S.wmin : 0xFFu;
+    }
+    uint32_t pb = 0, pe = 0, pw = 0;
+    if (c == 0xFFu || c == kClsPfor) pfor_best(R, S, pb, pe, pw);
+    if (c == 0xFFu) {
+        uint32_t best = 1u + S.wmin, bw = cdiv32(S.m * S.wmin, 32);
+        if (S.span <= kBitmapMaxSpan) {
+            const uint32_t w = cdiv32(S.span, 32);
+            if (w < bw) { bw = w; best = kClsBitmap; }
+        }
+        if (pw < bw) best = kClsPfor;
+        c = best;
+    }
+    I.cls = c;
+    if (c == kClsBitmap) {
+        I.param = 0;
+        I.aux = S.span;
+        I.words = cdiv32(S.span, 32);
+    } else if (c <= 33) {
+        I.param = c - 1;
+        I.aux = 0;
+        I.words = cdiv32(S.m * (c - 1), 32);
+    } else {
+        I.param = pb;
+        const uint32_t h = pe ? S.wmin - pb : 0u;
+        I.aux = pe | (h << 8);
+        I.words = pw;
+    }
+    return I;
+}
+
+// ------------------------------------------------------------------ packing
+
+__device__ __forceinline__ void put_bits(uint32_t *buf, uint32_t pos, uint32_t w, uint32_t v) {
+    if (w == 0) return;
+    const uint32_t wi = pos >> 5, sh = pos & 31;
+    atomicOr(&buf[wi], v << sh);
+    if (sh + w > 32) atomicOr(&buf[wi + 1], v >> (32 - sh));
+}
+
+// Builds one block's payload in the wave's LDS buffer (128 words).
+__device__ __forceinline__ void pack_block(uint32_t *buf, const BlockInfo &I, const BlockRegs &R,
+                                           const BlockStats &S, uint32_t lane) {
+    buf[lane] = 0;
+    buf[lane + 64] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t ja = lane, jb = 64 + lane;  // delta indices
+    if (I.cls == kClsBitmap) {
+        if (R.hasa && R.oa >= 1 && R.oa <= S.span) atomicOr(&buf[(R.oa - 1) >> 5], 1u << ((R.oa - 1) & 31));
+        if (R.hasb && R.ob >= 1 && R.ob <= S.span) atomicOr(&buf[(R.ob - 1) >> 5], 1u << ((R.ob - 1) & 31));
+    } else if (I.cls <= 33) {
+        const uint32_t w = I.param;
+        if (R.hasa) put_bits(buf, (ja - 1) * w, w, R.da);
+        if (R.hasb) put_bits(buf, (jb - 1) * w, w, R.db);
+    } else {
+        const uint32_t b = I.param, E = I.aux & 0xFFu, h = I.aux >> 8;
+        const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+        if (R.hasa) put_bits(buf, (ja - 1) * b, b, R.da & mask);
+        if (R.hasb) put_bits(buf, (jb - 1) * b, b, R.db & mask);
+        if (E) {
+            const uint32_t lw = cdiv32(S.m * b, 32), qw = cdiv32(E, 4);
+            const bool xa = R.hasa && b < 32 && (R.da >> b) != 0u;
+            const bool xb = R.hasb && b < 32 && (R.db >> b) != 0u;
+            const uint64_t ma = ballot(xa), mb = ballot(xb);
+            const uint64_t lt = lanemask_lt();
+            if (xa) {
+                const uint32_t e = popc64(ma & lt);
+                put_bits(buf, lw * 32 + e * 8, 8, ja - 1);
+                put_bits(buf, (lw + qw) * 32 + e * h, h, R.da >> b);
+            }
+            if (xb) {
+                const uint32_t e = popc64(ma) + popc64(mb & lt);
+                put_bits(buf, lw * 32 + e * 8, 8, jb - 1);
+                put_bits(buf, (lw + qw) * 32 + e * h, h, R.db >> b);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------------ encode
+
+struct EncArgs {
+    const uint32_t *ids;
+    const uint64_t *seg_off;
+    const uint32_t *seg_lo;
+    const uint32_t *seg_hi;
+    const uint32_t *seg_n;
+    const uint8_t *classes;
+    int mode;
+    uint32_t nseg;
+    uint32_t *out;          // word view of the output
+    uint64_t out_cap;       // bytes
+    uint64_t *seg_byte_off;
+    Plan p;
+    uint32_t *err;
+};
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_encode(EncArgs a) {
+    constexpr int BPW = (int)kGroup / WAVES;  // blocks per wave per tile
+    __shared__ uint32_t s_t, s_r;
+    __shared__ uint64_t s_X, s_P;
+    __shared__ BlockInfo s_info[kGroup];
+    __shared__ uint32_t s_pref[kGroup];
+    __shared__ uint32_t s_buf[WAVES][128];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t total = a.p.tile_base[a.nseg];
+
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t t = atomicAdd(a.p.counter, 1u);
+            s_t = t;
+            s_r = t < total ? upper_bound_m1(a.p.tile_base, a.nseg, t) : 0u;
+        }
+        __syncthreads();
+        const uint32_t t = s_t, r = s_r;
+        if (t >= total) break;
+        const uint32_t g = t - a.p.tile_base[r];
+        const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
+        const uint32_t ng = a.p.grp_base[r + 1] - a.p.grp_base[r];
+        const uint32_t n = a.seg_n[r];
+        const uint32_t k0 = g * kGroup;
+        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
+        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
+        const uint32_t *ids = a.ids + a.seg_off[r];
+
+        // phase A: analyse this wave's blocks
+        BlockRegs R[BPW];
+        BlockStats S[BPW];
+        BlockInfo I[BPW];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const uint32_t kk = w + (uint32_t)i * WAVES;
+            if (kk < nblk) {
+                const uint32_t k = k0 + kk;
+                const uint32_t nk = min(kBlock, n - k * kBlock);
+                load_block(ids + (uint64_t)k * kBlock, nk, lo, hi, lane, R[i], S[i], a.err);
+                const int given = a.classes ? (int)a.classes[a.p.blk_base[r] + k] : -1;
+                I[i] = choose(R[i], S[i], a.mode, given, a.err);
+                I[i].first = S[i].v0 - lo;
+                if (lane == 0) s_info[kk] = I[i];
+            }
+        }
+        __syncthreads();
+
+        // phase B: tile offsets (wave 0)
+        if (w == 0) {
+            const uint32_t wv = lane < nblk ? s_info[lane].words : 0u;
+            const uint32_t incl = wave_incl_scan(wv);
+            if (lane < kGroup) s_pref[lane] = incl - wv;
+            const uint64_t A = (uint64_t)readlane(incl, 63);
+            uint64_t X = 0;
+            if (t == 0) {
+                if (lane == 0) st_rel64(&a.p.status[0], kFlagIncl | A);
+            } else {
+                if (lane == 0) st_rel64(&a.p.status[t], kFlagAgg | A);
+                // windowed look-back over up to 64 predecessors at a time
+                int64_t base = (int64_t)t;
+                for (;;) {
+                    const int64_t idx = base - 1 - (int64_t)lane;
+                    uint64_t st = idx >= 0 ? ld_acq64(&a.p.status[idx]) : kFlagIncl;
+                    const uint64_t flag = st >> 62;
+                    const uint64_t incl_m = ballot(flag == 2);
+                    const uint32_t stop = incl_m ? (uint32_t)__builtin_ctzll(incl_m) : 64u;
+                    const uint64_t upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1ull);
+                    if (ballot(flag == 0) & upto) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    const uint64_t v = (lane <= stop) ? (st & kValMask) : 0ull;
+                    const uint64_t sum = wave_sum64(v);
+                    X += sum;
+                    if (stop < 64) break;
+                    base -= 64;
+                }
+                if (lane == 0) st_rel64(&a.p.status[t], kFlagIncl | (X + A));
+            }
+            uint64_t P;
+            if (g == 0) {
+                P = X;
+                if (lane == 0) st_rel64(&a.p.seg_pw[r], kReady | P);
+            } else {
+                uint64_t v;
+                for (;;) {
+                    v = ld_acq64(&a.p.seg_pw[r]);
+                    if (v & kReady) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                P = v & ~kReady;
+            }
+            if (lane == 0) {
+                s_X = X;
+                s_P = P;
+                // the last tile closes the batch
+                if (t + 1 == total) {
+                    const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
+                    a.seg_byte_off[a.nseg] = Sr + 16ull + 8ull * nb + 4ull * ng + 4ull * (X - P + A);
+                }
+            }
+        }
+        __syncthreads();
+
+        // phase C: write header, directory, group entry and payloads
+        const uint64_t X = s_X, P = s_P;
+        const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
+        const uint64_t sw = Sr >> 2;                        // segment start (words)
+        const uint64_t pwb = sw + 4 + 2ull * nb + ng + (X - P);  // this tile's payload start
+        const uint32_t Atile = nblk ? s_pref[nblk - 1] + s_info[nblk - 1].words : 0u;
+        const uint64_t capw = a.out_cap >> 2;
+        const bool fits = (sw + 4 + 2ull * nb + ng <= capw) && (pwb + Atile <= capw);
+        if (!fits) {
+            if (tid == 0) raise_err(a.err, kErrCapacity);
+        } else {
+            if (g == 0 && tid < 4) {
+                const uint32_t hv = tid == 0 ? n : tid == 1 ? lo : tid == 2 ? hi : kMagic;
+                a.out[sw + tid] = hv;
+                if (tid == 0) a.seg_byte_off[r] = Sr;
+            }
+            if (nblk && tid == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)(X - P);
+            if (tid < 2 * nblk) {
+                const BlockInfo &bi = s_info[tid >> 1];
+                const uint32_t v = (tid & 1) ? (bi.cls | (bi.param << 8) | (bi.aux << 16)) : bi.first;
+                a.out[sw + 4 + 2ull * (k0 + (tid >> 1)) + (tid & 1)] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < BPW; ++i) {
+                const uint32_t kk = w + (uint32_t)i * WAVES;
+                if (kk < nblk && I[i].words) {
+                    pack_block(s_buf[w], I[i], R[i], S[i], lane);
+                    uint32_t *dst = a.out + pwb + s_pref[kk];
+                    for (uint32_t q = lane; q < I[i].words; q += 64) dst[q] = s_buf[w][q];
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ select / features
+
+struct SelArgs {
+    const uint32_t *ids;
+    const uint64_t *seg_off;
+    const uint32_t *seg_lo;
+    const uint32_t *seg_hi;
+    const int32_t *seg_level;
+    const uint32_t *seg_n;
+    uint32_t nseg;
+    int mode;
+    uint8_t *classes;
+    uint16_t *feat;           // features out (may be NULL)
+    uint64_t *fallbacks;
+    const _Float16 *w16;      // fp16 weights (learned mode)
+    const float *params;      // fp32 master (biases)
+    Plan p;
+    uint32_t *err;
+};
+
+__device__ __forceinline__ uint16_t f16bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+// Eight selector features of a block (identical arithmetic to the spec in bfsc.h).
+__device__ __forceinline__ void block_features(const BlockStats &S, uint32_t seg_n, int32_t level,
+                                               float f[8]) {
+    const int32_t L = level < 0 ? 0 : (level > 63 ? 63 : level);
+    f[0] = (float)S.nk / 128.0f;
+    f[1] = S.m ? (float)bitlen32(S.dmin) / 32.0f : 0.0f;
+    f[2] = S.m ? (float)S.wmin / 32.0f : 0.0f;
+    f[3] = S.m ? (float)bitlen32(S.span / S.m) / 32.0f : 0.0f;
+    f[4] = (float)bitlen32(S.span) / 32.0f;
+    f[5] = __fdiv_rn((float)S.nk, (float)((uint64_t)S.span + 1ull));
+    f[6] = (float)L / 64.0f;
+    f[7] = (float)bitlen32(seg_n) / 32.0f;
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
+    constexpr int BPW = (int)kGroup / WAVES;
+    // learned-mode scratch: features and hidden activations of the tile
+    __shared__ float s_x[kGroup][kIn];
+    __shared__ float s_h1[kGroup][kH];
+    __shared__ float s_h2[kGroup][kH];
+    __shared__ float s_z[kGroup][kOut + 1];
+    __shared__ uint32_t s_wmin[kGroup], s_span[kGroup];
+    __shared__ uint32_t s_ex[kGroup];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t total = a.p.tile_base[a.nseg];
+    const bool learned = a.mode == BFSC_SEL_LEARNED;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
+        const uint32_t g = t - a.p.tile_base[r];
+        const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
+        const uint32_t n = a.seg_n[r];
+        const uint32_t k0 = g * kGroup;
+        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
+        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
+        const uint32_t *ids = a.ids + a.seg_off[r];
+        const int32_t level = a.seg_level ? a.seg_level[r] : 0;
+        const uint32_t gb = a.p.blk_base[r] + k0;
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const uint32_t kk = w + (uint32_t)i * WAVES;
+            if (kk < nblk) {
+                const uint32_t k = k0 + kk;
+                const uint32_t nk = min(kBlock, n - k * kBlock);
+                BlockRegs R;
+                BlockStats S;
+                load_block(ids + (uint64_t)k * kBlock, nk, lo, hi, lane, R, S, a.err);
+                if (a.feat || learned) {
+                    float f[8];
+                    block_features(S, n, level, f);
+                    if (lane < 8) {
+                        float fv = f[0];
+#pragma unroll
+                        for (int q = 1; q < 8; ++q) fv = lane == (uint32_t)q ? f[q] : fv;
+                        const uint16_t hb = f16bits(fv);
+                        if (a.feat) a.feat[(uint64_t)(gb + kk) * 8 + lane] = hb;
+                        s_x[kk][lane] = (float)__builtin_bit_cast(_Float16, hb);
+                    }
+                }
+                if (learned) {
+                    // exhaustive class kept for the fallback
+                    const BlockInfo ex = choose(R, S, BFSC_SEL_EXHAUSTIVE, -1, a.err);
+                    if (lane == 0) {
+                        s_wmin[kk] = S.wmin;
+                        s_span[kk] = S.span;
+                        s_ex[kk] = ex.cls;
+                    }
+                } else if (a.classes) {
+                    const BlockInfo I = choose(R, S, a.mode, -1, a.err);
+                    if (lane == 0) a.classes[gb + kk] = (uint8_t)I.cls;
+                }
+            }
+        }
+        if (!learned) continue;
+        __syncthreads();
+        // MLP on the tile's blocks (fp16 weights, fp32 accumulation)
+        const uint32_t nthr = WAVES * 64;
+        for (uint32_t o = tid; o < kGroup * kH; o += nthr) {
+            const uint32_t bi = o / kH, u = o % kH;
+            if (bi < nblk) {
+                float z = a.params[kB1 + u];
+                float acc = 0.0f;
+#pragma unroll
+                for (int i = 0; i < kIn; ++i) acc += (float)a.w16[kW1 + u * kIn + i] * s_x[bi][i];
+                z = acc + z;
+                s_h1[bi][u] = (float)(_Float16)fmaxf(z, 0.0f);
+            }
+        }
+        __syncthreads();
+        for (uint32_t o = tid; o < kGroup * kH; o += nthr) {
+            const uint32_t bi = o / kH, u = o % kH;
+            if (bi < nblk) {
+                float acc = 0.0f;
+                for (int i = 0; i < kH; ++i) acc += (float)a.w16[kW2 + u * kH + i] * s_h1[bi][i];
+                const float z = acc + a.params[kB2 + u];
+                s_h2[bi][u] = (float)(_Float16)fmaxf(z, 0.0f);
+            }
+        }
+        __syncthreads();
+        for (uint32_t o = tid; o < kGroup * kOut; o += nthr) {
+            const uint32_t bi = o / kOut, c = o % kOut;
+            if (bi < nblk) {
+                float acc = 0.0f;
+                for (int i = 0; i < kH; ++i) acc += (float)a.w16[kW3 + c * kH + i] * s_h2[bi][i];
+                s_z[bi][c] = acc + a.params[kB3 + c];
+            }
+        }
+        __syncthreads();
+        if (tid < nblk) {
+            const uint32_t bi = tid;
+            uint32_t best = 0;
+            float bz = s_z[bi][0];
+            bool nan = bz != bz;
+            for (uint32_t c = 1; c < (uint32_t)kOut; ++c) {
+                const float z = s_z[bi][c];
+                nan |= z != z;
+                if (z > bz) { bz = z; best = c; }
+            }
+            uint32_t res;
+            const uint32_t wmin = s_wmin[bi], span = s_span[bi];
+            bool fb = false;
+            if (nan) { fb = true; res = s_ex[bi]; }
+            else if (best == kClsBitmap) {
+                if (span <= kBitmapMaxSpan) res = kClsBitmap; else { fb = true; res = s_ex[bi]; }
+            } else if (best <= 33) res = 1u + wmin;
+            else res = kClsPfor;
+            if (a.classes) a.classes[gb + bi] = (uint8_t)res;
+            if (fb && a.fallbacks) atomicAdd((unsigned long long *)a.fallbacks, 1ull);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ decode
+
+struct DecPlanArgs {
+    const uint8_t *in;
+    const uint64_t *seg_byte_off;
+    uint32_t nseg;
+    uint64_t out_cap;
+    uint64_t *out_off;
+    uint32_t *seg_n;      // 0 for bad / empty
+    uint32_t *tile_base;  // [nseg+1]
+    uint32_t *err;
+};
+
+__global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
+    __shared__ uint32_t s_tmp[17];
+    __shared__ unsigned long long s_w[16];
+    __shared__ unsigned long long s_c;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t ct = 0;
+    uint64_t co = 0;
+    for (uint32_t base = 0; base < a.nseg; base += blockDim.x) {
+        const uint32_t r = base + tid;
+        uint32_t n = 0, ng = 0;
+        if (r < a.nseg) {
+            const uint64_t s = a.seg_byte_off[r], e = a.seg_byte_off[r + 1];
+            bool bad = e < s || e - s < 16 || (s & 3) || (e & 3);
+            if (!bad) {
+                const uint32_t *h = (const uint32_t *)(a.in + s);
+                const uint32_t hn = h[0], lo = h[1], hi = h[2], mg = h[3];
+                const uint64_t nb = cdiv32(hn, kBlock) + 0ull;
+                const uint64_t meta = 16ull + 8ull * nb + 4ull * ((nb + kGroup - 1) / kGroup);
+                bad = mg != kMagic || lo > hi || hn > hi - lo || meta > e - s;
+                if (!bad) {
+                    n = hn;
+                    ng = (uint32_t)((nb + kGroup - 1) / kGroup);
+                }
+            }
+            if (bad) raise_err(a.err, kErrCorrupt);
+            a.seg_n[r] = n;
+        }
+        uint32_t tt;
+        const uint32_t xt = wg_excl_scan(ng, s_tmp, &tt);
+        // 64-bit exclusive scan of n (two-level: waves then workgroup)
+        uint64_t incl = n;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t l2 = shfl_up((uint32_t)incl, d), h2 = shfl_up((uint32_t)(incl >> 32), d);
+            if (lane >= (uint32_t)d) incl += ((uint64_t)h2 << 32) | l2;
+        }
+        if (lane == 63) s_w[w] = incl;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long acc = 0;
+            for (uint32_t i = 0; i < (blockDim.x >> 6); ++i) {
+                const unsigned long long x = s_w[i];
+                s_w[i] = acc;
+                acc += x;
+            }
+            s_c = acc;
+        }
+        __syncthreads();
+        if (r < a.nseg) {
+            a.tile_base[r] = ct + xt;
+            a.out_off[r] = co + s_w[w] + incl - n;
+        }
+        ct += tt;
+        co += s_c;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.tile_base[a.nseg] = ct;
+        a.out_off[a.nseg] = co;
+        if (co > a.out_cap) raise_err(a.err, kErrCapacity);
+    }
+}
+
+struct DecArgs {
+    const uint8_t *in;
+    const uint64_t *seg_byte_off;
+    uint32_t nseg;
+    const uint32_t *seg_n;
+    const uint32_t *tile_base;
+    const uint64_t *out_off;
+    uint32_t *out;
+    uint64_t out_cap;
+    uint32_t *err;
+};
+
+__device__ __forceinline__ uint32_t get_field(const uint32_t *buf, uint32_t pos, uint32_t w) {
+    if (w == 0) return 0u;
+    const uint32_t wi = pos >> 5, sh = pos & 31;
+    uint32_t v = buf[wi] >> sh;
+    if (sh + w > 32) v |= buf[wi + 1] << (32 - sh);
+    return w >= 32 ? v : (v & ((1u << w) - 1u));
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
+    __shared__ uint32_t s_cls[kGroup], s_param[kGroup], s_aux[kGroup], s_first[kGroup + 1];
+    __shared__ uint32_t s_off[kGroup];
+    __shared__ uint32_t s_ok;
+    __shared__ uint32_t s_buf[WAVES][132];
+    __shared__ uint32_t s_val[WAVES][128];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t total = a.tile_base[a.nseg];
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t r = upper_bound_m1(a.tile_base, a.nseg, t);
+        const uint32_t g = t - a.tile_base[r];
+        const uint32_t n = a.seg_n[r];
+        const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
+        const uint64_t S = a.seg_byte_off[r];
+        const uint64_t bytes = a.seg_byte_off[r + 1] - S;
+        const uint32_t *seg = (const uint32_t *)(a.in + S);
+        const uint32_t lo = seg[1], hi = seg[2];
+        const uint32_t metaw = 4 + 2 * nb + ng;
+        const uint64_t availw = bytes / 4 - metaw;
+        const uint32_t k0 = g * kGroup;
+        const uint32_t nblk = min(kGroup, nb - k0);
+        const uint64_t oo = a.out_off[r];
+        if (w == 0) {
+            bool bad = false;
+            uint32_t words = 0;
+            if (lane <= nblk && k0 + lane < nb) {
+                const uint32_t e0 = seg[4 + 2 * (k0 + lane)], e1 = seg[4 + 2 * (k0 + lane) + 1];
+                s_first[lane] = e0;
+                if (lane < nblk) {
+                    const uint32_t cls = e1 & 0xFFu, param = (e1 >> 8) & 0xFFu, aux = e1 >> 16;
+                    const uint32_t k = k0 + lane;
+                    const uint32_t nk = min(kBlock, n - k * kBlock), m = nk - 1;
+                    if (cls == kClsBitmap) {
+                        bad = param != 0 || aux > kBitmapMaxSpan;
+                        words = cdiv32(aux, 32);
+                    } else if (cls <= 33) {
+                        bad = param != cls - 1 || aux != 0;
+                        words = cdiv32(m * (cls - 1), 32);
+                    } else if (cls == kClsPfor) {
+                        const uint32_t E = aux & 0xFFu, h = aux >> 8;
+                        bad = param > 32 || param + h > 32 || 10 * E > m;
+                        words = bad ? 0u : cdiv32(m * param, 32) + cdiv32(E, 4) + cdiv32(E * h, 32);
+                        bad |= words > kBlock;
+                    } else {
+                        bad = true;
+                    }
+                    s_cls[lane] = cls;
+                    s_param[lane] = param;
+                    s_aux[lane] = aux;
+                    // first value inside [lo, hi)
+                    bad |= (uint64_t)lo + e0 >= (uint64_t)hi;
+                }
+            }
+            const uint32_t incl = wave_incl_scan(lane < nblk ? words : 0u);
+            const uint32_t A = readlane(incl, 63);
+            const uint32_t gt = seg[4 + 2 * nb + g];
+            if (lane < nblk) s_off[lane] = gt + incl - words;
+            bool ok = ballot(bad) == 0ull;
+            ok = ok && (uint64_t)gt + A <= availw;
+            if (g + 1 < ng) ok = ok && seg[4 + 2 * nb + g + 1] == gt + A;
+            else ok = ok && (uint64_t)gt + A == availw;
+            if (lane == 0) {
+                s_ok = ok ? 1u : 0u;
+                if (!ok) raise_err(a.err, kErrCorrupt);
+            }
+        }
+        __syncthreads();
+        if (s_ok) {
+            const uint32_t *pay = seg + metaw;
+            for (uint32_t kk = w; kk < nblk; kk += WAVES) {
+                const uint32_t k = k0 + kk;
+                const uint32_t nk = min(kBlock, n - k * kBlock), m = nk - 1;
+                const uint32_t cls = s_cls[kk], param = s_param[kk], aux = s_aux[kk];
+                const uint32_t v0 = lo + s_first[kk];
+                uint32_t words;
+                if (cls == kClsBitmap) words = cdiv32(aux, 32);
+                else if (cls <= 33) words = cdiv32(m * (cls - 1), 32);
+                else words = cdiv32(m * param, 32) + cdiv32(aux & 0xFFu, 4) + cdiv32((aux & 0xFFu) * (aux >> 8), 32);
+                uint32_t *buf = s_buf[w];
+                uint32_t *val = s_val[w];
+                const uint32_t *src = pay + s_off[kk];
+                buf[lane] = lane < words ? src[lane] : 0u;
+                buf[lane + 64] = lane + 64 < words ? src[lane + 64] : 0u;
+                if (lane < 4) buf[128 + lane] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                bool bad = false;
+                uint32_t xa = 0, xb = 0;  // decoded values
+                const bool ina = lane < nk, inb = lane + 64 < nk;
+                if (cls == kClsBitmap) {
+                    const uint32_t ca = popc64(buf[lane]), cb = popc64(buf[lane + 64]);
+                    const uint32_t ia = wave_incl_scan(ca);
+                    const uint32_t ta = readlane(ia, 63);
+                    const uint32_t ib = wave_incl_scan(cb) + ta;
+                    const uint32_t tot = readlane(ib, 63);
+                    // bits beyond the span must be clear
+                    const uint32_t tailw = aux >> 5, tailb = aux & 31;
+                    const bool tail_bad = (tailb && (lane == tailw) && (buf[lane] >> tailb)) ||
+                                          (tailb && (lane + 64 == tailw) && (buf[lane + 64] >> tailb));
+                    bad |= tail_bad;
+                    const bool cnt_bad = tot != m;
+                    val[lane] = 0u;
+                    val[lane + 64] = 0u;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    if (!cnt_bad) {
+                        if (lane == 0) val[0] = v0;
+                        uint32_t x = buf[lane], j = 1 + ia - ca;
+                        while (x) {
+                            const uint32_t p = __builtin_ctz(x);
+                            x &= x - 1;
+                            if (j < 128) val[j] = v0 + 32 * lane + p + 1;
+                            ++j;
+                        }
+                        x = buf[lane + 64];
+                        j = 1 + ib - cb;
+                        while (x) {
+                            const uint32_t p = __builtin_ctz(x);
+                            x &= x - 1;
+                            if (j < 128) val[j] = v0 + 32 * (lane + 64) + p + 1;
+                            ++j;
+                        }
+                    }
+                    bad |= cnt_bad;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    xa = val[lane];
+                    xb = val[lane + 64];
+                    // highest set position: the last value, checked in 64 bits
+                    const uint32_t ta_ = buf[lane] ? 32 * lane + 32 - __builtin_clz(buf[lane]) : 0u;
+                    const uint32_t tb_ = buf[lane + 64] ? 32 * (lane + 64) + 32 - __builtin_clz(buf[lane + 64]) : 0u;
+                    const uint32_t top = wave_max(max(ta_, tb_));
+                    bad |= (uint64_t)v0 + top >= (uint64_t)hi;
+                } else {
+                    const uint32_t b = cls <= 33 ? cls - 1 : param;
+                    const uint32_t ja = lane, jb = 64 + lane;
+                    uint32_t da = (ina && ja >= 1) ? get_field(buf, (ja - 1) * b, b) : 0u;
+                    uint32_t db = inb ? get_field(buf, (jb - 1) * b, b) : 0u;
+                    if (cls == kClsPfor) {
+                        const uint32_t E = aux & 0xFFu, h = aux >> 8;
+                        const uint32_t lw = cdiv32(m * b, 32), qw = cdiv32(E, 4);
+                        val[lane] = 0u;
+                        val[lane + 64] = 0u;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        uint32_t p = 0;
+                        if (lane < E) {
+                            p = (buf[lw + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu;
+                            const uint32_t hv = get_field(buf + lw + qw, lane * h, h);
+                            if (p < m) val[p + 1] = b >= 32 ? 0u : (hv << b);
+                        }
+                        const uint32_t pp = shfl_up(p, 1);
+                        bad |= lane < E && (p >= m || (lane > 0 && p <= pp));
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        da |= val[lane];
+                        db |= val[lane + 64];
+                    }
+                    bad |= (ina && ja >= 1 && da == 0) || (inb && db == 0);
+                    const uint32_t sa = wave_incl_scan(da);
+                    const uint32_t ta = readlane(sa, 63);
+                    const uint32_t sb = wave_incl_scan(db) + ta;
+                    xa = v0 + sa;
+                    xb = v0 + sb;
+                    // a wrap shows as a decrease against the previous value
+                    const uint32_t pa = shfl_up(xa, 1);
+                    uint32_t pb = shfl_up(xb, 1);
+                    const uint32_t a63 = readlane(xa, 63);
+                    if (lane == 0) pb = a63;
+                    bad |= (ina && lane >= 1 && xa <= pa) || (inb && xb <= pb);
+                }
+                // last value below hi and below the next block's first value
+                const uint32_t last = nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65);
+                const bool has_next = k + 1 < nb;
+                const uint32_t nxt = has_next ? lo + s_first[kk + 1] : 0u;
+                bad |= last >= hi || (has_next && last >= nxt);
+                if (ballot(bad) != 0ull) {
+                    if (lane == 0) raise_err(a.err, kErrCorrupt);
+                } else {
+                    const uint64_t ob = oo + (uint64_t)k * kBlock;
+                    if (ina && ob + lane < a.out_cap) a.out[ob + lane] = xa;
+                    if (inb && ob + 64 + lane < a.out_cap) a.out[ob + 64 + lane] = xb;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ partition
+
+__global__ void k_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds,
+                            uint32_t nseg, uint64_t *seg_off) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > nseg) return;
+    const uint32_t n = *n_dev;
+    if (r == nseg) {
+        seg_off[nseg] = n;
+        return;
+    }
+    const uint32_t key = bounds[r];
+    uint32_t lo = 0, hi = n;  // first index with ids[i] >= key
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (ids[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    seg_off[r] = lo;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline uint32_t persistent_grid(const bfsc_ctx *ctx, uint32_t per_cu, uint64_t max_tiles) {
+    uint64_t g = (uint64_t)ctx->n_cu * per_cu;
+    if (g > max_tiles) g = max_tiles;
+    return (uint32_t)(g ? g : 1);
+}
+
+int launch_plan_prep(const bfsc_batch *b, const Plan &p, uint32_t *err, bool zero_status,
+                     hipStream_t s) {
+    PlanArgs a;
+    a.seg_off = b->seg_off;
+    a.seg_lo = b->seg_lo;
+    a.seg_hi = b->seg_hi;
+    a.nseg = b->nseg;
+    a.max_ids = b->max_ids;
+    a.p = p;
+    a.seg_n = p.seg_n;
+    a.err = err;
+    a.zero_status = zero_status ? 1 : 0;
+    uint32_t grid = 1;
+    if (zero_status) {
+        uint64_t need = ((uint64_t)p.max_tiles + 1023) / 1024;
+        grid = (uint32_t)(need < 64 ? (need ? need : 1) : 64);
+    }
+    hipLaunchKernelGGL(k_plan_prep, dim3(grid), dim3(1024), 0, s, a);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int mode,
+                  uint8_t *out, size_t out_cap, uint64_t *seg_byte_off, const Plan &p,
+                  hipStream_t s) {
+    EncArgs a;
+    a.ids = b->ids;
+    a.seg_off = b->seg_off;
+    a.seg_lo = b->seg_lo;
+    a.seg_hi = b->seg_hi;
+    a.seg_n = p.seg_n;
+    a.classes = classes;
+    a.mode = mode;
+    a.nseg = b->nseg;
+    a.out = (uint32_t *)out;
+    a.out_cap = out_cap;
+    a.seg_byte_off = seg_byte_off;
+    a.p = p;
+    a.err = ctx->err;
+    const uint32_t waves = ctx->tune.enc_waves;
+    const uint32_t grid = persistent_grid(ctx, ctx->tune.enc_wg_per_cu, p.max_tiles);
+    switch (waves) {
+        case 1: hipLaunchKernelGGL(k_encode<1>, dim3(grid), dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_encode<2>, dim3(grid), dim3(128), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_encode<8>, dim3(grid), dim3(512), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_encode<16>, dim3(grid), dim3(1024), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_encode<4>, dim3(grid), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes,
+                  uint64_t *fallbacks, uint16_t *feat, const Plan &p, hipStream_t s) {
+    SelArgs a;
+    a.ids = b->ids;
+    a.seg_off = b->seg_off;
+    a.seg_lo = b->seg_lo;
+    a.seg_hi = b->seg_hi;
+    a.seg_level = b->seg_level;
+    a.seg_n = p.seg_n;
+    a.nseg = b->nseg;
+    a.mode = mode;
+    a.classes = classes;
+    a.feat = feat;
+    a.fallbacks = fallbacks;
+    a.w16 = ctx->mlp_w16;
+    a.params = ctx->mlp_params;
+    a.p = p;
+    a.err = ctx->err;
+    const uint32_t grid = persistent_grid(ctx, 4, p.max_tiles);
+    hipLaunchKernelGGL(k_select<4>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg) {
+    (void)max_ids;
+    return align256(((size_t)nseg + 1) * 4) * 2 + 256;
+}
+
+int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                  uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
+                  void *ws, hipStream_t s) {
+    char *wb = (char *)ws;
+    uint32_t *seg_n = (uint32_t *)wb;
+    uint32_t *tile_base = (uint32_t *)(wb + align256(((size_t)nseg + 1) * 4));
+    DecPlanArgs pa;
+    pa.in = in;
+    pa.seg_byte_off = seg_byte_off;
+    pa.nseg = nseg;
+    pa.out_cap = out_cap;
+    pa.out_off = out_off;
+    pa.seg_n = seg_n;
+    pa.tile_base = tile_base;
+    pa.err = ctx->err;
+    hipLaunchKernelGGL(k_dec_prep, dim3(1), dim3(1024), 0, s, pa);
+    DecArgs a;
+    a.in = in;
+    a.seg_byte_off = seg_byte_off;
+    a.nseg = nseg;
+    a.seg_n = seg_n;
+    a.tile_base = tile_base;
+    a.out_off = out_off;
+    a.out = out_ids;
+    a.out_cap = out_cap;
+    a.err = ctx->err;
+    const uint64_t mt = plan_max_tiles(max_ids, nseg);
+    const uint32_t grid = persistent_grid(ctx, ctx->tune.dec_wg_per_cu, mt);
+    switch (ctx->tune.dec_waves) {
+        case 1: hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_decode<2>, dim3(grid), dim3(128), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_decode<8>, dim3(grid), dim3(512), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_decode<16>, dim3(grid), dim3(1024), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_decode<4>, dim3(grid), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+int launch_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds,
+                     uint32_t nseg, uint64_t *seg_off, hipStream_t s) {
+    const uint32_t threads = 256, grid = (nseg + 1 + threads - 1) / threads;
+    hipLaunchKernelGGL(k_partition, dim3(grid), dim3(threads), 0, s, ids, n_dev, bounds, nseg,
+                       seg_off);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+}  // namespace bfsc

@@ -1,0 +1,116 @@
+"""GPU parity of the learned selector: logits and gradients of the HIP
+network against the fp64 oracle (tolerances below), Adam's step, and the
+learned class choice resolved and encoded byte-exactly."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from oracle import mlp
+
+from gpu_util import gpu_encode, gpu_select, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+
+# fp32 accumulation of at most 64 fp16 x fp16 products per unit, plus rare
+# one-ulp fp16 flips of a hidden value where fp32 and fp64 round differently:
+# |dz| <= 2^-11 |h| |w| per flip; the bound below covers a few flips.
+LOGIT_RTOL, LOGIT_ATOL = 1e-3, 1e-3
+GRAD_RTOL, GRAD_ATOL = 1e-3, 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1704_00513_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def frontier_features(n_roots=2):
+    g = inputs.graph(inputs.RMAT, 16, 16, 1)
+    bs = []
+    for root in inputs.roots(g, n_roots, 1):
+        level, _, depth = oracle.bfs(g, int(root))
+        for L in range(depth + 1):
+            bs.append(oracle.batch_from_frontier(oracle.frontier(level, L),
+                                                 inputs.bounds_equal(g.n_vertices, 16), L))
+    b = oracle.concat_batches(bs)
+    return b, oracle.features(b), oracle.select(b)
+
+
+def test_forward_logits(ctx):
+    t = torch()
+    b, F, y = frontier_features()
+    theta = inputs.mlp_init(3)
+    theta[::5] += 0.05
+    ctx.mlp_set_weights(theta)
+    n = F.shape[0]
+    logits = t.zeros((n, 35), dtype=t.float32, device="cuda")
+    ctx.mlp_forward(to_dev(F, np.uint16, np.int16), n, logits)
+    assert ctx.sync_status() == 0
+    got = logits.cpu().numpy()
+    want, _ = mlp.forward(theta.astype(np.float64), mlp.features_to_f64(F))
+    np.testing.assert_allclose(got, want, rtol=LOGIT_RTOL, atol=LOGIT_ATOL)
+
+
+def test_gradient_matches_oracle(ctx):
+    t = torch()
+    b, F, y = frontier_features()
+    theta = inputs.mlp_init(4)
+    ctx.mlp_set_weights(theta)
+    n = F.shape[0]
+    grads = t.zeros(7011, dtype=t.float32, device="cuda")
+    loss = t.zeros(1, dtype=t.float32, device="cuda")
+    ctx.mlp_grad(to_dev(F, np.uint16, np.int16), to_dev(y, np.uint8, np.uint8), n, grads, loss)
+    assert ctx.sync_status() == 0
+    l_ref, g_ref = mlp.loss_and_grad(theta.astype(np.float64), mlp.features_to_f64(F), y)
+    assert abs(float(loss.item()) - l_ref) <= 1e-4 * abs(l_ref)
+    np.testing.assert_allclose(grads.cpu().numpy(), g_ref, rtol=GRAD_RTOL,
+                               atol=GRAD_ATOL * max(1.0, np.abs(g_ref).max()))
+
+
+def test_adam_steps_match_oracle(ctx):
+    b, F, y = frontier_features()
+    theta = inputs.mlp_init(5)
+    ctx.mlp_set_weights(theta)
+    n = F.shape[0]
+    X = to_dev(F, np.uint16, np.int16)
+    Y = to_dev(y, np.uint8, np.uint8)
+    ref = theta.astype(np.float64)
+    opt = mlp.Adam(ref.size)
+    Xf = mlp.features_to_f64(F)
+    for step in range(3):
+        ctx.mlp_train_step(X, Y, n)
+        _, g = mlp.loss_and_grad(ref, Xf, y)
+        ref = opt.step(ref, g)
+    assert ctx.sync_status() == 0
+    got = ctx.mlp_get_weights()
+    # each Adam step moves a weight by at most ~lr; sign flips of tiny
+    # gradients can move single weights differently
+    diff = np.abs(got - ref)
+    assert np.median(diff) < 1e-6
+    assert np.mean(diff < 1e-4) > 0.99
+
+
+def test_learned_select_resolves_and_encodes_exactly(ctx):
+    b, F, y = frontier_features()
+    theta = inputs.mlp_init(6)
+    ctx.mlp_set_weights(theta)
+    st, got, fb = gpu_select(ctx, b, 2)
+    assert st == 0
+    # oracle's own prediction, resolved
+    z, _ = mlp.forward(theta.astype(np.float64), mlp.features_to_f64(F))
+    pred = mlp.predict(theta.astype(np.float64), mlp.features_to_f64(F))
+    res, fb_ref = oracle.resolve(b, pred)
+    top2 = np.sort(z, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 2 * (LOGIT_ATOL + LOGIT_RTOL * np.abs(top2[:, 1]))
+    assert clear.mean() > 0.5
+    np.testing.assert_array_equal(got[clear], res[clear])
+    # whatever the network picked, the resolved vector is valid and the stream
+    # is the oracle's encoding of that vector
+    want, want_off = oracle.encode(b, classes=got)
+    st, stream, off = gpu_encode(ctx, b, classes=got)
+    assert st == 0
+    np.testing.assert_array_equal(stream, want)
+    np.testing.assert_array_equal(off, want_off)
