@@ -1,0 +1,305 @@
+"""Frontier-codec benchmark on one MI355X.
+
+Workload (default): R-MAT scale 22, edge factor 16, (a, b, c, d) = (0.57,
+0.19, 0.19, 0.05), seed 1; top-down BFS on the GPU from 8 seeded roots; every
+level's frontier split by vertex-ID range into 16 equal segments; the batch of
+all segments of all levels of all roots is resident in HBM.  One step = one
+exhaustive-choice encode of the whole batch followed by its decode.
+
+value = raw frontier bytes (4 B per ID) / (encode + decode time), GB/s.
+The JSON line also carries the roofline of the dominant kernel (algorithmic
+bytes per launch / its HIP-event-timed duration, against 8 TB/s) and the CPU
+oracle timed on a bounded sample on this host.
+
+    python bench.py [--steps 20] [--warmup 3] [--scale 22] [--roots 8] [--nseg 16]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("codec.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1704_00513_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_source_sha()
+    for line in open(path):
+        if line.startswith("#") or "=" not in line:
+            continue
+        kv = dict(x.split("=", 1) for x in line.split())
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("sha") == sha:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def build_batch(ctx, P, torch, g, roots, nseg, bounds_kind, seed):
+    """GPU BFS from each root; every level's frontier goes into one device
+    buffer and is partitioned on the GPU into nseg vertex ranges."""
+    import inputs
+    V = g.n_vertices
+    dg = P.DeviceGraph.from_host(g)
+    cap = V * (len(roots) + 1)
+    all_ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+    level = torch.empty(V, dtype=torch.int32, device="cuda")
+    parent = torch.empty(V, dtype=torch.int32, device="cuda")
+    la = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = ctx.bfs_workspace(dg)
+    if bounds_kind == "zipf":
+        bounds_h, _ = inputs.bounds_zipf(V, nseg, seed)
+    else:
+        bounds_h = inputs.bounds_equal(V, nseg)
+    bounds = torch.from_numpy(bounds_h.view(np.int32)).cuda()
+    seg_off_l = torch.zeros(nseg + 1, dtype=torch.int64, device="cuda")
+    offs, los, his, levs = [np.zeros(1, np.uint64)], [], [], []
+    base = 0
+    bfs_ms, bfs_levels, edges = 0.0, 0, 0
+    ctx.timing(True)
+    for root in roots:
+        front = all_ids[base:]
+        ctx.bfs_init(dg, int(root), level, parent, front, la, ws)
+        L = 0
+        while True:
+            n = int(la.item())
+            if n == 0:
+                break
+            ctx.partition(front, la, bounds, seg_off_l)
+            so = seg_off_l.cpu().numpy().view(np.uint64) + np.uint64(base)
+            offs.append(so[1:])
+            los.append(bounds_h[:-1])
+            his.append(bounds_h[1:])
+            levs.append(np.full(nseg, L, np.int32))
+            nxt = all_ids[base + n:]
+            ctx.bfs_level(dg, L, front, la, level, parent, nxt, lb, ws)
+            base += n
+            front = nxt
+            la, lb = lb, la
+            L += 1
+        bfs_levels += L
+        lv = level.cpu().numpy()
+        deg = np.diff(g.row_ptr)
+        edges += int(deg[lv >= 0].sum())
+        ms, cnt = ctx.timing_read(P._lib.OP_BFS)
+        bfs_ms += ms
+    ctx.timing(False)
+    ctx.sync()
+    seg_off = np.concatenate(offs)
+    b = P.DeviceBatch(all_ids[:max(1, base)],
+                      torch.from_numpy(seg_off.view(np.int64)).cuda(),
+                      torch.from_numpy(np.concatenate(los).view(np.int32)).cuda(),
+                      torch.from_numpy(np.concatenate(his).view(np.int32)).cuda(),
+                      torch.from_numpy(np.concatenate(levs)).cuda(), max_ids=base)
+    host = dict(seg_off=seg_off, seg_lo=np.concatenate(los), seg_hi=np.concatenate(his),
+                seg_level=np.concatenate(levs))
+    return b, host, dict(bfs_ms=bfs_ms, bfs_levels=bfs_levels, edges=edges, n_ids=base)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--graph", choices=["rmat", "uniform"], default="rmat")
+    ap.add_argument("--roots", type=int, default=8)
+    ap.add_argument("--nseg", type=int, default=16)
+    ap.add_argument("--bounds", choices=["equal", "zipf"], default="equal")
+    ap.add_argument("--mode", choices=["exhaustive", "plain"], default="exhaustive")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import inputs
+    import paper_1704_00513_amd as P
+
+    mode = P.SEL_EXHAUSTIVE if args.mode == "exhaustive" else P.SEL_PLAIN_BP
+    kind = inputs.RMAT if args.graph == "rmat" else inputs.UNIFORM
+    t0 = time.time()
+    g = inputs.graph(kind, args.scale, 16, args.seed)
+    log("graph %s scale %d: V=%d arcs=%d (%.1fs)" % (args.graph, args.scale, g.n_vertices, g.n_arcs,
+                                                    time.time() - t0))
+    roots = inputs.roots(g, args.roots, args.seed)
+    ctx = P.Context(0)
+    b, host, bfs = build_batch(ctx, P, torch, g, roots, args.nseg, args.bounds, args.seed)
+    N = bfs["n_ids"]
+    log("batch: %d IDs in %d segments, %d levels; BFS %.2f ms total" % (N, b.nseg, bfs["bfs_levels"],
+                                                                       bfs["bfs_ms"]))
+
+    cap = P.Context.encode_bound(N, b.nseg)
+    out = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    sbo = torch.zeros(b.nseg + 1, dtype=torch.int64, device="cuda")
+    dec = torch.empty(max(1, N), dtype=torch.int32, device="cuda")
+    doff = torch.zeros(b.nseg + 1, dtype=torch.int64, device="cuda")
+    ws_e = ctx.workspace(P.OP_ENCODE, b.max_ids, b.nseg)
+    ws_d = ctx.workspace(P.OP_DECODE, b.max_ids, b.nseg)
+
+    def step():
+        ctx.encode(b, out, sbo, mode=mode, ws=ws_e)
+        ctx.decode(out, sbo, b.nseg, N, dec, doff, ws=ws_d)
+
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    # parity at full size: round trip exact, sampled segments byte-equal to the oracle
+    assert torch.equal(dec[:N], b.ids[:N]), "round trip differs"
+    sbo_h = sbo.cpu().numpy().view(np.uint64)
+    comp = int(sbo_h[-1])
+    check_segments(out, sbo_h, b, host, mode)
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms_step = wall * 1e3 / args.steps
+    st = ctx.sync_status()
+    assert st == 0, "kernel status %d" % st
+    value = 4.0 * N / (ms_step * 1e-3) / 1e9
+
+    # per-kernel durations from event pairs around the main kernels
+    ctx.timing(True)
+    for _ in range(args.steps):
+        step()
+    ctx.sync()
+    enc_ms, enc_n = ctx.timing_read(P.OP_ENCODE)
+    dec_ms, dec_n = ctx.timing_read(P.OP_DECODE)
+    ctx.timing(False)
+    enc_avg, dec_avg = enc_ms / enc_n, dec_ms / dec_n
+    alg_bytes = 4.0 * N + comp  # per launch, for encode and for decode alike
+    dom = ("k_encode", enc_avg) if enc_avg >= dec_avg else ("k_decode", dec_avg)
+    achieved = alg_bytes / (dom[1] * 1e-3) / 1e9
+    workload = "rmat-s%d" % args.scale if args.graph == "rmat" else "uniform-s%d" % args.scale
+    workload += "-%droots-%s%d-%s" % (args.roots, args.bounds, args.nseg, args.mode)
+    traffic = read_traffic(dom[0], workload)
+
+    res = {
+        "metric": "frontier codec GB/s (enc+dec, raw bytes)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded R-MAT / uniform graphs, GPU BFS frontiers)",
+        "config": {"workload": workload, "scale": args.scale, "edgefactor": 16, "roots": args.roots,
+                   "segments_per_level": args.nseg, "bounds": args.bounds, "selector": args.mode,
+                   "n_ids": N, "segments": b.nseg, "levels": bfs["bfs_levels"]},
+        "ratio": round(4.0 * N / comp, 4),
+        "compressed_bytes": comp,
+        "encode_ms": round(enc_avg, 4),
+        "decode_ms": round(dec_avg, 4),
+        "encode_GBps_raw": round(4.0 * N / enc_avg / 1e6, 1),
+        "decode_GBps_raw": round(4.0 * N / dec_avg / 1e6, 1),
+        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": int(alg_bytes)},
+        "enc_dec_alg_frac": round((2 * alg_bytes) / ((enc_avg + dec_avg) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "bfs": {"ms_total": round(bfs["bfs_ms"], 3), "levels": bfs["bfs_levels"],
+                "GTEPS": round(bfs["edges"] / 2 / (bfs["bfs_ms"] * 1e-3) / 1e9, 3)},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(b, host, args.cpu_seconds, mode)
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def check_segments(out, sbo_h, b, host, mode, n_check=24):
+    """Sampled segments of the full-size batch: GPU bytes equal the oracle's
+    encoding of that segment alone (segments are independent)."""
+    import oracle
+    ids = b.ids[:b.max_ids].cpu().numpy().view(np.uint32)
+    R = b.nseg
+    rng = np.random.default_rng(0)
+    sizes = np.diff(host["seg_off"].astype(np.int64))
+    big = np.argsort(sizes)[-4:]
+    pick = np.unique(np.concatenate([big, rng.choice(R, min(R, n_check), replace=False)]))
+    data = out[:int(sbo_h[-1])].cpu().numpy()
+    for r in pick:
+        s, e = int(host["seg_off"][r]), int(host["seg_off"][r + 1])
+        ob = oracle.Batch(ids[s:e], [0, e - s], [host["seg_lo"][r]], [host["seg_hi"][r]],
+                          [host["seg_level"][r]])
+        want, _ = oracle.encode(ob, mode=mode)
+        got = data[int(sbo_h[r]):int(sbo_h[r + 1])]
+        assert np.array_equal(got, want), "segment %d differs from the oracle" % r
+
+
+def cpu_baseline(b, host, seconds, mode):
+    """The oracle's encode + decode on a bounded sample of the same batch,
+    single thread on this host, scaled to GB/s of raw bytes."""
+    import oracle
+    ids = b.ids[:b.max_ids].cpu().numpy().view(np.uint32)
+    R = b.nseg
+    order = np.random.default_rng(1).permutation(R)
+    done_ids, t_used, segs = 0, 0.0, 0
+    for r in order:
+        s, e = int(host["seg_off"][r]), int(host["seg_off"][r + 1])
+        if e == s:
+            continue
+        ob = oracle.Batch(ids[s:e], [0, e - s], [host["seg_lo"][r]], [host["seg_hi"][r]],
+                          [host["seg_level"][r]])
+        t = time.perf_counter()
+        stream, sbo = oracle.encode(ob, mode=mode)
+        st, got, _ = oracle.decode(stream, sbo)
+        t_used += time.perf_counter() - t
+        assert st == 0
+        done_ids += e - s
+        segs += 1
+        if t_used >= seconds:
+            break
+    return {"value": round(4.0 * done_ids / t_used / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d random segments (%d IDs, %.1f%% of the batch), encode+decode, %.1f s"
+                      % (segs, done_ids, 100.0 * done_ids / max(1, b.max_ids), t_used),
+            "cpu": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

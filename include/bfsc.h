@@ -234,6 +234,16 @@ int bfsc_get_tune(const bfsc_ctx *ctx, bfsc_tune *out);
 int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t);
 int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *stream);
 
+/* Per-kernel timing.  While enabled, every launch of an operation's main
+ * kernel (BFSC_OP_ENCODE: the encoder, BFSC_OP_DECODE: the decoder,
+ * BFSC_OP_SELECT / BFSC_OP_FEATURES: the selector, BFSC_OP_BFS: the whole
+ * level) is bracketed by a HIP event pair on the caller's stream (at most
+ * 4096 pairs are kept).  bfsc_timing_read waits for the events of `op`,
+ * returns their summed milliseconds and count, and forgets them.  Enabling
+ * clears all recorded pairs. */
+int bfsc_timing_enable(bfsc_ctx *ctx, int enable);
+int bfsc_timing_read(bfsc_ctx *ctx, int op, double *total_ms, uint64_t *count);
+
 /* Waits for `stream`, reads and clears the latched kernel error word:
  * returns BFSC_OK or the first error class found (CORRUPT > CAPACITY > INVAL). */
 int bfsc_sync_status(bfsc_ctx *ctx, void *stream);

@@ -186,6 +186,18 @@ class Context:
     def sync(self, stream=None) -> None:
         check(self.sync_status(stream), "kernel status")
 
+    # ---------------------------------------------------------- timing
+
+    def timing(self, enable: bool = True) -> None:
+        check(_lib.load().bfsc_timing_enable(self.h, int(enable)), "bfsc_timing_enable")
+
+    def timing_read(self, op: int):
+        """-> (total milliseconds, launches) of op's main kernel since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_uint64()
+        check(_lib.load().bfsc_timing_read(self.h, op, ctypes.byref(ms), ctypes.byref(n)),
+              "bfsc_timing_read")
+        return ms.value, n.value
+
     # ---------------------------------------------------------- tuning
 
     def get_tune(self):

@@ -67,6 +67,8 @@ _SIGS = {
     "bfsc_set_tune": [vp, P(Tune)],
     "bfsc_autotune": [vp, P(BatchDesc), vp, vp],
     "bfsc_sync_status": [vp, vp],
+    "bfsc_timing_enable": [vp, ctypes.c_int],
+    "bfsc_timing_read": [vp, ctypes.c_int, P(ctypes.c_double), P(u64)],
 }
 
 _lock = threading.Lock()
@@ -74,13 +76,18 @@ _lib = None
 
 
 def load() -> ctypes.CDLL:
-    """Loads libbfsc.so; raises if it has not been built."""
+    """Loads libbfsc.so; raises if it has not been built.
+
+    torch is imported first: it brings its own HIP runtime (SONAME
+    libamdhip64.so.7), and the library's dependency on that SONAME must bind
+    to the runtime already in the process, never to a second copy."""
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError("libbfsc.so not found at %s: build it with "
                                   "`python -m paper_1704_00513_amd.build`" % LIB_PATH)
+            import torch  # noqa: F401  (loads the process's HIP runtime)
             lib = ctypes.CDLL(LIB_PATH)
             for name, args in _SIGS.items():
                 fn = getattr(lib, name)

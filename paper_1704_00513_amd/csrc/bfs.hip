@@ -290,6 +290,7 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
     BfsWs ws = bfs_ws_layout(wsp, g->n_vertices, g->n_arcs, nullptr);
     const int32_t nl = cur_level + 1;
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
+    const int slot = timing_begin(ctx, BFSC_OP_BFS, s);
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
                        frontier, frontier_len, level, parent, nl, ws);
     hipLaunchKernelGGL(k_bfs_huge, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, level,
@@ -297,6 +298,7 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.nchunks), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws, next_len);
     hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next);
+    timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 

@@ -22,6 +22,32 @@ int launch_round16(bfsc_ctx *ctx, hipStream_t s);
 
 static inline hipStream_t S(void *s) { return (hipStream_t)s; }
 
+namespace bfsc {
+
+int timing_begin(bfsc_ctx *ctx, int op, hipStream_t s) {
+    if (!ctx->timing || ctx->n_timed >= 4096) return -1;
+    const uint32_t i = ctx->n_timed;
+    if (i >= ctx->ev_created) {
+        if (hipEventCreate(&ctx->ev_a[i]) != hipSuccess) return -1;
+        if (hipEventCreate(&ctx->ev_b[i]) != hipSuccess) {
+            hipEventDestroy(ctx->ev_a[i]);
+            return -1;
+        }
+        ctx->ev_created = i + 1;
+    }
+    if (hipEventRecord(ctx->ev_a[i], s) != hipSuccess) return -1;
+    ctx->timed_op[i] = op;
+    ctx->n_timed = i + 1;
+    return (int)i;
+}
+
+void timing_end(bfsc_ctx *ctx, int slot, hipStream_t s) {
+    if (slot < 0) return;
+    if (hipEventRecord(ctx->ev_b[slot], s) != hipSuccess) ctx->timed_op[slot] = -1;
+}
+
+}  // namespace bfsc
+
 static int set_device(const bfsc_ctx *ctx) {
     return hipSetDevice(ctx->device) == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
@@ -79,6 +105,10 @@ int bfsc_destroy(bfsc_ctx *ctx) {
     hipFree(ctx->adam_v);
     hipFree(ctx->mlp_grad);
     hipFree(ctx->mlp_w16);
+    for (uint32_t i = 0; i < ctx->ev_created; ++i) {
+        hipEventDestroy(ctx->ev_a[i]);
+        hipEventDestroy(ctx->ev_b[i]);
+    }
     delete ctx;
     return BFSC_OK;
 }
@@ -255,6 +285,45 @@ int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t) {
 int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *stream) {
     (void)ctx; (void)sample; (void)ws; (void)stream;
     return BFSC_E_UNIMPLEMENTED;
+}
+
+int bfsc_timing_enable(bfsc_ctx *ctx, int enable) {
+    if (!ctx) return BFSC_E_INVAL;
+    ctx->timing = enable ? 1 : 0;
+    ctx->n_timed = 0;
+    return BFSC_OK;
+}
+
+int bfsc_timing_read(bfsc_ctx *ctx, int op, double *total_ms, uint64_t *count) {
+    if (!ctx || !total_ms || !count) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    double tot = 0.0;
+    uint64_t cnt = 0;
+    uint32_t keep = 0;
+    for (uint32_t i = 0; i < ctx->n_timed; ++i) {
+        if (ctx->timed_op[i] != op) {
+            // compact the slots of other operations to the front
+            if (keep != i) {
+                hipEvent_t a = ctx->ev_a[keep], b = ctx->ev_b[keep];
+                ctx->ev_a[keep] = ctx->ev_a[i];
+                ctx->ev_b[keep] = ctx->ev_b[i];
+                ctx->ev_a[i] = a;
+                ctx->ev_b[i] = b;
+                ctx->timed_op[keep] = ctx->timed_op[i];
+            }
+            ++keep;
+            continue;
+        }
+        HIP_OK(hipEventSynchronize(ctx->ev_b[i]));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, ctx->ev_a[i], ctx->ev_b[i]));
+        tot += ms;
+        ++cnt;
+    }
+    ctx->n_timed = keep;
+    *total_ms = tot;
+    *count = cnt;
+    return BFSC_OK;
 }
 
 int bfsc_sync_status(bfsc_ctx *ctx, void *stream) {

@@ -950,6 +950,7 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     a.err = ctx->err;
     const uint32_t waves = ctx->tune.enc_waves;
     const uint32_t grid = persistent_grid(ctx, ctx->tune.enc_wg_per_cu, p.max_tiles);
+    const int slot = timing_begin(ctx, BFSC_OP_ENCODE, s);
     switch (waves) {
         case 1: hipLaunchKernelGGL(k_encode<1>, dim3(grid), dim3(64), 0, s, a); break;
         case 2: hipLaunchKernelGGL(k_encode<2>, dim3(grid), dim3(128), 0, s, a); break;
@@ -957,6 +958,7 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
         case 16: hipLaunchKernelGGL(k_encode<16>, dim3(grid), dim3(1024), 0, s, a); break;
         default: hipLaunchKernelGGL(k_encode<4>, dim3(grid), dim3(256), 0, s, a); break;
     }
+    timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -979,7 +981,9 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
     a.p = p;
     a.err = ctx->err;
     const uint32_t grid = persistent_grid(ctx, 4, p.max_tiles);
+    const int slot = timing_begin(ctx, feat ? BFSC_OP_FEATURES : BFSC_OP_SELECT, s);
     hipLaunchKernelGGL(k_select<4>, dim3(grid), dim3(256), 0, s, a);
+    timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -1016,6 +1020,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     a.err = ctx->err;
     const uint64_t mt = plan_max_tiles(max_ids, nseg);
     const uint32_t grid = persistent_grid(ctx, ctx->tune.dec_wg_per_cu, mt);
+    const int slot = timing_begin(ctx, BFSC_OP_DECODE, s);
     switch (ctx->tune.dec_waves) {
         case 1: hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(64), 0, s, a); break;
         case 2: hipLaunchKernelGGL(k_decode<2>, dim3(grid), dim3(128), 0, s, a); break;
@@ -1023,6 +1028,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
         case 16: hipLaunchKernelGGL(k_decode<16>, dim3(grid), dim3(1024), 0, s, a); break;
         default: hipLaunchKernelGGL(k_decode<4>, dim3(grid), dim3(256), 0, s, a); break;
     }
+    timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 

@@ -187,7 +187,20 @@ struct bfsc_ctx {
     _Float16 *mlp_w16;      // device fp16 copy of the parameters [7011]
     uint32_t adam_t;
     bfsc_tune tune;
+    // per-kernel event timing (bfsc_timing_enable / bfsc_timing_read)
+    int timing;
+    uint32_t n_timed;
+    int timed_op[4096];
+    hipEvent_t ev_a[4096], ev_b[4096];
+    uint32_t ev_created;
 };
+
+namespace bfsc {
+// Brackets one kernel launch with an event pair on stream s when timing is
+// on; returns the slot (or -1).
+int timing_begin(bfsc_ctx *ctx, int op, hipStream_t s);
+void timing_end(bfsc_ctx *ctx, int slot, hipStream_t s);
+}  // namespace bfsc
 
 // Launch helpers defined in the kernel files.
 namespace bfsc {

@@ -24,7 +24,8 @@ def lib():
     if not os.path.exists(LIB):
         from paper_1704_00513_amd import build
         build.build()
-    return ctypes.CDLL(LIB)
+    from paper_1704_00513_amd import _lib
+    return _lib.load()
 
 
 def test_every_declared_symbol_is_exported(lib):

@@ -61,7 +61,7 @@ def batches():
     top = np.array([0, 1, 0xFFFFFF00, 0xFFFFFFF0, 0xFFFFFFFD], np.uint32)
     out.append(("top", Batch(top, [0, 5], [0], [0xFFFFFFFE], [0])))
     # all segments empty but one
-    out.append(("mostly-empty", Batch(np.array([10, 20], np.uint32), [0, 0, 0, 2, 2], [0, 5, 8, 9],
+    out.append(("mostly-empty", Batch(np.array([10, 20], np.uint32), [0, 0, 0, 0, 2], [0, 5, 8, 9],
                                       [5, 8, 9, 100], [0, 0, 0, 0])))
     return out
 
@@ -129,8 +129,8 @@ def test_invalid_input_is_reported(ctx):
     assert st == 1
     out_of_range = Batch(np.array([1, 2, 300], np.uint32), [0, 3], [0], [100], [0])
     assert gpu_encode(ctx, out_of_range)[0] == 1
-    b = batches()[0][1]
-    d = oracle.block_details(b)
+    b = batches()[2][1]  # a multi-block level: gaps of at least 1
+    assert b.n_ids > 1000
     cls = np.full(b.n_blocks, 1, np.uint8)  # width 0 cannot hold real gaps
     assert gpu_encode(ctx, b, classes=cls)[0] == 1
     # still usable afterwards
