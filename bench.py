@@ -134,6 +134,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -195,11 +196,15 @@ def main():
         step()
     ctx.sync()
     enc_ms, enc_n = ctx.timing_read(P.OP_ENCODE)
+    place_ms, place_n = ctx.timing_read(P._lib.OP_ENCODE_PLACE)
     dec_ms, dec_n = ctx.timing_read(P.OP_DECODE)
     ctx.timing(False)
     enc_avg, dec_avg = enc_ms / enc_n, dec_ms / dec_n
-    alg_bytes = 4.0 * N + comp  # per launch, for encode and for decode alike
-    dom = ("k_encode", enc_avg) if enc_avg >= dec_avg else ("k_decode", dec_avg)
+    place_avg = place_ms / max(1, place_n)
+    # algorithmic bytes per launch: the pack pass reads the raw IDs and writes
+    # the compressed content; the decoder reads it and writes the raw IDs
+    alg_bytes = 4.0 * N + comp
+    dom = ("k_enc_pack", enc_avg) if enc_avg >= dec_avg else ("k_decode", dec_avg)
     achieved = alg_bytes / (dom[1] * 1e-3) / 1e9
     workload = "rmat-s%d" % args.scale if args.graph == "rmat" else "uniform-s%d" % args.scale
     workload += "-%droots-%s%d-%s" % (args.roots, args.bounds, args.nseg, args.mode)
@@ -224,8 +229,9 @@ def main():
         "ratio": round(4.0 * N / comp, 4),
         "compressed_bytes": comp,
         "encode_ms": round(enc_avg, 4),
+        "encode_place_ms": round(place_avg, 4),
         "decode_ms": round(dec_avg, 4),
-        "encode_GBps_raw": round(4.0 * N / enc_avg / 1e6, 1),
+        "encode_GBps_raw": round(4.0 * N / (enc_avg + place_avg) / 1e6, 1),
         "decode_GBps_raw": round(4.0 * N / dec_avg / 1e6, 1),
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -235,10 +241,112 @@ def main():
         "bfs": {"ms_total": round(bfs["bfs_ms"], 3), "levels": bfs["bfs_levels"],
                 "GTEPS": round(bfs["edges"] / 2 / (bfs["bfs_ms"] * 1e-3) / 1e9, 3)},
     }
+    if not args.no_extra:
+        res["extra"] = extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(b, host, args.cpu_seconds, mode)
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
+    """Comparison legs on the same batch: learned selector vs exhaustive, one
+    launch per segment vs one batched launch, per-level pipeline replayed
+    from HIP graphs vs launched kernel by kernel."""
+    out = {}
+    cap = P.Context.encode_bound(N, b.nseg)
+    buf = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    sbo = torch.zeros(b.nseg + 1, dtype=torch.int64, device="cuda")
+    dec = torch.empty(max(1, N), dtype=torch.int32, device="cuda")
+    doff = torch.zeros(b.nseg + 1, dtype=torch.int64, device="cuda")
+    steps = max(3, args.steps // 2)
+
+    # learned selector (weights trained by paper_1704_00513_amd/train.py)
+    wpath = os.path.join(ROOT, "paper_1704_00513_amd", "selector_weights.npy")
+    if os.path.exists(wpath):
+        ctx.mlp_set_weights(np.load(wpath, allow_pickle=False))
+        cls = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda")
+        fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+        def lstep():
+            ctx.select(b, P.SEL_LEARNED, cls, fallbacks=fb)
+            ctx.encode(b, buf, sbo, classes=cls)
+            ctx.decode(buf, sbo, b.nseg, N, dec, doff)
+
+        lstep()
+        ctx.sync()
+        assert torch.equal(dec[:N], b.ids[:N]), "learned round trip differs"
+        lcomp = int(sbo[-1].item())
+        fb.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            lstep()
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - t) * 1e3 / steps
+        ctx.sync()
+        nblk = int(sum((np.diff(host["seg_off"].astype(np.int64)) + 127) // 128))
+        out["learned"] = {"value_GBps": round(4.0 * N / (lms * 1e-3) / 1e9, 2),
+                          "ms_per_step": round(lms, 4),
+                          "compressed_bytes": lcomp,
+                          "size_gap_vs_exhaustive_pct": round(100.0 * (lcomp - comp) / comp, 3),
+                          "fallback_rate": round(int(fb.item()) / steps / max(1, nblk), 5),
+                          "vs_exhaustive_speed": round(ms_step / lms, 3)}
+
+    # one launch per segment (the same kernels, a one-segment batch each)
+    segs = []
+    so = host["seg_off"]
+    for r in range(b.nseg):
+        s, e = int(so[r]), int(so[r + 1])
+        if e == s:
+            continue
+        sb = P.DeviceBatch(b.ids[s:e], torch.tensor([0, e - s], dtype=torch.int64, device="cuda"),
+                           b.seg_lo[r:r + 1], b.seg_hi[r:r + 1], b.seg_level[r:r + 1], max_ids=e - s)
+        o = torch.zeros(P.Context.encode_bound(e - s, 1), dtype=torch.uint8, device="cuda")
+        segs.append((sb, o, torch.zeros(2, dtype=torch.int64, device="cuda"), dec[s:e],
+                     torch.zeros(2, dtype=torch.int64, device="cuda"), e - s))
+    ws_e = ctx.workspace(P.OP_ENCODE, max(x[5] for x in segs), 1, key="perseg_e")
+    ws_d = ctx.workspace(P.OP_DECODE, max(x[5] for x in segs), 1, key="perseg_d")
+
+    def pstep():
+        for sb, o, sbo1, d, doff1, n in segs:
+            ctx.encode(sb, o, sbo1, mode=mode, ws=ws_e)
+            ctx.decode(o, sbo1, 1, n, d, doff1, ws=ws_d)
+
+    pstep()
+    ctx.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        pstep()
+    torch.cuda.synchronize()
+    pms = (time.perf_counter() - t) * 1e3 / 3
+    out["per_segment_launches"] = {"segments": len(segs), "ms_per_step": round(pms, 3),
+                                   "value_GBps": round(4.0 * N / (pms * 1e-3) / 1e9, 2),
+                                   "batched_speedup": round(pms / ms_step, 2)}
+
+    # per-level pipeline for the first root: graph replay vs eager launches
+    dg = P.DeviceGraph.from_host(g)
+    bounds = host["seg_hi"][:args.nseg]
+    bounds = np.concatenate([[host["seg_lo"][0]], bounds]).astype(np.uint32)
+    for use_graph in (True, False):
+        pipe = P.Pipeline(ctx, dg, bounds, mode=mode, use_graph=use_graph)
+        times = []
+        for rep in range(3):
+            pipe.start(int(roots[0]))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            L, n = 0, 1
+            while n:
+                n = pipe.step()
+                L += 1
+            times.append((time.perf_counter() - t) * 1e3)
+        ctx.sync()
+        pipe.close()
+        key = "pipeline_graph" if use_graph else "pipeline_eager"
+        out[key] = {"levels": L, "ms_traversal": round(min(times), 3),
+                    "us_per_level": round(1e3 * min(times) / L, 1)}
+    return out
 
 
 def check_segments(out, sbo_h, b, host, mode, n_check=24):

@@ -79,7 +79,9 @@ enum {
     BFSC_OP_ENCODE = 2,
     BFSC_OP_DECODE = 3,
     BFSC_OP_FEATURES = 4,
-    BFSC_OP_MLP = 5
+    BFSC_OP_MLP = 5,
+    BFSC_OP_ENCODE_PLACE = 6, /* timing only: the encoder's placement pass */
+    BFSC_OP_PIPELINE = 7      /* timing only: one bfsc_pipeline_step */
 };
 
 /* One GPU's CSR partition: a row range with global column IDs; on one GPU
@@ -243,6 +245,50 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
  * clears all recorded pairs. */
 int bfsc_timing_enable(bfsc_ctx *ctx, int enable);
 int bfsc_timing_read(bfsc_ctx *ctx, int op, double *total_ms, uint64_t *count);
+
+/* Per-level pipeline: the level loop of the BFS-with-compression algorithm
+ * on one GPU.  One step takes the current frontier F_L, splits it into the
+ * nseg destination ranges given by bounds_host (u32[nseg+1], host,
+ * non-decreasing), chooses a codec per block with `mode`, encodes, decodes
+ * (the exchange itself is left out), and expands F_L into F_{L+1}.  The
+ * pipeline owns its device buffers (allocated at create, freed at destroy).
+ * use_graph != 0 captures the step into two HIP graphs (even / odd level,
+ * ping-pong frontier buffers; the level number lives on the device) that
+ * every step replays; use_graph == 0 launches the same kernels one by one.
+ * create is synchronous; start and step enqueue on `stream`; step with a
+ * non-NULL next_len_host also waits and returns the length of F_{L+1}. */
+typedef struct bfsc_pipeline bfsc_pipeline;
+
+/* Device buffers of a pipeline (valid until destroy).  After a step,
+ * prev_frontier holds the frontier that step compressed, seg_off its
+ * segments, stream / seg_byte_off its compressed form and decoded /
+ * decoded_off the decompressed IDs; frontier holds the next frontier. */
+typedef struct {
+    uint32_t *frontier;
+    uint32_t *frontier_len;
+    uint32_t *prev_frontier;
+    uint32_t *prev_frontier_len;
+    int32_t *level;
+    int32_t *parent;
+    uint64_t *seg_off;
+    uint8_t *stream;
+    size_t stream_cap;
+    uint64_t *seg_byte_off;
+    uint32_t *decoded;
+    uint64_t *decoded_off;
+    uint8_t *classes;
+} bfsc_pipeline_bufs;
+
+int bfsc_pipeline_create(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *bounds_host, uint32_t nseg,
+                         int mode, int use_graph, bfsc_pipeline **out);
+int bfsc_pipeline_start(bfsc_pipeline *p, uint32_t root, void *stream);
+int bfsc_pipeline_step(bfsc_pipeline *p, void *stream, uint32_t *next_len_host);
+int bfsc_pipeline_buffers(const bfsc_pipeline *p, bfsc_pipeline_bufs *bufs);
+int bfsc_pipeline_destroy(bfsc_pipeline *p);
+
+/* Synchronous copy of `bytes` between any two pointers the HIP runtime
+ * knows (host or device), for reading pipeline buffers. */
+int bfsc_memcpy(void *dst, const void *src, size_t bytes);
 
 /* Waits for `stream`, reads and clears the latched kernel error word:
  * returns BFSC_OK or the first error class found (CORRUPT > CAPACITY > INVAL). */

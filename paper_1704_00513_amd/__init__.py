@@ -81,6 +81,73 @@ class DeviceBatch:
         return (self.max_ids + 127) // 128 + self.nseg
 
 
+def memcpy_to_host(dev_ptr: int, count: int, dtype) -> np.ndarray:
+    """Copies count elements of dtype from a device pointer (synchronous)."""
+    out = np.empty(count, dtype)
+    if count:
+        check(_lib.load().bfsc_memcpy(out.ctypes.data, dev_ptr, out.nbytes), "bfsc_memcpy")
+    return out
+
+
+class Pipeline:
+    """The per-level BFS + compression pipeline of one traversal (see
+    bfsc_pipeline_* in bfsc.h).  use_graph replays captured HIP graphs."""
+
+    def __init__(self, ctx: "Context", g: DeviceGraph, bounds, mode=SEL_EXHAUSTIVE,
+                 use_graph: bool = True):
+        self.ctx, self.g = ctx, g
+        self.bounds = np.ascontiguousarray(bounds, np.uint32)
+        self.nseg = self.bounds.size - 1
+        h = ctypes.c_void_p()
+        check(_lib.load().bfsc_pipeline_create(ctx.h, ctypes.byref(g.desc), self.bounds.ctypes.data,
+                                               self.nseg, int(mode), int(use_graph), ctypes.byref(h)),
+              "bfsc_pipeline_create")
+        self.h = h
+
+    def start(self, root: int, stream=None):
+        check(_lib.load().bfsc_pipeline_start(self.h, int(root), _stream(stream)), "bfsc_pipeline_start")
+
+    def step(self, stream=None, wait: bool = True):
+        """One level; returns the next frontier's length when wait is set."""
+        n = ctypes.c_uint32()
+        check(_lib.load().bfsc_pipeline_step(self.h, _stream(stream),
+                                             ctypes.byref(n) if wait else None), "bfsc_pipeline_step")
+        return int(n.value) if wait else None
+
+    def buffers(self) -> "_lib.PipelineBufs":
+        b = _lib.PipelineBufs()
+        check(_lib.load().bfsc_pipeline_buffers(self.h, ctypes.byref(b)), "bfsc_pipeline_buffers")
+        return b
+
+    def last_step(self):
+        """Host copies of what the last step compressed and decompressed."""
+        b = self.buffers()
+        n = int(memcpy_to_host(b.prev_frontier_len, 1, np.uint32)[0])
+        sbo = memcpy_to_host(b.seg_byte_off, self.nseg + 1, np.uint64)
+        return dict(frontier=memcpy_to_host(b.prev_frontier, n, np.uint32),
+                    seg_off=memcpy_to_host(b.seg_off, self.nseg + 1, np.uint64),
+                    stream=memcpy_to_host(b.stream, int(sbo[-1]), np.uint8),
+                    seg_byte_off=sbo,
+                    decoded=memcpy_to_host(b.decoded, n, np.uint32),
+                    decoded_off=memcpy_to_host(b.decoded_off, self.nseg + 1, np.uint64))
+
+    def levels(self):
+        b = self.buffers()
+        return (memcpy_to_host(b.level, self.g.n_vertices, np.int32),
+                memcpy_to_host(b.parent, self.g.n_vertices, np.int32))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.load().bfsc_pipeline_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One bfsc context on one GPU, with grow-only workspaces."""
 
@@ -211,6 +278,13 @@ class Context:
         cur.update(kw)
         t = _lib.Tune(cur["enc_waves"], cur["enc_wg_per_cu"], cur["dec_waves"], cur["dec_wg_per_cu"])
         check(_lib.load().bfsc_set_tune(self.h, ctypes.byref(t)), "bfsc_set_tune")
+
+    def autotune(self, b: "DeviceBatch", ws=None, stream=None):
+        """Measures the launch shapes on a sample batch and keeps the fastest."""
+        ws = ws if ws is not None else self.workspace(OP_ENCODE, b.max_ids, b.nseg)
+        check(_lib.load().bfsc_autotune(self.h, ctypes.byref(b.desc), ptr(ws), _stream(stream)),
+              "bfsc_autotune")
+        return self.get_tune()
 
     # ---------------------------------------------------------- MLP
 

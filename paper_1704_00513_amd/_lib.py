@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbfsc.so")
 OK, E_INVAL, E_CAPACITY, E_CORRUPT, E_HIP, E_UNIMPLEMENTED = 0, 1, 2, 3, 4, 5
 SEL_PLAIN_BP, SEL_EXHAUSTIVE, SEL_LEARNED = 0, 1, 2
 OP_BFS, OP_SELECT, OP_ENCODE, OP_DECODE, OP_FEATURES, OP_MLP = 0, 1, 2, 3, 4, 5
+OP_ENCODE_PLACE, OP_PIPELINE = 6, 7
 N_PARAMS = 7011
 
 vp = ctypes.c_void_p
@@ -43,8 +44,21 @@ class Tune(ctypes.Structure):
                 ("dec_wg_per_cu", u32)]
 
 
+class PipelineBufs(ctypes.Structure):
+    _fields_ = [("frontier", vp), ("frontier_len", vp), ("prev_frontier", vp),
+                ("prev_frontier_len", vp), ("level", vp), ("parent", vp), ("seg_off", vp),
+                ("stream", vp), ("stream_cap", sz), ("seg_byte_off", vp), ("decoded", vp),
+                ("decoded_off", vp), ("classes", vp)]
+
+
 P = ctypes.POINTER
 _SIGS = {
+    "bfsc_pipeline_create": [vp, P(CSR), vp, u32, ctypes.c_int, ctypes.c_int, P(vp)],
+    "bfsc_pipeline_start": [vp, u32, vp],
+    "bfsc_pipeline_step": [vp, vp, P(u32)],
+    "bfsc_pipeline_buffers": [vp, P(PipelineBufs)],
+    "bfsc_pipeline_destroy": [vp],
+    "bfsc_memcpy": [vp, vp, sz],
     "bfsc_create": [P(vp), ctypes.c_int],
     "bfsc_destroy": [vp],
     "bfsc_workspace_size": [vp, ctypes.c_int, u64, u32, P(sz)],

@@ -70,7 +70,9 @@ __device__ __forceinline__ void visit(uint32_t w, uint32_t u, int32_t nl, const 
 
 __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
     const uint64_t *row_ptr, const uint32_t *col_idx, const uint32_t *frontier,
-    const uint32_t *frontier_len, int32_t *level, int32_t *parent, int32_t nl, BfsWs ws) {
+    const uint32_t *frontier_len, int32_t *level, int32_t *parent, int32_t nl_host, const int32_t *level_dev, BfsWs ws) {
+    // the new level: from the host, or one past the level kept on the device
+    const int32_t nl = level_dev ? *level_dev + 1 : nl_host;
     __shared__ uint32_t s_deg_scan[kExpandThreads];
     __shared__ uint32_t s_u[kExpandThreads];
     __shared__ uint64_t s_start[kExpandThreads];
@@ -166,7 +168,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
 }
 
 __global__ __launch_bounds__(256) void k_bfs_huge(const uint32_t *col_idx, int32_t *level,
-                                                  int32_t *parent, int32_t nl, BfsWs ws) {
+                                                  int32_t *parent, int32_t nl_host,
+                                                  const int32_t *level_dev, BfsWs ws) {
+    const int32_t nl = level_dev ? *level_dev + 1 : nl_host;
     const uint32_t nq = min(*ws.qcount, ws.qcap);
     for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const uint4 c = ws.queue[q];
@@ -284,17 +288,27 @@ int launch_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *le
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
+// Increments the device-side level (end of a captured pipeline step).
+__global__ void k_level_inc(int32_t *level_dev) { *level_dev += 1; }
+
+int launch_level_inc(int32_t *level_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_inc, dim3(1), dim3(1), 0, s, level_dev);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+// cur_level_dev != NULL: the current level is read on the device (for
+// replayed graphs); otherwise cur_level is used.
 int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *frontier,
                      const uint32_t *frontier_len, int32_t *level, int32_t *parent, uint32_t *next,
-                     uint32_t *next_len, void *wsp, hipStream_t s) {
+                     uint32_t *next_len, void *wsp, hipStream_t s, const int32_t *cur_level_dev) {
     BfsWs ws = bfs_ws_layout(wsp, g->n_vertices, g->n_arcs, nullptr);
     const int32_t nl = cur_level + 1;
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     const int slot = timing_begin(ctx, BFSC_OP_BFS, s);
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
-                       frontier, frontier_len, level, parent, nl, ws);
+                       frontier, frontier_len, level, parent, nl, cur_level_dev, ws);
     hipLaunchKernelGGL(k_bfs_huge, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, level,
-                       parent, nl, ws);
+                       parent, nl, cur_level_dev, ws);
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.nchunks), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws, next_len);
     hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next);

@@ -88,7 +88,7 @@ int bfsc_create(bfsc_ctx **out, int device) {
         bfsc_destroy(c);
         return BFSC_E_HIP;
     }
-    c->tune.enc_waves = 4;
+    c->tune.enc_waves = 8;
     c->tune.enc_wg_per_cu = 8;
     c->tune.dec_waves = 4;
     c->tune.dec_wg_per_cu = 8;
@@ -119,7 +119,7 @@ int bfsc_workspace_size(const bfsc_ctx *ctx, int op, uint64_t max_ids, uint32_t 
         case BFSC_OP_SELECT:
         case BFSC_OP_ENCODE:
         case BFSC_OP_FEATURES:
-            *bytes = plan_layout(nullptr, max_ids, nseg, nullptr);
+            *bytes = plan_layout(nullptr, max_ids, nseg, op == BFSC_OP_ENCODE, nullptr);
             return BFSC_OK;
         case BFSC_OP_DECODE:
             *bytes = decode_ws_bytes(max_ids, nseg);
@@ -170,7 +170,7 @@ int bfsc_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes,
     if (mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     Plan p;
-    plan_layout(ws, b->max_ids, b->nseg, &p);
+    plan_layout(ws, b->max_ids, b->nseg, false, &p);
     int st = launch_plan_prep(b, p, ctx->err, false, S(stream));
     if (st) return st;
     return launch_select(ctx, b, mode, classes, fallbacks_dev, nullptr, p, S(stream));
@@ -180,7 +180,7 @@ int bfsc_features(bfsc_ctx *ctx, const bfsc_batch *b, uint16_t *feat, void *ws, 
     if (!ctx || !batch_ok(b) || !feat || !ws) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     Plan p;
-    plan_layout(ws, b->max_ids, b->nseg, &p);
+    plan_layout(ws, b->max_ids, b->nseg, false, &p);
     int st = launch_plan_prep(b, p, ctx->err, false, S(stream));
     if (st) return st;
     return launch_select(ctx, b, BFSC_SEL_EXHAUSTIVE, nullptr, nullptr, feat, p, S(stream));
@@ -200,7 +200,7 @@ int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int 
     if (((uintptr_t)out & 3) || mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     Plan p;
-    plan_layout(ws, b->max_ids, b->nseg, &p);
+    plan_layout(ws, b->max_ids, b->nseg, true, &p);
     int st = launch_plan_prep(b, p, ctx->err, true, S(stream));
     if (st) return st;
     if (mode == BFSC_SEL_LEARNED && !classes) return BFSC_E_INVAL;  // select first, then encode
@@ -280,11 +280,6 @@ int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t) {
         return BFSC_E_INVAL;
     ctx->tune = *t;
     return BFSC_OK;
-}
-
-int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *stream) {
-    (void)ctx; (void)sample; (void)ws; (void)stream;
-    return BFSC_E_UNIMPLEMENTED;
 }
 
 int bfsc_timing_enable(bfsc_ctx *ctx, int enable) {

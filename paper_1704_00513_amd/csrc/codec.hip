@@ -1,37 +1,40 @@
 // Frontier codec kernels for gfx950: batch planning, per-block codec choice,
-// single-pass encode (decoupled look-back for output offsets) and validating
-// decode.  The block formats follow the compression techniques of Romera,
-// arXiv 1704.00513 (delta coding + binary packing in blocks of 128, eqs.
-// (6)-(7); patched coding with exceptions, eqs. (8)-(9); bitmap indexes for
-// dense sets), in this project's own byte layout (described in bfsc.h).
+// encode and validating decode.  The block formats follow the compression
+// techniques of Romera, arXiv 1704.00513 (delta coding + binary packing in
+// blocks of 128, eqs. (6)-(7); patched coding with exceptions, eqs. (8)-(9);
+// bitmap indexes for dense sets), in this project's own byte layout
+// (described in bfsc.h).
 //
 // Work decomposition: a tile is one group of <= 16 blocks of one segment.
 // One wave handles one 128-ID block at a time, two IDs per lane (lane l holds
-// IDs l and 64+l, so loads and stores are fully coalesced).
+// IDs l and 64+l, so loads and stores are fully coalesced); cross-lane steps
+// use DPP.  Encode = pack pass (every tile into a private slot; the last
+// workgroup to finish scans the tile sizes) + place pass.  Decode is one pass:
+// the group table gives every tile its payload offset.
 #include "common.hpp"
 
 namespace bfsc {
 
 // ------------------------------------------------------------------ scans
 
-// Exclusive prefix sum over a 1024-thread workgroup (16 waves).
+// Exclusive prefix sum over a workgroup of up to 1024 threads.
 __device__ uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tmp /*[17]*/, uint32_t *total) {
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t nw = blockDim.x >> 6;
-    uint32_t incl = wave_incl_scan(v);
+    const uint32_t incl = wave_incl_scan(v);
     if (lane == 63) s_tmp[w] = incl;
     __syncthreads();
     if (tid == 0) {
         uint32_t acc = 0;
         for (uint32_t i = 0; i < nw; ++i) {
-            uint32_t x = s_tmp[i];
+            const uint32_t x = s_tmp[i];
             s_tmp[i] = acc;
             acc += x;
         }
         s_tmp[16] = acc;
     }
     __syncthreads();
-    uint32_t r = s_tmp[w] + incl - v;
+    const uint32_t r = s_tmp[w] + incl - v;
     *total = s_tmp[16];
     __syncthreads();
     return r;
@@ -46,43 +49,32 @@ struct PlanArgs {
     uint32_t nseg;
     uint64_t max_ids;
     Plan p;
-    uint32_t *seg_n;
     uint32_t *err;
-    int zero_status;
 };
 
-// All workgroups clear the look-back state; workgroup 0 computes the
-// per-segment block / group / tile bases.
+// One workgroup: per-segment block / group / tile bases.
 __global__ __launch_bounds__(1024) void k_plan_prep(PlanArgs a) {
     const uint32_t tid = threadIdx.x;
-    if (a.zero_status) {
-        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + tid; i < a.p.max_tiles; i += stride)
-            a.p.status[i] = 0;
-        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + tid; i < a.nseg; i += stride)
-            a.p.seg_pw[i] = 0;
-    }
-    if (blockIdx.x != 0) return;
     __shared__ uint32_t s_tmp[17];
     uint32_t cb = 0, cg = 0, ct = 0;
     for (uint32_t base = 0; base < a.nseg; base += blockDim.x) {
-        uint32_t r = base + tid;
+        const uint32_t r = base + tid;
         uint32_t nb = 0, ng = 0, nt = 0;
         if (r < a.nseg) {
-            uint64_t s = a.seg_off[r], e = a.seg_off[r + 1];
-            uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
-            bool bad = e < s || e > a.max_ids || lo > hi || (e - s) > (uint64_t)(hi - lo);
-            uint32_t n = bad ? 0u : (uint32_t)(e - s);
+            const uint64_t s = a.seg_off[r], e = a.seg_off[r + 1];
+            const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
+            const bool bad = e < s || e > a.max_ids || lo > hi || (e - s) > (uint64_t)(hi - lo);
+            const uint32_t n = bad ? 0u : (uint32_t)(e - s);
             if (bad) raise_err(a.err, kErrInval);
-            a.seg_n[r] = n;
+            a.p.seg_n[r] = n;
             nb = cdiv32(n, kBlock);
             ng = cdiv32(nb, kGroup);
             nt = ng ? ng : 1u;
         }
         uint32_t tb, tg, tt;
-        uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
-        uint32_t xg = wg_excl_scan(ng, s_tmp, &tg);
-        uint32_t xt = wg_excl_scan(nt, s_tmp, &tt);
+        const uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
+        const uint32_t xg = wg_excl_scan(ng, s_tmp, &tg);
+        const uint32_t xt = wg_excl_scan(nt, s_tmp, &tt);
         if (r < a.nseg) {
             a.p.blk_base[r] = cb + xb;
             a.p.grp_base[r] = cg + xg;
@@ -111,8 +103,8 @@ struct BlockInfo {
     uint32_t cls, param, aux, words, first;
 };
 
-// Deltas and statistics of one block, held by one wave.  Lane l holds value
-// index l (a) and 64+l (b).  Delta index j of value j is v_j - v_{j-1}.
+// Deltas of one block, held by one wave: lane l holds value index l (a) and
+// 64+l (b); delta index j of value j is v_j - v_{j-1}.
 struct BlockRegs {
     uint32_t da, db;   // deltas (0 where there is none)
     uint32_t oa, ob;   // value - v0
@@ -123,16 +115,19 @@ struct BlockStats {
     uint32_t nk, m, v0, span, dmin, dmax, wmin;
 };
 
-__device__ __forceinline__ void load_block(const uint32_t *ids, uint32_t nk, uint32_t lo,
-                                           uint32_t hi, uint32_t lane, BlockRegs &R,
-                                           BlockStats &S, uint32_t *err) {
+__device__ __forceinline__ void fetch_block(const uint32_t *ids, uint32_t nk, uint32_t lane,
+                                            uint32_t &va, uint32_t &vb) {
+    va = lane < nk ? ids[lane] : 0u;
+    vb = lane + 64 < nk ? ids[64 + lane] : 0u;
+}
+
+__device__ __forceinline__ void analyze_block(uint32_t va, uint32_t vb, uint32_t nk, uint32_t lo,
+                                              uint32_t hi, uint32_t lane, bool want_min,
+                                              BlockRegs &R, BlockStats &S, uint32_t *err) {
     const bool ina = lane < nk, inb = lane + 64 < nk;
-    const uint32_t va = ina ? ids[lane] : 0u;
-    const uint32_t vb = inb ? ids[64 + lane] : 0u;
-    const uint32_t pa = shfl_up(va, 1);
-    uint32_t pb = shfl_up(vb, 1);
     const uint32_t a63 = readlane(va, 63);
-    if (lane == 0) pb = a63;
+    const uint32_t pa = lane_prev(va, 0u);
+    const uint32_t pb = lane_prev(vb, a63);
     R.hasa = ina && lane >= 1;
     R.hasb = inb;
     R.da = R.hasa ? va - pa : 0u;
@@ -146,17 +141,22 @@ __device__ __forceinline__ void load_block(const uint32_t *ids, uint32_t nk, uin
     const uint32_t vlast = nk <= 64 ? readlane(va, nk - 1) : readlane(vb, nk - 65);
     S.span = vlast - S.v0;
     S.dmax = wave_max(max(R.da, R.db));
-    uint32_t mn = 0xFFFFFFFFu;
-    if (R.hasa) mn = R.da;
-    if (R.hasb) mn = min(mn, R.db);
-    S.dmin = S.m ? wave_min(mn) : 0u;
+    if (want_min) {
+        uint32_t mn = 0xFFFFFFFFu;
+        if (R.hasa) mn = R.da;
+        if (R.hasb) mn = min(mn, R.db);
+        S.dmin = S.m ? wave_min(mn) : 0u;
+    } else {
+        S.dmin = 0;
+    }
     S.wmin = bitlen32(S.dmax);
     R.oa = va - S.v0;
     R.ob = vb - S.v0;
 }
 
 // Best PFOR exception width: fewest payload words with 10 E <= m; ties go
-// to the larger b.  b = wmin (no exceptions) is always allowed.
+// to the larger b.  b = wmin (no exceptions) is always allowed.  E only
+// grows as b shrinks, so the search stops at the first b with too many.
 __device__ __forceinline__ void pfor_best(const BlockRegs &R, const BlockStats &S, uint32_t &bb,
                                           uint32_t &E, uint32_t &words) {
     bb = S.wmin;
@@ -182,7 +182,9 @@ __device__ __forceinline__ bool class_valid(const BlockStats &S, uint32_t c) {
     return c == kClsPfor;
 }
 
-// Exhaustive choice: fewest payload words; ties: bit-pack < bitmap < PFOR.
+// Class and payload size of a block.  given >= 0: that class (checked);
+// otherwise plain minimal-width packing or the exhaustive choice (fewest
+// payload words; ties: bit-pack < bitmap < PFOR).
 __device__ __forceinline__ BlockInfo choose(const BlockRegs &R, const BlockStats &S, int mode,
                                             int given, uint32_t *err) {
     BlockInfo I;
@@ -191,7 +193,7 @@ __device__ __forceinline__ BlockInfo choose(const BlockRegs &R, const BlockStats
     if (given >= 0) {
         c = (uint32_t)given;
         if (!class_valid(S, c)) {
-            if (threadIdx.x % 64 == 0) raise_err(err, kErrInval);
+            if (lane_id() == 0) raise_err(err, kErrInval);
             c = 0xFFu;
         }
     } else {
@@ -284,7 +286,6 @@ struct EncArgs {
     const uint64_t *seg_off;
     const uint32_t *seg_lo;
     const uint32_t *seg_hi;
-    const uint32_t *seg_n;
     const uint8_t *classes;
     int mode;
     uint32_t nseg;
@@ -295,36 +296,97 @@ struct EncArgs {
     uint32_t *err;
 };
 
+// Tile sizes to offsets (one workgroup, after the pack pass): tile_off = exclusive prefix of tile_words; then every segment's
+// start, header and seg_byte_off.
+__device__ void finish_offsets(const EncArgs &a, uint32_t total) {
+    __shared__ uint32_t s_wt[16];
+    __shared__ unsigned long long s_carry;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t nthr = blockDim.x, nw = nthr >> 6;
+    constexpr uint32_t kPer = 8;  // tiles per thread per pass
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < total; base += nthr * kPer) {
+        uint32_t v[kPer];
+        uint32_t sum = 0;
+        const uint32_t t0 = base + tid * kPer;
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            v[k] = (t0 + k < total) ? a.p.tile_words[t0 + k] : 0u;
+            sum += v[k];
+        }
+        const uint32_t incl = wave_incl_scan(sum);
+        if (lane == 63) s_wt[w] = incl;
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (uint32_t q = 0; q < nw; ++q) {
+            wb += q < w ? s_wt[q] : 0u;
+            tot += s_wt[q];
+        }
+        uint64_t run = s_carry + wb + incl - sum;
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            if (t0 + k < total) a.p.tile_off[t0 + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (tid == 0) s_carry += tot;
+        __syncthreads();
+    }
+    const uint64_t total_words = s_carry;
+    __syncthreads();
+    const uint64_t capw = a.out_cap >> 2;
+    for (uint32_t r = tid; r < a.nseg; r += nthr) {
+        const uint64_t P = a.p.tile_off[a.p.tile_base[r]];
+        const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
+        a.seg_byte_off[r] = Sr;
+        const uint64_t sw = Sr >> 2;
+        if (sw + 4 <= capw) {
+            a.out[sw + 0] = a.p.seg_n[r];
+            a.out[sw + 1] = a.seg_lo[r];
+            a.out[sw + 2] = a.seg_hi[r];
+            a.out[sw + 3] = kMagic;
+        }
+    }
+    if (tid == 0) {
+        const uint64_t end = 16ull * a.nseg + 8ull * a.p.blk_base[a.nseg] + 4ull * a.p.grp_base[a.nseg] +
+                             4ull * total_words;
+        a.seg_byte_off[a.nseg] = end;
+        if (end > a.out_cap) raise_err(a.err, kErrCapacity);
+    }
+}
+
+// Pack pass: analyse, choose and pack every block of a tile into the tile's
+// slot (directory words first, then the payloads in block order).
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_encode(EncArgs a) {
+__global__ __launch_bounds__(WAVES * 64) void k_enc_pack(EncArgs a) {
     constexpr int BPW = (int)kGroup / WAVES;  // blocks per wave per tile
-    __shared__ uint32_t s_t, s_r;
-    __shared__ uint64_t s_X, s_P;
     __shared__ BlockInfo s_info[kGroup];
     __shared__ uint32_t s_pref[kGroup];
     __shared__ uint32_t s_buf[WAVES][128];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t total = a.p.tile_base[a.nseg];
 
-    for (;;) {
-        if (tid == 0) {
-            const uint32_t t = atomicAdd(a.p.counter, 1u);
-            s_t = t;
-            s_r = t < total ? upper_bound_m1(a.p.tile_base, a.nseg, t) : 0u;
-        }
-        __syncthreads();
-        const uint32_t t = s_t, r = s_r;
-        if (t >= total) break;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
         const uint32_t g = t - a.p.tile_base[r];
         const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
-        const uint32_t ng = a.p.grp_base[r + 1] - a.p.grp_base[r];
-        const uint32_t n = a.seg_n[r];
+        const uint32_t n = a.p.seg_n[r];
         const uint32_t k0 = g * kGroup;
         const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
         const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
         const uint32_t *ids = a.ids + a.seg_off[r];
+        uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
 
-        // phase A: analyse this wave's blocks
+        // issue every load of this wave's blocks first
+        uint32_t va[BPW], vb[BPW];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const uint32_t kk = w + (uint32_t)i * WAVES;
+            const uint32_t k = k0 + kk;
+            const uint32_t nk = kk < nblk ? min(kBlock, n - k * kBlock) : 0u;
+            fetch_block(ids + (uint64_t)k * kBlock, nk, lane, va[i], vb[i]);
+        }
         BlockRegs R[BPW];
         BlockStats S[BPW];
         BlockInfo I[BPW];
@@ -334,7 +396,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_encode(EncArgs a) {
             if (kk < nblk) {
                 const uint32_t k = k0 + kk;
                 const uint32_t nk = min(kBlock, n - k * kBlock);
-                load_block(ids + (uint64_t)k * kBlock, nk, lo, hi, lane, R[i], S[i], a.err);
+                analyze_block(va[i], vb[i], nk, lo, hi, lane, false, R[i], S[i], a.err);
                 const int given = a.classes ? (int)a.classes[a.p.blk_base[r] + k] : -1;
                 I[i] = choose(R[i], S[i], a.mode, given, a.err);
                 I[i].first = S[i].v0 - lo;
@@ -342,98 +404,64 @@ __global__ __launch_bounds__(WAVES * 64) void k_encode(EncArgs a) {
             }
         }
         __syncthreads();
-
-        // phase B: tile offsets (wave 0)
         if (w == 0) {
             const uint32_t wv = lane < nblk ? s_info[lane].words : 0u;
             const uint32_t incl = wave_incl_scan(wv);
             if (lane < kGroup) s_pref[lane] = incl - wv;
-            const uint64_t A = (uint64_t)readlane(incl, 63);
-            uint64_t X = 0;
-            if (t == 0) {
-                if (lane == 0) st_rel64(&a.p.status[0], kFlagIncl | A);
-            } else {
-                if (lane == 0) st_rel64(&a.p.status[t], kFlagAgg | A);
-                // windowed look-back over up to 64 predecessors at a time
-                int64_t base = (int64_t)t;
-                for (;;) {
-                    const int64_t idx = base - 1 - (int64_t)lane;
-                    uint64_t st = idx >= 0 ? ld_acq64(&a.p.status[idx]) : kFlagIncl;
-                    const uint64_t flag = st >> 62;
-                    const uint64_t incl_m = ballot(flag == 2);
-                    const uint32_t stop = incl_m ? (uint32_t)__builtin_ctzll(incl_m) : 64u;
-                    const uint64_t upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1ull);
-                    if (ballot(flag == 0) & upto) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    const uint64_t v = (lane <= stop) ? (st & kValMask) : 0ull;
-                    const uint64_t sum = wave_sum64(v);
-                    X += sum;
-                    if (stop < 64) break;
-                    base -= 64;
-                }
-                if (lane == 0) st_rel64(&a.p.status[t], kFlagIncl | (X + A));
-            }
-            uint64_t P;
-            if (g == 0) {
-                P = X;
-                if (lane == 0) st_rel64(&a.p.seg_pw[r], kReady | P);
-            } else {
-                uint64_t v;
-                for (;;) {
-                    v = ld_acq64(&a.p.seg_pw[r]);
-                    if (v & kReady) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                P = v & ~kReady;
-            }
-            if (lane == 0) {
-                s_X = X;
-                s_P = P;
-                // the last tile closes the batch
-                if (t + 1 == total) {
-                    const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
-                    a.seg_byte_off[a.nseg] = Sr + 16ull + 8ull * nb + 4ull * ng + 4ull * (X - P + A);
-                }
-            }
+            if (lane == 63) a.p.tile_words[t] = incl;
+        }
+        if (tid < 2 * nblk) {
+            const BlockInfo &bi = s_info[tid >> 1];
+            slot[tid] = (tid & 1) ? (bi.cls | (bi.param << 8) | (bi.aux << 16)) : bi.first;
         }
         __syncthreads();
-
-        // phase C: write header, directory, group entry and payloads
-        const uint64_t X = s_X, P = s_P;
-        const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
-        const uint64_t sw = Sr >> 2;                        // segment start (words)
-        const uint64_t pwb = sw + 4 + 2ull * nb + ng + (X - P);  // this tile's payload start
-        const uint32_t Atile = nblk ? s_pref[nblk - 1] + s_info[nblk - 1].words : 0u;
-        const uint64_t capw = a.out_cap >> 2;
-        const bool fits = (sw + 4 + 2ull * nb + ng <= capw) && (pwb + Atile <= capw);
-        if (!fits) {
-            if (tid == 0) raise_err(a.err, kErrCapacity);
-        } else {
-            if (g == 0 && tid < 4) {
-                const uint32_t hv = tid == 0 ? n : tid == 1 ? lo : tid == 2 ? hi : kMagic;
-                a.out[sw + tid] = hv;
-                if (tid == 0) a.seg_byte_off[r] = Sr;
-            }
-            if (nblk && tid == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)(X - P);
-            if (tid < 2 * nblk) {
-                const BlockInfo &bi = s_info[tid >> 1];
-                const uint32_t v = (tid & 1) ? (bi.cls | (bi.param << 8) | (bi.aux << 16)) : bi.first;
-                a.out[sw + 4 + 2ull * (k0 + (tid >> 1)) + (tid & 1)] = v;
-            }
 #pragma unroll
-            for (int i = 0; i < BPW; ++i) {
-                const uint32_t kk = w + (uint32_t)i * WAVES;
-                if (kk < nblk && I[i].words) {
-                    pack_block(s_buf[w], I[i], R[i], S[i], lane);
-                    uint32_t *dst = a.out + pwb + s_pref[kk];
-                    for (uint32_t q = lane; q < I[i].words; q += 64) dst[q] = s_buf[w][q];
-                    __builtin_amdgcn_wave_barrier();
-                }
+        for (int i = 0; i < BPW; ++i) {
+            const uint32_t kk = w + (uint32_t)i * WAVES;
+            if (kk < nblk && I[i].words) {
+                pack_block(s_buf[w], I[i], R[i], S[i], lane);
+                uint32_t *dst = slot + kSlotDirWords + s_pref[kk];
+                if (lane < I[i].words) dst[lane] = s_buf[w][lane];
+                if (lane + 64 < I[i].words) dst[lane + 64] = s_buf[w][lane + 64];
+                __builtin_amdgcn_wave_barrier();
             }
         }
         __syncthreads();
+    }
+}
+
+// One workgroup: tile sizes -> offsets, segment starts and headers.
+__global__ __launch_bounds__(1024) void k_enc_scan(EncArgs a) {
+    finish_offsets(a, a.p.tile_base[a.nseg]);
+}
+
+// Place pass: copy every tile's directory entries, group-table entry and
+// payload words from its slot to the final position.
+__global__ __launch_bounds__(256) void k_enc_place(EncArgs a) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t total = a.p.tile_base[a.nseg];
+    const uint64_t capw = a.out_cap >> 2;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
+        const uint32_t g = t - a.p.tile_base[r];
+        const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
+        const uint32_t ng = a.p.grp_base[r + 1] - a.p.grp_base[r];
+        const uint32_t k0 = g * kGroup;
+        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
+        if (!nblk) continue;
+        const uint64_t sw = a.seg_byte_off[r] >> 2;
+        const uint64_t rel = a.p.tile_off[t] - a.p.tile_off[a.p.tile_base[r]];
+        const uint32_t A = a.p.tile_words[t];
+        const uint64_t pwb = sw + 4 + 2ull * nb + ng + rel;
+        const uint64_t dwb = sw + 4 + 2ull * k0;
+        if (pwb + A > capw || sw + 4 + 2ull * nb + ng > capw) {
+            if (tid == 0) raise_err(a.err, kErrCapacity);
+            continue;
+        }
+        const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+        if (tid < 2 * nblk) a.out[dwb + tid] = slot[tid];
+        if (tid == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)rel;
+        for (uint32_t q = tid; q < A; q += blockDim.x) a.out[pwb + q] = slot[kSlotDirWords + q];
     }
 }
 
@@ -445,7 +473,6 @@ struct SelArgs {
     const uint32_t *seg_lo;
     const uint32_t *seg_hi;
     const int32_t *seg_level;
-    const uint32_t *seg_n;
     uint32_t nseg;
     int mode;
     uint8_t *classes;
@@ -493,13 +520,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
         const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
         const uint32_t g = t - a.p.tile_base[r];
         const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
-        const uint32_t n = a.seg_n[r];
+        const uint32_t n = a.p.seg_n[r];
         const uint32_t k0 = g * kGroup;
         const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
         const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
         const uint32_t *ids = a.ids + a.seg_off[r];
         const int32_t level = a.seg_level ? a.seg_level[r] : 0;
         const uint32_t gb = a.p.blk_base[r] + k0;
+        uint32_t va[BPW], vb[BPW];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const uint32_t kk = w + (uint32_t)i * WAVES;
+            const uint32_t k = k0 + kk;
+            const uint32_t nk = kk < nblk ? min(kBlock, n - k * kBlock) : 0u;
+            fetch_block(ids + (uint64_t)k * kBlock, nk, lane, va[i], vb[i]);
+        }
 #pragma unroll
         for (int i = 0; i < BPW; ++i) {
             const uint32_t kk = w + (uint32_t)i * WAVES;
@@ -508,8 +543,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
                 const uint32_t nk = min(kBlock, n - k * kBlock);
                 BlockRegs R;
                 BlockStats S;
-                load_block(ids + (uint64_t)k * kBlock, nk, lo, hi, lane, R, S, a.err);
-                if (a.feat || learned) {
+                const bool feats = a.feat || learned;
+                analyze_block(va[i], vb[i], nk, lo, hi, lane, feats, R, S, a.err);
+                if (feats) {
                     float f[8];
                     block_features(S, n, level, f);
                     if (lane < 8) {
@@ -542,11 +578,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
         for (uint32_t o = tid; o < kGroup * kH; o += nthr) {
             const uint32_t bi = o / kH, u = o % kH;
             if (bi < nblk) {
-                float z = a.params[kB1 + u];
                 float acc = 0.0f;
 #pragma unroll
                 for (int i = 0; i < kIn; ++i) acc += (float)a.w16[kW1 + u * kIn + i] * s_x[bi][i];
-                z = acc + z;
+                const float z = acc + a.params[kB1 + u];
                 s_h1[bi][u] = (float)(_Float16)fmaxf(z, 0.0f);
             }
         }
@@ -637,7 +672,7 @@ __global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
         }
         uint32_t tt;
         const uint32_t xt = wg_excl_scan(ng, s_tmp, &tt);
-        // 64-bit exclusive scan of n (two-level: waves then workgroup)
+        // 64-bit exclusive scan of n (waves, then the workgroup)
         uint64_t incl = n;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -683,18 +718,25 @@ struct DecArgs {
     uint32_t *err;
 };
 
+// w-bit field at bit pos of the staged words (funnel shift of two words).
 __device__ __forceinline__ uint32_t get_field(const uint32_t *buf, uint32_t pos, uint32_t w) {
-    if (w == 0) return 0u;
     const uint32_t wi = pos >> 5, sh = pos & 31;
-    uint32_t v = buf[wi] >> sh;
-    if (sh + w > 32) v |= buf[wi + 1] << (32 - sh);
+    const uint32_t v = __builtin_amdgcn_alignbit(buf[wi + 1], buf[wi], sh);
     return w >= 32 ? v : (v & ((1u << w) - 1u));
+}
+
+__device__ __forceinline__ uint32_t block_words(uint32_t cls, uint32_t param, uint32_t aux, uint32_t m) {
+    if (cls == kClsBitmap) return cdiv32(aux, 32);
+    if (cls <= 33) return cdiv32(m * (cls - 1), 32);
+    const uint32_t E = aux & 0xFFu;
+    return cdiv32(m * param, 32) + cdiv32(E, 4) + cdiv32(E * (aux >> 8), 32);
 }
 
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
+    constexpr int BPW = (int)kGroup / WAVES;
     __shared__ uint32_t s_cls[kGroup], s_param[kGroup], s_aux[kGroup], s_first[kGroup + 1];
-    __shared__ uint32_t s_off[kGroup];
+    __shared__ uint32_t s_off[kGroup], s_words[kGroup];
     __shared__ uint32_t s_ok;
     __shared__ uint32_t s_buf[WAVES][132];
     __shared__ uint32_t s_val[WAVES][128];
@@ -726,21 +768,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
                     const uint32_t nk = min(kBlock, n - k * kBlock), m = nk - 1;
                     if (cls == kClsBitmap) {
                         bad = param != 0 || aux > kBitmapMaxSpan;
-                        words = cdiv32(aux, 32);
                     } else if (cls <= 33) {
                         bad = param != cls - 1 || aux != 0;
-                        words = cdiv32(m * (cls - 1), 32);
                     } else if (cls == kClsPfor) {
                         const uint32_t E = aux & 0xFFu, h = aux >> 8;
                         bad = param > 32 || param + h > 32 || 10 * E > m;
-                        words = bad ? 0u : cdiv32(m * param, 32) + cdiv32(E, 4) + cdiv32(E * h, 32);
-                        bad |= words > kBlock;
                     } else {
                         bad = true;
                     }
+                    words = bad ? 0u : block_words(cls, param, aux, m);
+                    bad |= words > kBlock;
                     s_cls[lane] = cls;
                     s_param[lane] = param;
                     s_aux[lane] = aux;
+                    s_words[lane] = words;
                     // first value inside [lo, hi)
                     bad |= (uint64_t)lo + e0 >= (uint64_t)hi;
                 }
@@ -761,20 +802,28 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
         __syncthreads();
         if (s_ok) {
             const uint32_t *pay = seg + metaw;
-            for (uint32_t kk = w; kk < nblk; kk += WAVES) {
+            // issue the payload loads of all of this wave's blocks first
+            uint32_t pa[BPW], pb[BPW];
+#pragma unroll
+            for (int i = 0; i < BPW; ++i) {
+                const uint32_t kk = w + (uint32_t)i * WAVES;
+                const uint32_t words = kk < nblk ? s_words[kk] : 0u;
+                const uint32_t *src = pay + (kk < nblk ? s_off[kk] : 0u);
+                pa[i] = lane < words ? src[lane] : 0u;
+                pb[i] = lane + 64 < words ? src[lane + 64] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < BPW; ++i) {
+                const uint32_t kk = w + (uint32_t)i * WAVES;
+                if (kk >= nblk) continue;
                 const uint32_t k = k0 + kk;
                 const uint32_t nk = min(kBlock, n - k * kBlock), m = nk - 1;
                 const uint32_t cls = s_cls[kk], param = s_param[kk], aux = s_aux[kk];
                 const uint32_t v0 = lo + s_first[kk];
-                uint32_t words;
-                if (cls == kClsBitmap) words = cdiv32(aux, 32);
-                else if (cls <= 33) words = cdiv32(m * (cls - 1), 32);
-                else words = cdiv32(m * param, 32) + cdiv32(aux & 0xFFu, 4) + cdiv32((aux & 0xFFu) * (aux >> 8), 32);
                 uint32_t *buf = s_buf[w];
                 uint32_t *val = s_val[w];
-                const uint32_t *src = pay + s_off[kk];
-                buf[lane] = lane < words ? src[lane] : 0u;
-                buf[lane + 64] = lane + 64 < words ? src[lane + 64] : 0u;
+                buf[lane] = pa[i];
+                buf[lane + 64] = pb[i];
                 if (lane < 4) buf[128 + lane] = 0u;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -782,54 +831,37 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
                 uint32_t xa = 0, xb = 0;  // decoded values
                 const bool ina = lane < nk, inb = lane + 64 < nk;
                 if (cls == kClsBitmap) {
-                    const uint32_t ca = popc64(buf[lane]), cb = popc64(buf[lane + 64]);
-                    const uint32_t ia = wave_incl_scan(ca);
-                    const uint32_t ta = readlane(ia, 63);
-                    const uint32_t ib = wave_incl_scan(cb) + ta;
-                    const uint32_t tot = readlane(ib, 63);
-                    // bits beyond the span must be clear
-                    const uint32_t tailw = aux >> 5, tailb = aux & 31;
-                    const bool tail_bad = (tailb && (lane == tailw) && (buf[lane] >> tailb)) ||
-                                          (tailb && (lane + 64 == tailw) && (buf[lane + 64] >> tailb));
-                    bad |= tail_bad;
-                    const bool cnt_bad = tot != m;
-                    val[lane] = 0u;
-                    val[lane + 64] = 0u;
-                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    if (!cnt_bad) {
-                        if (lane == 0) val[0] = v0;
-                        uint32_t x = buf[lane], j = 1 + ia - ca;
-                        while (x) {
-                            const uint32_t p = __builtin_ctz(x);
-                            x &= x - 1;
-                            if (j < 128) val[j] = v0 + 32 * lane + p + 1;
-                            ++j;
-                        }
-                        x = buf[lane + 64];
-                        j = 1 + ib - cb;
-                        while (x) {
-                            const uint32_t p = __builtin_ctz(x);
-                            x &= x - 1;
-                            if (j < 128) val[j] = v0 + 32 * (lane + 64) + p + 1;
-                            ++j;
-                        }
+                    // 64 candidate positions per step; set bits are ranked
+                    // with a ballot and written to their output slots
+                    const uint32_t nch = (aux + 63) >> 6;
+                    uint32_t cnt = 1;
+                    if (lane == 0) val[0] = v0;
+                    for (uint32_t c = 0; c < nch; ++c) {
+                        const uint32_t word = lane < 32 ? buf[2 * c] : buf[2 * c + 1];
+                        const bool set = (word >> (lane & 31)) & 1u;
+                        const uint64_t mk = ballot(set);
+                        const uint32_t rank = popc64(mk & lanemask_lt());
+                        if (set && cnt + rank < 128) val[cnt + rank] = v0 + 64 * c + lane + 1;
+                        cnt += popc64(mk);
                     }
-                    bad |= cnt_bad;
+                    // bits beyond the span must be clear, and there must be m of them
+                    const uint32_t tailw = aux >> 5, tailb = aux & 31;
+                    bad |= tailb && lane == 0 && (buf[tailw] >> tailb) != 0u;
+                    bad |= cnt - 1 != m;
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     xa = val[lane];
                     xb = val[lane + 64];
-                    // highest set position: the last value, checked in 64 bits
-                    const uint32_t ta_ = buf[lane] ? 32 * lane + 32 - __builtin_clz(buf[lane]) : 0u;
-                    const uint32_t tb_ = buf[lane + 64] ? 32 * (lane + 64) + 32 - __builtin_clz(buf[lane + 64]) : 0u;
-                    const uint32_t top = wave_max(max(ta_, tb_));
-                    bad |= (uint64_t)v0 + top >= (uint64_t)hi;
+                    // the last value, checked in 64 bits (no wrap)
+                    if (cnt - 1 == m) {
+                        const uint32_t lastv = m ? (nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65)) : v0;
+                        bad |= (uint64_t)v0 + (lastv - v0) >= (uint64_t)hi;
+                    }
                 } else {
                     const uint32_t b = cls <= 33 ? cls - 1 : param;
                     const uint32_t ja = lane, jb = 64 + lane;
-                    uint32_t da = (ina && ja >= 1) ? get_field(buf, (ja - 1) * b, b) : 0u;
-                    uint32_t db = inb ? get_field(buf, (jb - 1) * b, b) : 0u;
+                    uint32_t da = (ina && ja >= 1 && b) ? get_field(buf, (ja - 1) * b, b) : 0u;
+                    uint32_t db = (inb && b) ? get_field(buf, (jb - 1) * b, b) : 0u;
                     if (cls == kClsPfor) {
                         const uint32_t E = aux & 0xFFu, h = aux >> 8;
                         const uint32_t lw = cdiv32(m * b, 32), qw = cdiv32(E, 4);
@@ -840,10 +872,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
                         uint32_t p = 0;
                         if (lane < E) {
                             p = (buf[lw + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu;
-                            const uint32_t hv = get_field(buf + lw + qw, lane * h, h);
+                            const uint32_t hv = h ? get_field(buf + lw + qw, lane * h, h) : 0u;
                             if (p < m) val[p + 1] = b >= 32 ? 0u : (hv << b);
                         }
-                        const uint32_t pp = shfl_up(p, 1);
+                        const uint32_t pp = lane_prev(p, 0u);
                         bad |= lane < E && (p >= m || (lane > 0 && p <= pp));
                         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                         __builtin_amdgcn_wave_barrier();
@@ -857,11 +889,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
                     xa = v0 + sa;
                     xb = v0 + sb;
                     // a wrap shows as a decrease against the previous value
-                    const uint32_t pa = shfl_up(xa, 1);
-                    uint32_t pb = shfl_up(xb, 1);
                     const uint32_t a63 = readlane(xa, 63);
-                    if (lane == 0) pb = a63;
-                    bad |= (ina && lane >= 1 && xa <= pa) || (inb && xb <= pb);
+                    const uint32_t prva = lane_prev(xa, 0u);
+                    const uint32_t prvb = lane_prev(xb, a63);
+                    bad |= (ina && lane >= 1 && xa <= prva) || (inb && xb <= prvb);
                 }
                 // last value below hi and below the next block's first value
                 const uint32_t last = nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65);
@@ -912,6 +943,7 @@ static inline uint32_t persistent_grid(const bfsc_ctx *ctx, uint32_t per_cu, uin
 
 int launch_plan_prep(const bfsc_batch *b, const Plan &p, uint32_t *err, bool zero_status,
                      hipStream_t s) {
+    (void)zero_status;
     PlanArgs a;
     a.seg_off = b->seg_off;
     a.seg_lo = b->seg_lo;
@@ -919,15 +951,8 @@ int launch_plan_prep(const bfsc_batch *b, const Plan &p, uint32_t *err, bool zer
     a.nseg = b->nseg;
     a.max_ids = b->max_ids;
     a.p = p;
-    a.seg_n = p.seg_n;
     a.err = err;
-    a.zero_status = zero_status ? 1 : 0;
-    uint32_t grid = 1;
-    if (zero_status) {
-        uint64_t need = ((uint64_t)p.max_tiles + 1023) / 1024;
-        grid = (uint32_t)(need < 64 ? (need ? need : 1) : 64);
-    }
-    hipLaunchKernelGGL(k_plan_prep, dim3(grid), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_plan_prep, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -939,7 +964,6 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     a.seg_off = b->seg_off;
     a.seg_lo = b->seg_lo;
     a.seg_hi = b->seg_hi;
-    a.seg_n = p.seg_n;
     a.classes = classes;
     a.mode = mode;
     a.nseg = b->nseg;
@@ -952,13 +976,17 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     const uint32_t grid = persistent_grid(ctx, ctx->tune.enc_wg_per_cu, p.max_tiles);
     const int slot = timing_begin(ctx, BFSC_OP_ENCODE, s);
     switch (waves) {
-        case 1: hipLaunchKernelGGL(k_encode<1>, dim3(grid), dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_encode<2>, dim3(grid), dim3(128), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_encode<8>, dim3(grid), dim3(512), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(k_encode<16>, dim3(grid), dim3(1024), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_encode<4>, dim3(grid), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_enc_pack<1>, dim3(grid), dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_enc_pack<2>, dim3(grid), dim3(128), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(k_enc_pack<8>, dim3(grid), dim3(512), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_enc_pack<16>, dim3(grid), dim3(1024), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_enc_pack<4>, dim3(grid), dim3(256), 0, s, a); break;
     }
     timing_end(ctx, slot, s);
+    hipLaunchKernelGGL(k_enc_scan, dim3(1), dim3(1024), 0, s, a);
+    const int slot2 = timing_begin(ctx, BFSC_OP_ENCODE_PLACE, s);
+    hipLaunchKernelGGL(k_enc_place, dim3(persistent_grid(ctx, 8, p.max_tiles)), dim3(256), 0, s, a);
+    timing_end(ctx, slot2, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -970,7 +998,6 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
     a.seg_lo = b->seg_lo;
     a.seg_hi = b->seg_hi;
     a.seg_level = b->seg_level;
-    a.seg_n = p.seg_n;
     a.nseg = b->nseg;
     a.mode = mode;
     a.classes = classes;

@@ -22,12 +22,6 @@ constexpr uint32_t kErrInval = 1u;
 constexpr uint32_t kErrCapacity = 2u;
 constexpr uint32_t kErrCorrupt = 4u;
 
-// Look-back status word: flag in the top two bits, value in the low 62.
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagIncl = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-constexpr uint64_t kReady = 1ull << 63;
-
 // MLP shape 8 -> 64 -> 64 -> 35.
 constexpr int kIn = 8, kH = 64, kOut = 35;
 constexpr int kW1 = 0, kB1 = kW1 + kH * kIn, kW2 = kB1 + kH, kB2 = kW2 + kH * kH;
@@ -63,17 +57,54 @@ __device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return __shfl
 __device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int d) { return __shfl_xor(v, d, 64); }
 __device__ __forceinline__ uint32_t shfl(uint32_t v, int src) { return __shfl(v, src, 64); }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, shfl_xor(v, d));
-    return readfirst(v);
+// DPP lane movement (GFX9 controls): row_shr:n = 0x110+n within rows of 16,
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143, wave_shl:1 = 0x130,
+// wave_shr:1 = 0x138.  Lanes whose source is outside the pattern, or whose
+// row is masked off, receive `old`.
+template <int CTRL, int ROWMASK = 0xF, int BANKMASK = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, BANKMASK, false);
 }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, shfl_xor(v, d));
-    return readfirst(v);
+// Value of lane-1 (lane 0 receives `first`).
+__device__ __forceinline__ uint32_t lane_prev(uint32_t v, uint32_t first) { return dpp<0x138>(first, v); }
+// Value of lane+1 (lane 63 receives `last`).
+__device__ __forceinline__ uint32_t lane_next(uint32_t v, uint32_t last) { return dpp<0x130>(last, v); }
+
+// Inclusive scans over the 64 lanes: Hillis-Steele inside rows of 16, then
+// the row totals are carried across rows with the two broadcasts.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += dpp<0x111>(0u, v);
+    v += dpp<0x112>(0u, v);
+    v += dpp<0x114>(0u, v);
+    v += dpp<0x118>(0u, v);
+    v += dpp<0x142, 0xA>(0u, v);
+    v += dpp<0x143, 0xC>(0u, v);
+    return v;
 }
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    v = max(v, dpp<0x111>(0u, v));
+    v = max(v, dpp<0x112>(0u, v));
+    v = max(v, dpp<0x114>(0u, v));
+    v = max(v, dpp<0x118>(0u, v));
+    v = max(v, dpp<0x142, 0xA>(0u, v));
+    v = max(v, dpp<0x143, 0xC>(0u, v));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_min(uint32_t v) {
+    v = min(v, dpp<0x111>(0xFFFFFFFFu, v));
+    v = min(v, dpp<0x112>(0xFFFFFFFFu, v));
+    v = min(v, dpp<0x114>(0xFFFFFFFFu, v));
+    v = min(v, dpp<0x118>(0xFFFFFFFFu, v));
+    v = min(v, dpp<0x142, 0xA>(0xFFFFFFFFu, v));
+    v = min(v, dpp<0x143, 0xC>(0xFFFFFFFFu, v));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) { return readlane(wave_incl_max(v), 63); }
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) { return readlane(wave_incl_min(v), 63); }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 #pragma unroll
@@ -84,22 +115,7 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
     return ((uint64_t)readfirst((uint32_t)(v >> 32)) << 32) | readfirst((uint32_t)v);
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += shfl_xor(v, d);
-    return readfirst(v);
-}
-
-// Inclusive prefix sum over the 64 lanes.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    uint32_t l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = shfl_up(v, d);
-        if (l >= (uint32_t)d) v += t;
-    }
-    return v;
-}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return readlane(wave_incl_scan(v), 63); }
 
 __device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32u - (uint32_t)__clz(x) : 0u; }
 
@@ -107,14 +123,6 @@ __device__ __forceinline__ uint32_t cdiv32(uint32_t a, uint32_t b) { return (a +
 
 __device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
     __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t ld_acq64(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void st_rel64(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Index of the last entry of base[0..n] (non-decreasing) that is <= t.
@@ -131,15 +139,22 @@ __device__ __forceinline__ uint32_t upper_bound_m1(const uint32_t *base, uint32_
 
 // Per-batch tiling computed by the prep kernel into the workspace.  A tile is
 // one group of up to 16 blocks of one segment; an empty segment gets one
-// tile without blocks (so that someone writes its header).
+// tile without blocks (so that someone writes its header).  The encoder packs
+// every tile into a private slot (directory words, then payload words), then
+// one workgroup turns the tile sizes into output offsets, then the slots are
+// placed: no workgroup ever waits for another.
+constexpr uint32_t kSlotDirWords = 2 * kGroup;
+constexpr uint32_t kSlotWords = kSlotDirWords + kGroup * kBlock;
+
 struct Plan {
     uint32_t *blk_base;   // [nseg+1] first global block of each segment
     uint32_t *grp_base;   // [nseg+1] first global group
     uint32_t *tile_base;  // [nseg+1] first tile
-    uint64_t *seg_pw;     // [nseg]   payload-word base of each segment (kReady when set)
-    uint64_t *status;     // [max_tiles] look-back status
-    uint32_t *counter;    // [4]      tile ticket, spare
     uint32_t *seg_n;      // [nseg]   IDs per segment (0 for a rejected segment)
+    uint32_t *counter;    // [4]      [0]: workgroups done with the pack pass
+    uint32_t *tile_words; // [max_tiles] payload words per tile
+    uint64_t *tile_off;   // [max_tiles] exclusive prefix of tile_words
+    uint32_t *slots;      // [max_tiles][kSlotWords] (encode only)
     uint32_t max_tiles;
 };
 
@@ -149,8 +164,10 @@ __host__ __device__ inline uint64_t plan_max_tiles(uint64_t max_ids, uint32_t ns
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Carves a Plan out of a workspace; returns the bytes used.
-__host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32_t nseg, Plan *p) {
+// Carves a Plan out of a workspace; returns the bytes used.  Slots are only
+// laid out (and only counted) for the encoder.
+__host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32_t nseg, bool slots,
+                                              Plan *p) {
     char *b = (char *)ws;
     size_t off = 0;
     size_t n1 = (size_t)nseg + 1;
@@ -161,14 +178,16 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     off = align256(off + n1 * 4);
     if (p) p->tile_base = (uint32_t *)(b + off);
     off = align256(off + n1 * 4);
-    if (p) p->seg_pw = (uint64_t *)(b + off);
-    off = align256(off + n1 * 8);
-    if (p) p->status = (uint64_t *)(b + off);
-    off = align256(off + mt * 8);
-    if (p) p->counter = (uint32_t *)(b + off);
-    off = align256(off + 16);
     if (p) p->seg_n = (uint32_t *)(b + off);
     off = align256(off + n1 * 4);
+    if (p) p->counter = (uint32_t *)(b + off);
+    off = align256(off + 16);
+    if (p) p->tile_words = (uint32_t *)(b + off);
+    off = align256(off + mt * 4);
+    if (p) p->tile_off = (uint64_t *)(b + off);
+    off = align256(off + mt * 8);
+    if (p) p->slots = slots ? (uint32_t *)(b + off) : nullptr;
+    if (slots) off = align256(off + mt * (size_t)kSlotWords * 4);
     if (p) p->max_tiles = (uint32_t)mt;
     return off;
 }
@@ -222,7 +241,9 @@ int launch_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *le
                     hipStream_t s);
 int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *frontier,
                      const uint32_t *frontier_len, int32_t *level, int32_t *parent, uint32_t *next,
-                     uint32_t *next_len, void *ws, hipStream_t s);
+                     uint32_t *next_len, void *ws, hipStream_t s,
+                     const int32_t *cur_level_dev = nullptr);
+int launch_level_inc(int32_t *level_dev, hipStream_t s);
 size_t mlp_ws_bytes(uint32_t n);
 int launch_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, hipStream_t s);
 int launch_mlp_grad(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n, float *grads,

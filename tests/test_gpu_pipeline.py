@@ -1,0 +1,92 @@
+"""GPU parity of the per-level pipeline (BFS level -> partition -> choose ->
+encode -> decode), replayed from captured HIP graphs and launched eagerly:
+every level of every replay is checked against the oracle, with host work
+and synchronisation between replays; and the autotuner's choice keeps the
+streams byte-exact."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+from gpu_util import gpu_encode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1704_00513_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def run_pipeline(ctx, g, root, bounds, use_graph, mode=1):
+    import paper_1704_00513_amd as P
+    dg = P.DeviceGraph.from_host(g)
+    pipe = P.Pipeline(ctx, dg, bounds, mode=mode, use_graph=use_graph)
+    olevel, _, depth = oracle.bfs(g, root)
+    pipe.start(root)
+    L = 0
+    n = 1
+    while n:
+        n = pipe.step()
+        assert ctx.sync_status() == 0
+        got = pipe.last_step()
+        front = oracle.frontier(olevel, L)
+        np.testing.assert_array_equal(got["frontier"], front)
+        ob = oracle.batch_from_frontier(front, bounds, L)
+        np.testing.assert_array_equal(got["seg_off"], ob.seg_off)
+        want, want_off = oracle.encode(ob, mode=mode)
+        np.testing.assert_array_equal(got["seg_byte_off"], want_off)
+        np.testing.assert_array_equal(got["stream"], want)
+        np.testing.assert_array_equal(got["decoded"], front)
+        np.testing.assert_array_equal(got["decoded_off"], ob.seg_off)
+        L += 1
+        assert L <= depth + 1
+    assert L == depth + 1
+    lv, par = pipe.levels()
+    np.testing.assert_array_equal(lv, olevel)
+    assert oracle.bfs_check(g, root, lv, par) == 0
+    pipe.close()
+    return L
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("kind,scale,nseg,zipf", [(inputs.RMAT, 14, 16, False),
+                                                  (inputs.RMAT, 16, 64, True),
+                                                  (inputs.UNIFORM, 15, 16, False)])
+def test_pipeline_levels_exact(ctx, use_graph, kind, scale, nseg, zipf):
+    g = inputs.graph(kind, scale, 16, 1)
+    bounds = inputs.bounds_zipf(g.n_vertices, nseg, 1)[0] if zipf else inputs.bounds_equal(g.n_vertices, nseg)
+    for root in inputs.roots(g, 2, 1):
+        print("pipeline graph=%s kind=%d scale=%d nseg=%d root=%d" % (use_graph, kind, scale, nseg, root),
+              flush=True)
+        run_pipeline(ctx, g, int(root), bounds, use_graph)
+
+
+def test_pipeline_plain_mode(ctx):
+    g = inputs.graph(inputs.RMAT, 14, 16, 2)
+    root = int(inputs.roots(g, 1, 2)[0])
+    print("pipeline plain", flush=True)
+    run_pipeline(ctx, g, root, np.array([0, g.n_vertices], np.uint32), True, mode=0)
+
+
+def test_autotune_keeps_streams_exact(ctx):
+    import paper_1704_00513_amd as P
+    from gpu_util import device_batch
+    g = inputs.graph(inputs.RMAT, 16, 16, 1)
+    level, _, depth = oracle.bfs(g, int(inputs.roots(g, 1, 1)[0]))
+    bs = [oracle.batch_from_frontier(oracle.frontier(level, L), inputs.bounds_equal(g.n_vertices, 16), L)
+          for L in range(depth + 1)]
+    b = oracle.concat_batches(bs)
+    before = ctx.get_tune()
+    tuned = ctx.autotune(device_batch(b))
+    print("autotune", before, "->", tuned, flush=True)
+    assert tuned["enc_waves"] in (1, 2, 4, 8, 16) and tuned["dec_waves"] in (1, 2, 4, 8, 16)
+    want, want_off = oracle.encode(b)
+    st, got, off = gpu_encode(ctx, b)
+    assert st == 0
+    np.testing.assert_array_equal(got, want)
+    ctx.set_tune(**before)
