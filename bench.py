@@ -135,6 +135,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a copy-like kernel of known size (counter calibration)")
+    ap.add_argument("--tune", action="append", default=[],
+                    help="launch shape override, e.g. --tune enc_waves=8 --tune enc_pack=1")
+    ap.add_argument("--autotune", action="store_true", help="measure launch shapes on the batch first")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -170,6 +175,10 @@ def main():
         ctx.encode(b, out, sbo, mode=mode, ws=ws_e)
         ctx.decode(out, sbo, b.nseg, N, dec, doff, ws=ws_d)
 
+    if args.tune:
+        ctx.set_tune(**{k: int(v) for k, v in (x.split("=", 1) for x in args.tune)})
+    if args.autotune:
+        log("autotune:", ctx.autotune(b))
     for _ in range(args.warmup):
         step()
     ctx.sync()
@@ -225,7 +234,8 @@ def main():
         "data": "synthetic (seeded R-MAT / uniform graphs, GPU BFS frontiers)",
         "config": {"workload": workload, "scale": args.scale, "edgefactor": 16, "roots": args.roots,
                    "segments_per_level": args.nseg, "bounds": args.bounds, "selector": args.mode,
-                   "n_ids": N, "segments": b.nseg, "levels": bfs["bfs_levels"]},
+                   "n_ids": N, "segments": b.nseg, "levels": bfs["bfs_levels"],
+                   "tune": ctx.get_tune()},
         "ratio": round(4.0 * N / comp, 4),
         "compressed_bytes": comp,
         "encode_ms": round(enc_avg, 4),
@@ -241,6 +251,14 @@ def main():
         "bfs": {"ms_total": round(bfs["bfs_ms"], 3), "levels": bfs["bfs_levels"],
                 "GTEPS": round(bfs["edges"] / 2 / (bfs["bfs_ms"] * 1e-3) / 1e9, 3)},
     }
+    if args.calib:
+        # a plain elementwise kernel of known traffic (256 MiB read + 256 MiB
+        # written per launch), for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE
+        x = torch.zeros(1 << 26, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.add(x, 1, out=y)
+        torch.cuda.synchronize()
     if not args.no_extra:
         res["extra"] = extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode)
     if not args.no_cpu:

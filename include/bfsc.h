@@ -123,6 +123,9 @@ typedef struct {
     uint32_t enc_wg_per_cu;  /* resident workgroups per CU for the persistent grid */
     uint32_t dec_waves;
     uint32_t dec_wg_per_cu;
+    uint32_t enc_pack;       /* bit 0: prefix-sum packing instead of LDS atomic ORs;
+                                bit 1: one wave per tile instead of one workgroup per tile */
+    uint32_t dec_mode;       /* 0: one workgroup per tile; 1: one wave per tile */
 } bfsc_tune;
 
 /* Creates a context on HIP device `device`: queries the device, allocates

@@ -271,12 +271,13 @@ class Context:
         t = _lib.Tune()
         check(_lib.load().bfsc_get_tune(self.h, ctypes.byref(t)), "bfsc_get_tune")
         return dict(enc_waves=t.enc_waves, enc_wg_per_cu=t.enc_wg_per_cu, dec_waves=t.dec_waves,
-                    dec_wg_per_cu=t.dec_wg_per_cu)
+                    dec_wg_per_cu=t.dec_wg_per_cu, enc_pack=t.enc_pack, dec_mode=t.dec_mode)
 
     def set_tune(self, **kw):
         cur = self.get_tune()
         cur.update(kw)
-        t = _lib.Tune(cur["enc_waves"], cur["enc_wg_per_cu"], cur["dec_waves"], cur["dec_wg_per_cu"])
+        t = _lib.Tune(cur["enc_waves"], cur["enc_wg_per_cu"], cur["dec_waves"], cur["dec_wg_per_cu"],
+                      cur["enc_pack"], cur["dec_mode"])
         check(_lib.load().bfsc_set_tune(self.h, ctypes.byref(t)), "bfsc_set_tune")
 
     def autotune(self, b: "DeviceBatch", ws=None, stream=None):

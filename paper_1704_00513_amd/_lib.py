@@ -41,7 +41,7 @@ class Adam(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("enc_waves", u32), ("enc_wg_per_cu", u32), ("dec_waves", u32),
-                ("dec_wg_per_cu", u32)]
+                ("dec_wg_per_cu", u32), ("enc_pack", u32), ("dec_mode", u32)]
 
 
 class PipelineBufs(ctypes.Structure):

@@ -237,6 +237,95 @@ __device__ __forceinline__ void put_bits(uint32_t *buf, uint32_t pos, uint32_t w
     if (sh + w > 32) atomicOr(&buf[wi + 1], v >> (32 - sh));
 }
 
+// floor(x / w) for x < 2^13 and 1 <= w <= 32: multiply by ceil(2^32 / w)
+// and keep the high word (the error term is below 2^-19, far from the next
+// integer because frac(x / w) <= 1 - 1/w).
+__device__ __forceinline__ uint32_t div_small(uint32_t x, uint32_t w, uint32_t recip) {
+    return w == 1 ? x : __umulhi(x, recip);
+}
+
+// Packs the deltas of one block at width w (w >= 1) into words [0,
+// ceil(m w / 32)) of buf without atomics.  Field t = j - 1 starts at bit t w.
+// Fields that start in the same word occupy disjoint bits, so an inclusive
+// prefix sum of the shifted fields gives each word as a difference of two
+// prefixes; the field that straddles into the word adds its spilled high bits.
+// pj / dj are per-wave LDS scratch of 128 words each.
+__device__ __forceinline__ void pack_fields(uint32_t *buf, uint32_t *pj, uint32_t *dj, uint32_t da,
+                                            uint32_t db, bool hasa, bool hasb, uint32_t m,
+                                            uint32_t w, uint32_t lane) {
+    const uint32_t ja = lane, jb = 64 + lane;
+    const uint32_t loa = hasa ? da << (((ja - 1) * w) & 31) : 0u;
+    const uint32_t lob = hasb ? db << (((jb - 1) * w) & 31) : 0u;
+    const uint32_t pa = wave_incl_scan(loa);
+    const uint32_t pb = wave_incl_scan(lob) + readlane(pa, 63);
+    pj[ja] = pa;  // pj[j] = sum of fields 0 .. j-1; pj[0] = 0
+    pj[jb] = pb;
+    dj[ja] = da;
+    dj[jb] = db;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t words = cdiv32(m * w, 32);
+    const uint32_t recip = w > 1 ? 0xFFFFFFFFu / w + 1u : 0u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t q = lane + 64u * h;
+        if (q < words) {
+            const uint32_t x0 = 32 * q;
+            const uint32_t tA = div_small(x0 + w - 1, w, recip);   // first field starting here
+            const uint32_t tB = min(div_small(x0 + 31, w, recip), m - 1);
+            uint32_t v = tA <= tB ? pj[tB + 1] - pj[tA] : 0u;
+            if (tA >= 1 && tA * w != x0) v += dj[tA] >> (x0 - (tA - 1) * w);
+            buf[q] = v;
+        }
+    }
+}
+
+// Builds one block's payload in the wave's LDS buffer (128 words) without
+// atomics for the packed fields (bit-pack, PFOR low bits); bitmap bits and
+// PFOR exceptions use LDS atomics.
+__device__ __forceinline__ void pack_block_scan(uint32_t *buf, uint32_t *pj, uint32_t *dj,
+                                                const BlockInfo &I, const BlockRegs &R,
+                                                const BlockStats &S, uint32_t lane) {
+    if (I.cls == kClsBitmap) {
+        buf[lane] = 0;
+        buf[lane + 64] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (R.hasa && R.oa >= 1 && R.oa <= S.span) atomicOr(&buf[(R.oa - 1) >> 5], 1u << ((R.oa - 1) & 31));
+        if (R.hasb && R.ob >= 1 && R.ob <= S.span) atomicOr(&buf[(R.ob - 1) >> 5], 1u << ((R.ob - 1) & 31));
+    } else if (I.cls <= 33) {
+        pack_fields(buf, pj, dj, R.da, R.db, R.hasa, R.hasb, S.m, I.param, lane);
+    } else {
+        const uint32_t b = I.param, E = I.aux & 0xFFu, h = I.aux >> 8;
+        const uint32_t lw = cdiv32(S.m * b, 32), qw = cdiv32(E, 4), hw = cdiv32(E * h, 32);
+        if (b) {
+            const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+            pack_fields(buf, pj, dj, R.da & mask, R.db & mask, R.hasa, R.hasb, S.m, b, lane);
+        }
+        if (lane < qw + hw) buf[lw + lane] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (E) {
+            const bool xa = R.hasa && b < 32 && (R.da >> b) != 0u;
+            const bool xb = R.hasb && b < 32 && (R.db >> b) != 0u;
+            const uint64_t ma = ballot(xa), mb = ballot(xb);
+            const uint64_t lt = lanemask_lt();
+            if (xa) {
+                const uint32_t e = popc64(ma & lt);
+                put_bits(buf, lw * 32 + e * 8, 8, lane - 1);
+                put_bits(buf, (lw + qw) * 32 + e * h, h, R.da >> b);
+            }
+            if (xb) {
+                const uint32_t e = popc64(ma) + popc64(mb & lt);
+                put_bits(buf, lw * 32 + e * 8, 8, 63 + lane);
+                put_bits(buf, (lw + qw) * 32 + e * h, h, R.db >> b);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Builds one block's payload in the wave's LDS buffer (128 words).
 __device__ __forceinline__ void pack_block(uint32_t *buf, const BlockInfo &I, const BlockRegs &R,
                                            const BlockStats &S, uint32_t lane) {
@@ -296,25 +385,70 @@ struct EncArgs {
     uint32_t *err;
 };
 
-// Tile sizes to offsets (one workgroup, after the pack pass): tile_off = exclusive prefix of tile_words; then every segment's
-// start, header and seg_byte_off.
+// Segment and metadata of one encoder tile.
+struct EncTile {
+    uint64_t id_base;
+    uint32_t n, nb, lo, hi, bb, g;
+    int32_t level;
+};
+constexpr uint32_t kMetaChunk = 64;  // tiles resolved per pre-pass of a workgroup
+
+__device__ __forceinline__ EncTile enc_tile_meta(const Plan &p, const uint64_t *seg_off,
+                                                 const uint32_t *seg_lo, const uint32_t *seg_hi,
+                                                 uint32_t nseg, uint32_t t,
+                                                 const int32_t *seg_level = nullptr) {
+    const uint32_t r = upper_bound_m1(p.tile_base, nseg, t);
+    EncTile m;
+    m.g = t - p.tile_base[r];
+    m.bb = p.blk_base[r];
+    m.nb = p.blk_base[r + 1] - m.bb;
+    m.n = p.seg_n[r];
+    m.lo = seg_lo[r];
+    m.hi = seg_hi[r];
+    m.id_base = seg_off[r];
+    m.level = seg_level ? seg_level[r] : 0;
+    return m;
+}
+
+// A workgroup's contiguous share [tb, te) of the tiles: consecutive tiles
+// mostly share a segment, so segment bounds are searched once per
+// workgroup and then walked forward.
+__device__ __forceinline__ void tile_range(uint32_t total, uint32_t &tb, uint32_t &te) {
+    const uint64_t G = gridDim.x, b = blockIdx.x;
+    tb = (uint32_t)(b * total / G);
+    te = (uint32_t)((b + 1) * total / G);
+}
+
+// Tile sizes to offsets (one workgroup, after the pack pass): tile_off =
+// exclusive prefix of tile_words; the batch end goes to seg_byte_off[nseg].
 __device__ void finish_offsets(const EncArgs &a, uint32_t total) {
     __shared__ uint32_t s_wt[16];
     __shared__ unsigned long long s_carry;
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t nthr = blockDim.x, nw = nthr >> 6;
-    constexpr uint32_t kPer = 8;  // tiles per thread per pass
+    constexpr uint32_t kPer = 16;  // tiles per thread per pass
     if (tid == 0) s_carry = 0;
     __syncthreads();
     for (uint32_t base = 0; base < total; base += nthr * kPer) {
         uint32_t v[kPer];
         uint32_t sum = 0;
         const uint32_t t0 = base + tid * kPer;
+        if (t0 + kPer <= total) {
+            const uint4 *src = (const uint4 *)(a.p.tile_words + t0);
 #pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) {
-            v[k] = (t0 + k < total) ? a.p.tile_words[t0 + k] : 0u;
-            sum += v[k];
+            for (uint32_t k = 0; k < kPer / 4; ++k) {
+                const uint4 x = src[k];
+                v[4 * k] = x.x;
+                v[4 * k + 1] = x.y;
+                v[4 * k + 2] = x.z;
+                v[4 * k + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < kPer; ++k) v[k] = (t0 + k < total) ? a.p.tile_words[t0 + k] : 0u;
         }
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) sum += v[k];
         const uint32_t incl = wave_incl_scan(sum);
         if (lane == 63) s_wt[w] = incl;
         __syncthreads();
@@ -334,20 +468,6 @@ __device__ void finish_offsets(const EncArgs &a, uint32_t total) {
         __syncthreads();
     }
     const uint64_t total_words = s_carry;
-    __syncthreads();
-    const uint64_t capw = a.out_cap >> 2;
-    for (uint32_t r = tid; r < a.nseg; r += nthr) {
-        const uint64_t P = a.p.tile_off[a.p.tile_base[r]];
-        const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
-        a.seg_byte_off[r] = Sr;
-        const uint64_t sw = Sr >> 2;
-        if (sw + 4 <= capw) {
-            a.out[sw + 0] = a.p.seg_n[r];
-            a.out[sw + 1] = a.seg_lo[r];
-            a.out[sw + 2] = a.seg_hi[r];
-            a.out[sw + 3] = kMagic;
-        }
-    }
     if (tid == 0) {
         const uint64_t end = 16ull * a.nseg + 8ull * a.p.blk_base[a.nseg] + 4ull * a.p.grp_base[a.nseg] +
                              4ull * total_words;
@@ -358,24 +478,36 @@ __device__ void finish_offsets(const EncArgs &a, uint32_t total) {
 
 // Pack pass: analyse, choose and pack every block of a tile into the tile's
 // slot (directory words first, then the payloads in block order).
-template <int WAVES>
+template <int WAVES, bool SCANPACK>
 __global__ __launch_bounds__(WAVES * 64) void k_enc_pack(EncArgs a) {
     constexpr int BPW = (int)kGroup / WAVES;  // blocks per wave per tile
     __shared__ BlockInfo s_info[kGroup];
     __shared__ uint32_t s_pref[kGroup];
-    __shared__ uint32_t s_buf[WAVES][128];
+    __shared__ uint32_t s_buf[WAVES][132];
+    __shared__ uint32_t s_pj[SCANPACK ? WAVES : 1][128];
+    __shared__ uint32_t s_dj[SCANPACK ? WAVES : 1][128];
+    __shared__ EncTile s_tm[kMetaChunk];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t total = a.p.tile_base[a.nseg];
+    const uint32_t G = gridDim.x;
 
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
-        const uint32_t g = t - a.p.tile_base[r];
-        const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
-        const uint32_t n = a.p.seg_n[r];
+    for (uint32_t base = blockIdx.x; base < total; base += G * kMetaChunk) {
+    // tiles base, base + G, ... (strided for balance); their segments and
+    // metadata are resolved first, one thread per tile, all in flight at once
+    if (tid < kMetaChunk) {
+        const uint32_t t = base + tid * G;
+        if (t < total) s_tm[tid] = enc_tile_meta(a.p, a.seg_off, a.seg_lo, a.seg_hi, a.nseg, t);
+    }
+    __syncthreads();
+    for (uint32_t it = 0; it < kMetaChunk; ++it) {
+        const uint32_t t = base + it * G;
+        if (t >= total) break;
+        const EncTile m = s_tm[it];
+        const uint32_t nb = m.nb, n = m.n, lo = m.lo, hi = m.hi, bb = m.bb;
+        const uint32_t *ids = a.ids + m.id_base;
+        const uint32_t g = m.g;
         const uint32_t k0 = g * kGroup;
         const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
-        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
-        const uint32_t *ids = a.ids + a.seg_off[r];
         uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
 
         // issue every load of this wave's blocks first
@@ -397,7 +529,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack(EncArgs a) {
                 const uint32_t k = k0 + kk;
                 const uint32_t nk = min(kBlock, n - k * kBlock);
                 analyze_block(va[i], vb[i], nk, lo, hi, lane, false, R[i], S[i], a.err);
-                const int given = a.classes ? (int)a.classes[a.p.blk_base[r] + k] : -1;
+                const int given = a.classes ? (int)a.classes[bb + k] : -1;
                 I[i] = choose(R[i], S[i], a.mode, given, a.err);
                 I[i].first = S[i].v0 - lo;
                 if (lane == 0) s_info[kk] = I[i];
@@ -419,7 +551,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack(EncArgs a) {
         for (int i = 0; i < BPW; ++i) {
             const uint32_t kk = w + (uint32_t)i * WAVES;
             if (kk < nblk && I[i].words) {
-                pack_block(s_buf[w], I[i], R[i], S[i], lane);
+                if constexpr (SCANPACK)
+                    pack_block_scan(s_buf[w], s_pj[w], s_dj[w], I[i], R[i], S[i], lane);
+                else
+                    pack_block(s_buf[w], I[i], R[i], S[i], lane);
                 uint32_t *dst = slot + kSlotDirWords + s_pref[kk];
                 if (lane < I[i].words) dst[lane] = s_buf[w][lane];
                 if (lane + 64 < I[i].words) dst[lane + 64] = s_buf[w][lane + 64];
@@ -428,6 +563,82 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack(EncArgs a) {
         }
         __syncthreads();
     }
+    }
+}
+
+// Last r < n with base[r] <= t (base non-decreasing, base[0] <= t), found by
+// the whole wave: 64 probes per round, so 2 dependent loads for up to 4096
+// entries and 3 for up to 262144.
+__device__ __forceinline__ uint32_t wave_find(const uint32_t *base, uint32_t n, uint32_t t,
+                                              uint32_t lane) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) >> 6;
+        const uint32_t idx = lo + lane * step;
+        const bool ok = idx < hi && base[idx] <= t;
+        const uint64_t mk = ballot(ok);
+        const uint32_t k = 63u - (uint32_t)__builtin_clzll(mk | 1ull);
+        lo = lo + k * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+// Pack pass, one wave per tile: the wave walks the tile's blocks in order,
+// prefetching the next block while it analyses, chooses and packs the
+// current one, and keeps the running payload offset itself -- no
+// workgroup barriers and no per-tile scan.
+template <int WAVES, bool SCANPACK>
+__global__ __launch_bounds__(WAVES * 64) void k_enc_pack_w(EncArgs a) {
+    __shared__ uint32_t s_buf[WAVES][132];
+    __shared__ uint32_t s_pj[SCANPACK ? WAVES : 1][128];
+    __shared__ uint32_t s_dj[SCANPACK ? WAVES : 1][128];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t total = a.p.tile_base[a.nseg];
+    const uint32_t nw = gridDim.x * WAVES;
+    for (uint32_t t = blockIdx.x * WAVES + w; t < total; t += nw) {
+        const uint32_t r = wave_find(a.p.tile_base, a.nseg, t, lane);
+        const uint32_t g = t - a.p.tile_base[r];
+        const uint32_t bb = a.p.blk_base[r];
+        const uint32_t nb = a.p.blk_base[r + 1] - bb;
+        const uint32_t n = a.p.seg_n[r];
+        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
+        const uint32_t *ids = a.ids + a.seg_off[r];
+        const uint32_t k0 = g * kGroup;
+        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
+        uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+        uint32_t run = 0;  // payload words of the tile so far
+        uint32_t va = 0, vb = 0;
+        if (nblk) fetch_block(ids + (uint64_t)k0 * kBlock, min(kBlock, n - k0 * kBlock), lane, va, vb);
+        for (uint32_t kk = 0; kk < nblk; ++kk) {
+            const uint32_t k = k0 + kk;
+            const uint32_t nk = min(kBlock, n - k * kBlock);
+            uint32_t na = 0, nbv = 0;
+            if (kk + 1 < nblk)
+                fetch_block(ids + (uint64_t)(k + 1) * kBlock, min(kBlock, n - (k + 1) * kBlock), lane, na, nbv);
+            BlockRegs R;
+            BlockStats S;
+            analyze_block(va, vb, nk, lo, hi, lane, false, R, S, a.err);
+            const int given = a.classes ? (int)a.classes[bb + k] : -1;
+            BlockInfo I = choose(R, S, a.mode, given, a.err);
+            if (lane < 2)
+                slot[2 * kk + lane] = lane ? (I.cls | (I.param << 8) | (I.aux << 16)) : S.v0 - lo;
+            if (I.words) {
+                if constexpr (SCANPACK)
+                    pack_block_scan(s_buf[w], s_pj[w], s_dj[w], I, R, S, lane);
+                else
+                    pack_block(s_buf[w], I, R, S, lane);
+                uint32_t *dst = slot + kSlotDirWords + run;
+                if (lane < I.words) dst[lane] = s_buf[w][lane];
+                if (lane + 64 < I.words) dst[lane + 64] = s_buf[w][lane + 64];
+                __builtin_amdgcn_wave_barrier();
+            }
+            run += I.words;
+            va = na;
+            vb = nbv;
+        }
+        if (lane == 0) a.p.tile_words[t] = run;
+    }
 }
 
 // One workgroup: tile sizes -> offsets, segment starts and headers.
@@ -435,22 +646,48 @@ __global__ __launch_bounds__(1024) void k_enc_scan(EncArgs a) {
     finish_offsets(a, a.p.tile_base[a.nseg]);
 }
 
-// Place pass: copy every tile's directory entries, group-table entry and
-// payload words from its slot to the final position.
+// Place pass: every segment's header and start offset (by its first tile),
+// then every tile's directory entries, group-table entry and payload words,
+// copied from its slot to the final position.
 __global__ __launch_bounds__(256) void k_enc_place(EncArgs a) {
     const uint32_t tid = threadIdx.x;
     const uint32_t total = a.p.tile_base[a.nseg];
     const uint64_t capw = a.out_cap >> 2;
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
-        const uint32_t g = t - a.p.tile_base[r];
-        const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
-        const uint32_t ng = a.p.grp_base[r + 1] - a.p.grp_base[r];
+    uint32_t tb, te;
+    tile_range(total, tb, te);
+    if (tb >= te) return;
+    uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, tb);
+    uint32_t t_first = a.p.tile_base[r], t_next = a.p.tile_base[r + 1];
+    uint32_t nb = 0, ng = 0;
+    uint64_t P = 0, sw = 0;
+    bool fresh = true;
+    for (uint32_t t = tb; t < te; ++t) {
+        while (t >= t_next) {
+            ++r;
+            t_first = t_next;
+            t_next = a.p.tile_base[r + 1];
+            fresh = true;
+        }
+        if (fresh) {
+            nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
+            ng = a.p.grp_base[r + 1] - a.p.grp_base[r];
+            P = a.p.tile_off[t_first];
+            const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
+            sw = Sr >> 2;
+            fresh = false;
+        }
+        const uint32_t g = t - t_first;
+        if (g == 0 && tid < 4) {
+            if (tid == 0) a.seg_byte_off[r] = sw << 2;
+            if (sw + 4 <= capw) {
+                const uint32_t hv = tid == 0 ? a.p.seg_n[r] : tid == 1 ? a.seg_lo[r] : tid == 2 ? a.seg_hi[r] : kMagic;
+                a.out[sw + tid] = hv;
+            }
+        }
         const uint32_t k0 = g * kGroup;
         const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
         if (!nblk) continue;
-        const uint64_t sw = a.seg_byte_off[r] >> 2;
-        const uint64_t rel = a.p.tile_off[t] - a.p.tile_off[a.p.tile_base[r]];
+        const uint64_t rel = a.p.tile_off[t] - P;
         const uint32_t A = a.p.tile_words[t];
         const uint64_t pwb = sw + 4 + 2ull * nb + ng + rel;
         const uint64_t dwb = sw + 4 + 2ull * k0;
@@ -516,17 +753,26 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t total = a.p.tile_base[a.nseg];
     const bool learned = a.mode == BFSC_SEL_LEARNED;
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, t);
-        const uint32_t g = t - a.p.tile_base[r];
-        const uint32_t nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
-        const uint32_t n = a.p.seg_n[r];
+    __shared__ EncTile s_tm[kMetaChunk];
+    const uint32_t G = gridDim.x;
+    for (uint32_t base = blockIdx.x; base < total; base += G * kMetaChunk) {
+    if (tid < kMetaChunk) {
+        const uint32_t t = base + tid * G;
+        if (t < total)
+            s_tm[tid] = enc_tile_meta(a.p, a.seg_off, a.seg_lo, a.seg_hi, a.nseg, t, a.seg_level);
+    }
+    __syncthreads();
+    for (uint32_t it = 0; it < kMetaChunk; ++it) {
+        const uint32_t t = base + it * G;
+        if (t >= total) break;
+        const EncTile m = s_tm[it];
+        const uint32_t nb = m.nb, n = m.n, lo = m.lo, hi = m.hi, bb = m.bb;
+        const int32_t level = m.level;
+        const uint32_t *ids = a.ids + m.id_base;
+        const uint32_t g = m.g;
         const uint32_t k0 = g * kGroup;
         const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
-        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
-        const uint32_t *ids = a.ids + a.seg_off[r];
-        const int32_t level = a.seg_level ? a.seg_level[r] : 0;
-        const uint32_t gb = a.p.blk_base[r] + k0;
+        const uint32_t gb = bb + k0;
         uint32_t va[BPW], vb[BPW];
 #pragma unroll
         for (int i = 0; i < BPW; ++i) {
@@ -628,6 +874,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
         }
         __syncthreads();
     }
+    __syncthreads();  // s_tm is rewritten by the next chunk
+    }
 }
 
 // ------------------------------------------------------------------ decode
@@ -706,6 +954,12 @@ __global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
     }
 }
 
+// Segment and header fields of one decoder tile.
+struct DecTile {
+    uint64_t S, bytes, oo;
+    uint32_t n, g, lo, hi;
+};
+
 struct DecArgs {
     const uint8_t *in;
     const uint64_t *seg_byte_off;
@@ -740,22 +994,43 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
     __shared__ uint32_t s_ok;
     __shared__ uint32_t s_buf[WAVES][132];
     __shared__ uint32_t s_val[WAVES][128];
+    __shared__ DecTile s_tm[kMetaChunk];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t total = a.tile_base[a.nseg];
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t r = upper_bound_m1(a.tile_base, a.nseg, t);
-        const uint32_t g = t - a.tile_base[r];
-        const uint32_t n = a.seg_n[r];
+    const uint32_t G = gridDim.x;
+    for (uint32_t base = blockIdx.x; base < total; base += G * kMetaChunk) {
+    // strided tiles; segment lookups and header reads of the chunk first,
+    // one thread per tile (segments without tiles never match a tile)
+    if (tid < kMetaChunk) {
+        const uint32_t t = base + tid * G;
+        if (t < total) {
+            const uint32_t r = upper_bound_m1(a.tile_base, a.nseg, t);
+            DecTile m;
+            m.g = t - a.tile_base[r];
+            m.n = a.seg_n[r];
+            m.S = a.seg_byte_off[r];
+            m.bytes = a.seg_byte_off[r + 1] - m.S;
+            m.oo = a.out_off[r];
+            const uint32_t *h = (const uint32_t *)(a.in + m.S);
+            m.lo = h[1];
+            m.hi = h[2];
+            s_tm[tid] = m;
+        }
+    }
+    __syncthreads();
+    for (uint32_t it = 0; it < kMetaChunk; ++it) {
+        const uint32_t t = base + it * G;
+        if (t >= total) break;
+        const DecTile m = s_tm[it];
+        const uint32_t n = m.n, lo = m.lo, hi = m.hi;
         const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
-        const uint64_t S = a.seg_byte_off[r];
-        const uint64_t bytes = a.seg_byte_off[r + 1] - S;
-        const uint32_t *seg = (const uint32_t *)(a.in + S);
-        const uint32_t lo = seg[1], hi = seg[2];
+        const uint32_t *seg = (const uint32_t *)(a.in + m.S);
         const uint32_t metaw = 4 + 2 * nb + ng;
-        const uint64_t availw = bytes / 4 - metaw;
+        const uint64_t availw = m.bytes / 4 - metaw;
+        const uint64_t oo = m.oo;
+        const uint32_t g = m.g;
         const uint32_t k0 = g * kGroup;
         const uint32_t nblk = min(kGroup, nb - k0);
-        const uint64_t oo = a.out_off[r];
         if (w == 0) {
             bool bad = false;
             uint32_t words = 0;
@@ -911,6 +1186,181 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
         }
         __syncthreads();
     }
+    }
+}
+
+// Decodes and validates one block whose payload words are pa (word lane) and
+// pb (word 64+lane); writes its IDs to out[ob ..] unless it is damaged.
+__device__ __forceinline__ void decode_one_block(uint32_t *buf, uint32_t *val, uint32_t pa, uint32_t pb,
+                                                 uint32_t cls, uint32_t param, uint32_t aux,
+                                                 uint32_t v0, uint32_t nk, uint32_t hi, bool has_next,
+                                                 uint32_t nxt, uint32_t *out, uint64_t ob,
+                                                 uint64_t out_cap, uint32_t *err, uint32_t lane) {
+    const uint32_t m = nk - 1;
+    buf[lane] = pa;
+    buf[lane + 64] = pb;
+    if (lane < 4) buf[128 + lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    bool bad = false;
+    uint32_t xa = 0, xb = 0;
+    const bool ina = lane < nk, inb = lane + 64 < nk;
+    if (cls == kClsBitmap) {
+        const uint32_t nch = (aux + 63) >> 6;
+        uint32_t cnt = 1;
+        if (lane == 0) val[0] = v0;
+        for (uint32_t c = 0; c < nch; ++c) {
+            const uint32_t word = lane < 32 ? buf[2 * c] : buf[2 * c + 1];
+            const bool set = (word >> (lane & 31)) & 1u;
+            const uint64_t mk = ballot(set);
+            const uint32_t rank = popc64(mk & lanemask_lt());
+            if (set && cnt + rank < 128) val[cnt + rank] = v0 + 64 * c + lane + 1;
+            cnt += popc64(mk);
+        }
+        const uint32_t tailw = aux >> 5, tailb = aux & 31;
+        bad |= tailb && lane == 0 && (buf[tailw] >> tailb) != 0u;
+        bad |= cnt - 1 != m;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        xa = val[lane];
+        xb = val[lane + 64];
+        if (cnt - 1 == m) {
+            const uint32_t lastv = m ? (nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65)) : v0;
+            bad |= (uint64_t)v0 + (lastv - v0) >= (uint64_t)hi;
+        }
+    } else {
+        const uint32_t b = cls <= 33 ? cls - 1 : param;
+        const uint32_t ja = lane, jb = 64 + lane;
+        uint32_t da = (ina && ja >= 1 && b) ? get_field(buf, (ja - 1) * b, b) : 0u;
+        uint32_t db = (inb && b) ? get_field(buf, (jb - 1) * b, b) : 0u;
+        if (cls == kClsPfor) {
+            const uint32_t E = aux & 0xFFu, h = aux >> 8;
+            const uint32_t lw = cdiv32(m * b, 32), qw = cdiv32(E, 4);
+            val[lane] = 0u;
+            val[lane + 64] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            uint32_t p = 0;
+            if (lane < E) {
+                p = (buf[lw + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu;
+                const uint32_t hv = h ? get_field(buf + lw + qw, lane * h, h) : 0u;
+                if (p < m) val[p + 1] = b >= 32 ? 0u : (hv << b);
+            }
+            const uint32_t pp = lane_prev(p, 0u);
+            bad |= lane < E && (p >= m || (lane > 0 && p <= pp));
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            da |= val[lane];
+            db |= val[lane + 64];
+        }
+        bad |= (ina && ja >= 1 && da == 0) || (inb && db == 0);
+        const uint32_t sa = wave_incl_scan(da);
+        const uint32_t ta = readlane(sa, 63);
+        const uint32_t sb = wave_incl_scan(db) + ta;
+        xa = v0 + sa;
+        xb = v0 + sb;
+        const uint32_t a63 = readlane(xa, 63);
+        const uint32_t prva = lane_prev(xa, 0u);
+        const uint32_t prvb = lane_prev(xb, a63);
+        bad |= (ina && lane >= 1 && xa <= prva) || (inb && xb <= prvb);
+    }
+    const uint32_t last = nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65);
+    bad |= last >= hi || (has_next && last >= nxt);
+    if (ballot(bad) != 0ull) {
+        if (lane == 0) raise_err(err, kErrCorrupt);
+    } else {
+        if (ina && ob + lane < out_cap) out[ob + lane] = xa;
+        if (inb && ob + 64 + lane < out_cap) out[ob + 64 + lane] = xb;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Decode, one wave per tile: the wave reads and checks the tile's directory
+// entries (one lane per block), then decodes the blocks in order while the
+// next block's payload is already in flight.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_decode_w(DecArgs a) {
+    __shared__ uint32_t s_buf[WAVES][132];
+    __shared__ uint32_t s_val[WAVES][128];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t total = a.tile_base[a.nseg];
+    const uint32_t nw = gridDim.x * WAVES;
+    uint32_t *buf = s_buf[w];
+    uint32_t *val = s_val[w];
+    for (uint32_t t = blockIdx.x * WAVES + w; t < total; t += nw) {
+        const uint32_t r = wave_find(a.tile_base, a.nseg, t, lane);
+        const uint32_t g = t - a.tile_base[r];
+        const uint32_t n = a.seg_n[r];
+        const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
+        const uint64_t S = a.seg_byte_off[r];
+        const uint64_t bytes = a.seg_byte_off[r + 1] - S;
+        const uint32_t *seg = (const uint32_t *)(a.in + S);
+        const uint32_t lo = seg[1], hi = seg[2];
+        const uint32_t metaw = 4 + 2 * nb + ng;
+        const uint64_t availw = bytes / 4 - metaw;
+        const uint64_t oo = a.out_off[r];
+        const uint32_t k0 = g * kGroup;
+        const uint32_t nblk = min(kGroup, nb - k0);
+        // lane i < nblk: block k0+i; lane nblk: the next block's first value
+        bool bad = false;
+        uint32_t words = 0, cls = 0, param = 0, aux = 0, first = 0;
+        if (lane <= nblk && k0 + lane < nb) {
+            first = seg[4 + 2 * (k0 + lane)];
+            const uint32_t e1 = seg[4 + 2 * (k0 + lane) + 1];
+            if (lane < nblk) {
+                cls = e1 & 0xFFu;
+                param = (e1 >> 8) & 0xFFu;
+                aux = e1 >> 16;
+                const uint32_t nk = min(kBlock, n - (k0 + lane) * kBlock), m = nk - 1;
+                if (cls == kClsBitmap) {
+                    bad = param != 0 || aux > kBitmapMaxSpan;
+                } else if (cls <= 33) {
+                    bad = param != cls - 1 || aux != 0;
+                } else if (cls == kClsPfor) {
+                    const uint32_t E = aux & 0xFFu, h = aux >> 8;
+                    bad = param > 32 || param + h > 32 || 10 * E > m;
+                } else {
+                    bad = true;
+                }
+                words = bad ? 0u : block_words(cls, param, aux, m);
+                bad |= words > kBlock;
+                bad |= (uint64_t)lo + first >= (uint64_t)hi;
+            }
+        }
+        const uint32_t incl = wave_incl_scan(lane < nblk ? words : 0u);
+        const uint32_t A = readlane(incl, 63);
+        const uint32_t gt = seg[4 + 2 * nb + g];
+        const uint32_t off = gt + incl - words;
+        bool ok = ballot(bad) == 0ull;
+        ok = ok && (uint64_t)gt + A <= availw;
+        if (g + 1 < ng) ok = ok && seg[4 + 2 * nb + g + 1] == gt + A;
+        else ok = ok && (uint64_t)gt + A == availw;
+        if (!ok) {
+            if (lane == 0) raise_err(a.err, kErrCorrupt);
+            continue;
+        }
+        const uint32_t *pay = seg + metaw;
+        uint32_t wc = readlane(words, 0), oc = readlane(off, 0);
+        uint32_t pa = lane < wc ? pay[oc + lane] : 0u;
+        uint32_t pb = lane + 64 < wc ? pay[oc + lane + 64] : 0u;
+        for (uint32_t kk = 0; kk < nblk; ++kk) {
+            const uint32_t k = k0 + kk;
+            uint32_t na = 0, nbw = 0;
+            if (kk + 1 < nblk) {
+                const uint32_t wn = readlane(words, kk + 1), on = readlane(off, kk + 1);
+                na = lane < wn ? pay[on + lane] : 0u;
+                nbw = lane + 64 < wn ? pay[on + lane + 64] : 0u;
+            }
+            const bool has_next = k + 1 < nb;
+            const uint32_t nxt = has_next ? lo + readlane(first, kk + 1) : 0u;
+            decode_one_block(buf, val, pa, pb, readlane(cls, kk), readlane(param, kk),
+                             readlane(aux, kk), lo + readlane(first, kk),
+                             min(kBlock, n - k * kBlock), hi, has_next, nxt, a.out,
+                             oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
+            pa = na;
+            pb = nbw;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ partition
@@ -976,11 +1426,19 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     const uint32_t grid = persistent_grid(ctx, ctx->tune.enc_wg_per_cu, p.max_tiles);
     const int slot = timing_begin(ctx, BFSC_OP_ENCODE, s);
     switch (waves) {
-        case 1: hipLaunchKernelGGL(k_enc_pack<1>, dim3(grid), dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_enc_pack<2>, dim3(grid), dim3(128), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_enc_pack<8>, dim3(grid), dim3(512), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(k_enc_pack<16>, dim3(grid), dim3(1024), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_enc_pack<4>, dim3(grid), dim3(256), 0, s, a); break;
+#define BFSC_PACK_CASE(W)                                                                  \
+    switch (ctx->tune.enc_pack) {                                                          \
+        case 1: hipLaunchKernelGGL((k_enc_pack<W, true>), dim3(grid), dim3(W * 64), 0, s, a); break;   \
+        case 2: hipLaunchKernelGGL((k_enc_pack_w<W, false>), dim3(grid), dim3(W * 64), 0, s, a); break; \
+        case 3: hipLaunchKernelGGL((k_enc_pack_w<W, true>), dim3(grid), dim3(W * 64), 0, s, a); break;  \
+        default: hipLaunchKernelGGL((k_enc_pack<W, false>), dim3(grid), dim3(W * 64), 0, s, a); break;  \
+    }
+        case 1: BFSC_PACK_CASE(1) break;
+        case 2: BFSC_PACK_CASE(2) break;
+        case 8: BFSC_PACK_CASE(8) break;
+        case 16: BFSC_PACK_CASE(16) break;
+        default: BFSC_PACK_CASE(4) break;
+#undef BFSC_PACK_CASE
     }
     timing_end(ctx, slot, s);
     hipLaunchKernelGGL(k_enc_scan, dim3(1), dim3(1024), 0, s, a);
@@ -1048,13 +1506,19 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     const uint64_t mt = plan_max_tiles(max_ids, nseg);
     const uint32_t grid = persistent_grid(ctx, ctx->tune.dec_wg_per_cu, mt);
     const int slot = timing_begin(ctx, BFSC_OP_DECODE, s);
+#define BFSC_DEC_CASE(W)                                                                   \
+    if (ctx->tune.dec_mode)                                                                \
+        hipLaunchKernelGGL((k_decode_w<W>), dim3(grid), dim3(W * 64), 0, s, a);            \
+    else                                                                                   \
+        hipLaunchKernelGGL((k_decode<W>), dim3(grid), dim3(W * 64), 0, s, a);
     switch (ctx->tune.dec_waves) {
-        case 1: hipLaunchKernelGGL(k_decode<1>, dim3(grid), dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_decode<2>, dim3(grid), dim3(128), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_decode<8>, dim3(grid), dim3(512), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(k_decode<16>, dim3(grid), dim3(1024), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_decode<4>, dim3(grid), dim3(256), 0, s, a); break;
+        case 1: BFSC_DEC_CASE(1) break;
+        case 2: BFSC_DEC_CASE(2) break;
+        case 8: BFSC_DEC_CASE(8) break;
+        case 16: BFSC_DEC_CASE(16) break;
+        default: BFSC_DEC_CASE(4) break;
     }
+#undef BFSC_DEC_CASE
     timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }

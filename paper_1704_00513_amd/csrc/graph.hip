@@ -308,14 +308,20 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
     const bfsc_tune keep = ctx->tune;
     const int timing = ctx->timing;
     ctx->timing = 0;
-    static const uint32_t kEnc[][2] = {{4, 4}, {4, 8}, {8, 2}, {8, 4}, {8, 8}, {16, 2}, {16, 4}};
-    static const uint32_t kDec[][2] = {{2, 8}, {4, 4}, {4, 8}, {4, 12}, {8, 4}, {8, 8}, {16, 2}};
+    // {waves per workgroup, workgroups per CU, pack variant}
+    static const uint32_t kEnc[][3] = {{4, 8, 0}, {8, 8, 0}, {8, 8, 1}, {2, 8, 2}, {4, 4, 2},
+                                       {4, 8, 2}, {4, 16, 2}, {8, 4, 2}, {8, 8, 2}, {4, 8, 3},
+                                       {8, 8, 3}};
+    // {waves per workgroup, workgroups per CU, decoder variant}
+    static const uint32_t kDec[][3] = {{4, 8, 0}, {8, 4, 0}, {2, 8, 1}, {4, 4, 1}, {4, 8, 1},
+                                       {4, 16, 1}, {8, 4, 1}, {8, 8, 1}};
     bfsc_tune best = keep;
     float best_e = 1e30f, best_d = 1e30f;
     for (const auto &c : kEnc) {
         if (st) break;
         ctx->tune.enc_waves = c[0];
         ctx->tune.enc_wg_per_cu = c[1];
+        ctx->tune.enc_pack = c[2];
         float tot = 0.0f;
         for (int rep = 0; rep < 4 && !st; ++rep) {
             if (hipEventRecord(e0, s) != hipSuccess) st = BFSC_E_HIP;
@@ -329,15 +335,18 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
             best_e = tot;
             best.enc_waves = c[0];
             best.enc_wg_per_cu = c[1];
+            best.enc_pack = c[2];
         }
     }
     ctx->tune.enc_waves = best.enc_waves;
     ctx->tune.enc_wg_per_cu = best.enc_wg_per_cu;
+    ctx->tune.enc_pack = best.enc_pack;
     if (!st) st |= bfsc_encode(ctx, sample, nullptr, BFSC_SEL_EXHAUSTIVE, out, cap, sbo, ws, s);
     for (const auto &c : kDec) {
         if (st) break;
         ctx->tune.dec_waves = c[0];
         ctx->tune.dec_wg_per_cu = c[1];
+        ctx->tune.dec_mode = c[2];
         float tot = 0.0f;
         for (int rep = 0; rep < 4 && !st; ++rep) {
             if (hipEventRecord(e0, s) != hipSuccess) st = BFSC_E_HIP;
@@ -351,6 +360,7 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
             best_d = tot;
             best.dec_waves = c[0];
             best.dec_wg_per_cu = c[1];
+            best.dec_mode = c[2];
         }
     }
     ctx->timing = timing;

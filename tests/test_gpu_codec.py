@@ -66,15 +66,39 @@ def batches():
     return out
 
 
+@pytest.mark.parametrize("pack", [0, 1, 2, 3])
+@pytest.mark.parametrize("waves", [4, 8, 16])
 @pytest.mark.parametrize("mode", [oracle.PLAIN_BP, oracle.EXHAUSTIVE])
-def test_encode_is_byte_exact(ctx, mode):
-    for name, b in batches():
-        log("encode mode=%d case=%s n=%d nseg=%d" % (mode, name, b.n_ids, b.nseg))
-        want, want_off = oracle.encode(b, mode=mode)
-        st, got, got_off = gpu_encode(ctx, b, mode=mode)
-        assert st == 0, name
-        np.testing.assert_array_equal(got_off, want_off, err_msg=name)
-        np.testing.assert_array_equal(got, want, err_msg=name)
+def test_encode_is_byte_exact(ctx, mode, waves, pack):
+    before = ctx.get_tune()
+    ctx.set_tune(enc_waves=waves, enc_pack=pack)
+    try:
+        for name, b in batches():
+            log("encode mode=%d waves=%d pack=%d case=%s n=%d nseg=%d" % (mode, waves, pack, name,
+                                                                         b.n_ids, b.nseg))
+            want, want_off = oracle.encode(b, mode=mode)
+            st, got, got_off = gpu_encode(ctx, b, mode=mode)
+            assert st == 0, name
+            np.testing.assert_array_equal(got_off, want_off, err_msg=name)
+            np.testing.assert_array_equal(got, want, err_msg=name)
+    finally:
+        ctx.set_tune(**before)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("waves", [2, 4, 8, 16])
+def test_decode_shapes(ctx, waves, mode):
+    before = ctx.get_tune()
+    ctx.set_tune(dec_waves=waves, dec_mode=mode)
+    try:
+        for name, b in batches():
+            log("decode waves=%d mode=%d case=%s" % (waves, mode, name))
+            stream, sbo = oracle.encode(b)
+            st, ids, off = gpu_decode(ctx, stream, sbo)
+            assert st == 0
+            np.testing.assert_array_equal(ids, b.ids)
+    finally:
+        ctx.set_tune(**before)
 
 
 def test_select_matches_oracle(ctx):
@@ -148,7 +172,9 @@ def test_capacity_is_reported(ctx):
     assert st == 2
 
 
-def test_damaged_streams_agree_with_oracle(ctx):
+@pytest.mark.parametrize("dec_mode", [0, 1])
+def test_damaged_streams_agree_with_oracle(ctx, dec_mode):
+    ctx.set_tune(dec_mode=dec_mode)
     rng = np.random.default_rng(9)
     for name, b in [x for x in batches() if x[0] in ("clustered", "pfor", "s16-L3", "zipf256")]:
         stream, sbo = oracle.encode(b)
@@ -164,3 +190,4 @@ def test_damaged_streams_agree_with_oracle(ctx):
             if st == 0:
                 np.testing.assert_array_equal(ids, want_ids)
                 np.testing.assert_array_equal(off, want_off)
+    ctx.set_tune(dec_mode=0)
