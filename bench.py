@@ -213,7 +213,7 @@ def main():
     # algorithmic bytes per launch: the pack pass reads the raw IDs and writes
     # the compressed content; the decoder reads it and writes the raw IDs
     alg_bytes = 4.0 * N + comp
-    dom = ("k_enc_pack", enc_avg) if enc_avg >= dec_avg else ("k_decode", dec_avg)
+    dom = ("k_enc_pack_u", enc_avg) if enc_avg >= dec_avg else ("k_decode_u", dec_avg)
     achieved = alg_bytes / (dom[1] * 1e-3) / 1e9
     workload = "rmat-s%d" % args.scale if args.graph == "rmat" else "uniform-s%d" % args.scale
     workload += "-%droots-%s%d-%s" % (args.roots, args.bounds, args.nseg, args.mode)

@@ -120,12 +120,19 @@ typedef struct {
 /* Launch shapes of the codec kernels (chosen by bfsc_autotune or set). */
 typedef struct {
     uint32_t enc_waves;      /* waves per workgroup, encode (1..16) */
-    uint32_t enc_wg_per_cu;  /* resident workgroups per CU for the persistent grid */
+    uint32_t enc_wg_per_cu;  /* workgroups per CU for the persistent grid (capped at
+                                the kernel's occupancy limit) */
     uint32_t dec_waves;
     uint32_t dec_wg_per_cu;
     uint32_t enc_pack;       /* bit 0: prefix-sum packing instead of LDS atomic ORs;
-                                bit 1: one wave per tile instead of one workgroup per tile */
-    uint32_t dec_mode;       /* 0: one workgroup per tile; 1: one wave per tile */
+                                bit 1: IDs loaded block by block instead of a whole unit
+                                (8 blocks) staged in LDS at once;
+                                bit 2: units taken every NW-th by a wave instead of in one
+                                contiguous run per wave */
+    uint32_t dec_mode;       /* bit 0: payload loaded block by block instead of a whole
+                                unit staged in LDS at once;
+                                bit 1: units taken every NW-th instead of in one contiguous
+                                run per wave */
 } bfsc_tune;
 
 /* Creates a context on HIP device `device`: queries the device, allocates

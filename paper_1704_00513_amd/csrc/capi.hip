@@ -88,14 +88,14 @@ int bfsc_create(bfsc_ctx **out, int device) {
         bfsc_destroy(c);
         return BFSC_E_HIP;
     }
-    // measured best on MI355X for R-MAT s22 frontier batches: one wave per
-    // tile for both passes, 4-wave workgroups, 8 workgroups per CU
+    // one wave per unit of 8 blocks, loaded block by block, units dealt out
+    // every NW-th; 4-wave workgroups, as many resident per CU as fit
     c->tune.enc_waves = 4;
     c->tune.enc_wg_per_cu = 8;
     c->tune.dec_waves = 4;
     c->tune.dec_wg_per_cu = 8;
-    c->tune.enc_pack = 2;
-    c->tune.dec_mode = 1;
+    c->tune.enc_pack = 6;
+    c->tune.dec_mode = 3;
     *out = c;
     return BFSC_OK;
 }
@@ -280,8 +280,8 @@ static bool waves_ok(uint32_t w) { return w == 1 || w == 2 || w == 4 || w == 8 |
 int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t) {
     if (!ctx || !t) return BFSC_E_INVAL;
     if (!waves_ok(t->enc_waves) || !waves_ok(t->dec_waves) || t->enc_wg_per_cu < 1 ||
-        t->enc_wg_per_cu > 64 || t->dec_wg_per_cu < 1 || t->dec_wg_per_cu > 64 || t->enc_pack > 3 ||
-        t->dec_mode > 1)
+        t->enc_wg_per_cu > 64 || t->dec_wg_per_cu < 1 || t->dec_wg_per_cu > 64 || t->enc_pack > 7 ||
+        t->dec_mode > 3)
         return BFSC_E_INVAL;
     ctx->tune = *t;
     return BFSC_OK;

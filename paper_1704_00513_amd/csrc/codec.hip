@@ -132,8 +132,9 @@ __device__ __forceinline__ void analyze_block(uint32_t va, uint32_t vb, uint32_t
     R.hasb = inb;
     R.da = R.hasa ? va - pa : 0u;
     R.db = R.hasb ? vb - pb : 0u;
-    const bool bad = (R.hasa && va <= pa) || (R.hasb && vb <= pb) ||
-                     (ina && (va < lo || va >= hi)) || (inb && (vb < lo || vb >= hi));
+    // bitwise, not short-circuit: straight-line selects instead of branches
+    const bool bad = (R.hasa & (va <= pa)) | (R.hasb & (vb <= pb)) |
+                     (ina & ((va < lo) | (va >= hi))) | (inb & ((vb < lo) | (vb >= hi)));
     if (ballot(bad) != 0ull && lane == 0) raise_err(err, kErrInval);
     S.nk = nk;
     S.m = nk - 1;
@@ -163,8 +164,9 @@ __device__ __forceinline__ void pfor_best(const BlockRegs &R, const BlockStats &
     E = 0;
     words = cdiv32(S.m * S.wmin, 32);
     for (int b = (int)S.wmin - 1; b >= 0; --b) {
-        const uint32_t e = popc64(ballot(R.hasa && (R.da >> b) != 0u)) +
-                           popc64(ballot(R.hasb && (R.db >> b) != 0u));
+        // deltas of lanes without one are 0, so they never count
+        const uint32_t thr = (1u << b) - 1u;
+        const uint32_t e = popc64(ballot(R.da > thr)) + popc64(ballot(R.db > thr));
         if (10u * e > S.m) break;
         const uint32_t h = e ? S.wmin - (uint32_t)b : 0u;
         const uint32_t w = cdiv32(S.m * (uint32_t)b, 32) + cdiv32(e, 4) + cdiv32(e * h, 32);
@@ -383,6 +385,7 @@ struct EncArgs {
     uint64_t *seg_byte_off;
     Plan p;
     uint32_t *err;
+    uint32_t strided;       // unit order of the staged pack pass (else contiguous per wave)
 };
 
 // Segment and metadata of one encoder tile.
@@ -410,31 +413,22 @@ __device__ __forceinline__ EncTile enc_tile_meta(const Plan &p, const uint64_t *
     return m;
 }
 
-// A workgroup's contiguous share [tb, te) of the tiles: consecutive tiles
-// mostly share a segment, so segment bounds are searched once per
-// workgroup and then walked forward.
-__device__ __forceinline__ void tile_range(uint32_t total, uint32_t &tb, uint32_t &te) {
-    const uint64_t G = gridDim.x, b = blockIdx.x;
-    tb = (uint32_t)(b * total / G);
-    te = (uint32_t)((b + 1) * total / G);
-}
-
-// Tile sizes to offsets (one workgroup, after the pack pass): tile_off =
-// exclusive prefix of tile_words; the batch end goes to seg_byte_off[nseg].
-__device__ void finish_offsets(const EncArgs &a, uint32_t total) {
+// Unit sizes to offsets (one workgroup, after the pack pass): unit_off =
+// exclusive prefix of unit_words; the batch end goes to seg_byte_off[nseg].
+__device__ void finish_offsets(const EncArgs &a, uint32_t units) {
     __shared__ uint32_t s_wt[16];
     __shared__ unsigned long long s_carry;
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t nthr = blockDim.x, nw = nthr >> 6;
-    constexpr uint32_t kPer = 16;  // tiles per thread per pass
+    constexpr uint32_t kPer = 16;  // units per thread per pass
     if (tid == 0) s_carry = 0;
     __syncthreads();
-    for (uint32_t base = 0; base < total; base += nthr * kPer) {
+    for (uint32_t base = 0; base < units; base += nthr * kPer) {
         uint32_t v[kPer];
         uint32_t sum = 0;
         const uint32_t t0 = base + tid * kPer;
-        if (t0 + kPer <= total) {
-            const uint4 *src = (const uint4 *)(a.p.tile_words + t0);
+        if (t0 + kPer <= units) {
+            const uint4 *src = (const uint4 *)(a.p.unit_words + t0);
 #pragma unroll
             for (uint32_t k = 0; k < kPer / 4; ++k) {
                 const uint4 x = src[k];
@@ -445,7 +439,7 @@ __device__ void finish_offsets(const EncArgs &a, uint32_t total) {
             }
         } else {
 #pragma unroll
-            for (uint32_t k = 0; k < kPer; ++k) v[k] = (t0 + k < total) ? a.p.tile_words[t0 + k] : 0u;
+            for (uint32_t k = 0; k < kPer; ++k) v[k] = (t0 + k < units) ? a.p.unit_words[t0 + k] : 0u;
         }
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) sum += v[k];
@@ -460,7 +454,7 @@ __device__ void finish_offsets(const EncArgs &a, uint32_t total) {
         uint64_t run = s_carry + wb + incl - sum;
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) {
-            if (t0 + k < total) a.p.tile_off[t0 + k] = run;
+            if (t0 + k < units) a.p.unit_off[t0 + k] = run;
             run += v[k];
         }
         __syncthreads();
@@ -476,94 +470,157 @@ __device__ void finish_offsets(const EncArgs &a, uint32_t total) {
     }
 }
 
-// Pack pass: analyse, choose and pack every block of a tile into the tile's
-// slot (directory words first, then the payloads in block order).
-template <int WAVES, bool SCANPACK>
-__global__ __launch_bounds__(WAVES * 64) void k_enc_pack(EncArgs a) {
-    constexpr int BPW = (int)kGroup / WAVES;  // blocks per wave per tile
-    __shared__ BlockInfo s_info[kGroup];
-    __shared__ uint32_t s_pref[kGroup];
-    __shared__ uint32_t s_buf[WAVES][132];
-    __shared__ uint32_t s_pj[SCANPACK ? WAVES : 1][128];
-    __shared__ uint32_t s_dj[SCANPACK ? WAVES : 1][128];
-    __shared__ EncTile s_tm[kMetaChunk];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t total = a.p.tile_base[a.nseg];
-    const uint32_t G = gridDim.x;
+// ORs a field (v < 2^32, at most 32 bits) into the LDS words at bit pos, the
+// spilled high part into the next word unconditionally (it is 0 when the
+// field does not cross a word boundary): no branches.
+__device__ __forceinline__ void or_field(uint32_t *buf, uint32_t pos, uint32_t v) {
+    const uint32_t wi = pos >> 5, sh = pos & 31;
+    atomicOr(&buf[wi], v << sh);
+    atomicOr(&buf[wi + 1], sh ? v >> (32 - sh) : 0u);
+}
 
-    for (uint32_t base = blockIdx.x; base < total; base += G * kMetaChunk) {
-    // tiles base, base + G, ... (strided for balance); their segments and
-    // metadata are resolved first, one thread per tile, all in flight at once
-    if (tid < kMetaChunk) {
-        const uint32_t t = base + tid * G;
-        if (t < total) s_tm[tid] = enc_tile_meta(a.p, a.seg_off, a.seg_lo, a.seg_hi, a.nseg, t);
+// Full block (128 IDs) whose class the encoder picks itself (plain minimal
+// width or exhaustive): the same choice as choose(), computed with scalar
+// selects, and bit-pack / bitmap payloads packed without branches.  A PFOR
+// choice (which always has exceptions) is packed by the general routine.
+__device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t lo, uint32_t hi,
+                                             bool exhaustive, uint32_t *dir, uint32_t *dst,
+                                             uint32_t *buf, uint32_t lane, uint32_t *err) {
+    constexpr uint32_t m = kBlock - 1;
+    const uint32_t a63 = readlane(va, 63);
+    const uint32_t pa = lane_prev(va, 0u);
+    const uint32_t pb = lane_prev(vb, a63);
+    const uint32_t da = lane ? va - pa : 0u;
+    const uint32_t db = vb - pb;
+    const uint32_t v0 = readlane(va, 0), vlast = readlane(vb, 63);
+    // strictly increasing, then first >= lo and last < hi bound every value
+    const uint64_t bad = ballot((lane != 0) & (va <= pa)) | ballot(vb <= pb);
+    if ((bad != 0ull) | (v0 < lo) | (vlast >= hi)) {
+        if (lane == 0) raise_err(err, kErrInval);
     }
-    __syncthreads();
-    for (uint32_t it = 0; it < kMetaChunk; ++it) {
-        const uint32_t t = base + it * G;
-        if (t >= total) break;
-        const EncTile m = s_tm[it];
-        const uint32_t nb = m.nb, n = m.n, lo = m.lo, hi = m.hi, bb = m.bb;
-        const uint32_t *ids = a.ids + m.id_base;
-        const uint32_t g = m.g;
-        const uint32_t k0 = g * kGroup;
-        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
-        uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-
-        // issue every load of this wave's blocks first
-        uint32_t va[BPW], vb[BPW];
-#pragma unroll
-        for (int i = 0; i < BPW; ++i) {
-            const uint32_t kk = w + (uint32_t)i * WAVES;
-            const uint32_t k = k0 + kk;
-            const uint32_t nk = kk < nblk ? min(kBlock, n - k * kBlock) : 0u;
-            fetch_block(ids + (uint64_t)k * kBlock, nk, lane, va[i], vb[i]);
+    const uint32_t wmin = bitlen32(wave_max(max(da, db)));
+    const uint32_t span = vlast - v0;
+    const uint32_t bpw = (m * wmin + 31) >> 5;
+    uint32_t cls = 1 + wmin, param = wmin, aux = 0, words = bpw;
+    uint32_t pfb = wmin, pfe = 0;
+    if (exhaustive) {
+        const uint32_t bmw = (span + 31) >> 5;
+        if ((span <= kBitmapMaxSpan) & (bmw < words)) {
+            cls = kClsBitmap;
+            param = 0;
+            aux = span;
+            words = bmw;
         }
-        BlockRegs R[BPW];
-        BlockStats S[BPW];
-        BlockInfo I[BPW];
-#pragma unroll
-        for (int i = 0; i < BPW; ++i) {
-            const uint32_t kk = w + (uint32_t)i * WAVES;
-            if (kk < nblk) {
-                const uint32_t k = k0 + kk;
-                const uint32_t nk = min(kBlock, n - k * kBlock);
-                analyze_block(va[i], vb[i], nk, lo, hi, lane, false, R[i], S[i], a.err);
-                const int given = a.classes ? (int)a.classes[bb + k] : -1;
-                I[i] = choose(R[i], S[i], a.mode, given, a.err);
-                I[i].first = S[i].v0 - lo;
-                if (lane == 0) s_info[kk] = I[i];
+        // PFOR: fewest words with 10 E <= m (E <= 12), ties to the larger b.
+        // A width b < wmin has E >= 1, so it costs at least ceil(m b / 32) + 2
+        // words: widths whose bound reaches the best so far cannot be chosen
+        // and are skipped (b <= (32 (words - 3)) / m is the largest candidate).
+        uint32_t best = bpw;
+        const uint32_t bcap = words >= 3 ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
+        uint32_t low = m * bcap, h = wmin - bcap;
+        for (uint32_t b = bcap; b-- > 0;) {
+            low -= m;
+            ++h;
+            const uint32_t thr = (1u << b) - 1u;
+            const uint32_t e = popc64(ballot(da > thr)) + popc64(ballot(db > thr));
+            if (e > m / 10) break;
+            const uint32_t wd = ((low + 31) >> 5) + ((e + 3) >> 2) + ((e * h + 31) >> 5);
+            if (wd < best) {
+                best = wd;
+                pfb = b;
+                pfe = e;
             }
         }
-        __syncthreads();
-        if (w == 0) {
-            const uint32_t wv = lane < nblk ? s_info[lane].words : 0u;
-            const uint32_t incl = wave_incl_scan(wv);
-            if (lane < kGroup) s_pref[lane] = incl - wv;
-            if (lane == 63) a.p.tile_words[t] = incl;
+        if (best < words) {
+            cls = kClsPfor;
+            param = pfb;
+            aux = pfe | ((wmin - pfb) << 8);
+            words = best;
         }
-        if (tid < 2 * nblk) {
-            const BlockInfo &bi = s_info[tid >> 1];
-            slot[tid] = (tid & 1) ? (bi.cls | (bi.param << 8) | (bi.aux << 16)) : bi.first;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < BPW; ++i) {
-            const uint32_t kk = w + (uint32_t)i * WAVES;
-            if (kk < nblk && I[i].words) {
-                if constexpr (SCANPACK)
-                    pack_block_scan(s_buf[w], s_pj[w], s_dj[w], I[i], R[i], S[i], lane);
-                else
-                    pack_block(s_buf[w], I[i], R[i], S[i], lane);
-                uint32_t *dst = slot + kSlotDirWords + s_pref[kk];
-                if (lane < I[i].words) dst[lane] = s_buf[w][lane];
-                if (lane + 64 < I[i].words) dst[lane + 64] = s_buf[w][lane + 64];
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        __syncthreads();
     }
+    if (lane < 2) dir[lane] = lane ? (cls | (param << 8) | (aux << 16)) : v0 - lo;
+    buf[lane] = 0u;
+    buf[lane + 64] = 0u;
+    if (lane < 4) buf[128 + lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (cls == kClsPfor) {
+        BlockRegs R;
+        R.da = da;
+        R.db = db;
+        R.oa = va - v0;
+        R.ob = vb - v0;
+        R.hasa = lane >= 1;
+        R.hasb = true;
+        BlockStats S;
+        S.nk = kBlock;
+        S.m = m;
+        S.v0 = v0;
+        S.span = span;
+        S.dmin = 0;
+        S.dmax = 0;
+        S.wmin = wmin;
+        BlockInfo I;
+        I.cls = cls;
+        I.param = param;
+        I.aux = aux;
+        I.words = words;
+        I.first = 0;
+        pack_block(buf, I, R, S, lane);
+    } else if (cls == kClsBitmap) {
+        // bit o-1 for offset o = v - v0 >= 1 (the first value is implied); the
+        // word index is kept inside the buffer even for unsorted input,
+        // which has already been flagged as invalid
+        const uint32_t oa = va - v0, ob = vb - v0;
+        const uint32_t qa = oa ? oa - 1 : 0u, qb = ob - 1;
+        atomicOr(&buf[(qa >> 5) & 127], oa ? 1u << (qa & 31) : 0u);
+        atomicOr(&buf[(qb >> 5) & 127], 1u << (qb & 31));
+    } else {
+        // field of delta j at bit (j-1) w: lane l carries deltas l (none for
+        // l = 0, whose delta is 0) and 64+l
+        or_field(buf, (lane ? lane - 1 : 0u) * param, da);
+        or_field(buf, (63 + lane) * param, db);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t wa = buf[lane], wb = buf[lane + 64];
+    if (lane < words) dst[lane] = wa;
+    if (lane + 64 < words) dst[lane + 64] = wb;
+    return words;
+}
+
+// Analyses, chooses and packs one block held by the wave (value index l in
+// va, 64+l in vb of lane l); writes its directory entry to dir[0..1] and its
+// payload words to dst; returns the payload words.  FULL: a block of exactly
+// 128 IDs (all but the last block of a segment), where every per-lane
+// validity test folds away at compile time.
+template <bool FULL, bool SCANPACK>
+__device__ __forceinline__ uint32_t enc_block(uint32_t va, uint32_t vb, uint32_t nk, uint32_t lo,
+                                              uint32_t hi, int mode, int given, uint32_t *dir,
+                                              uint32_t *dst, uint32_t *buf, uint32_t *pj, uint32_t *dj,
+                                              uint32_t lane, uint32_t *err) {
+    if constexpr (FULL) {
+        if (given < 0 && !SCANPACK)
+            return enc_full(va, vb, lo, hi, mode != BFSC_SEL_PLAIN_BP, dir, dst, buf, lane, err);
+        nk = kBlock;
+    } else {
+        nk = readfirst(nk);
+    }
+    BlockRegs R;
+    BlockStats S;
+    analyze_block(va, vb, nk, lo, hi, lane, false, R, S, err);
+    const BlockInfo I = choose(R, S, mode, given, err);
+    if (lane < 2) dir[lane] = lane ? (I.cls | (I.param << 8) | (I.aux << 16)) : S.v0 - lo;
+    if (I.words) {
+        if constexpr (SCANPACK)
+            pack_block_scan(buf, pj, dj, I, R, S, lane);
+        else
+            pack_block(buf, I, R, S, lane);
+        if (lane < I.words) dst[lane] = buf[lane];
+        if (lane + 64 < I.words) dst[lane + 64] = buf[lane + 64];
+        __builtin_amdgcn_wave_barrier();
+    }
+    return I.words;
 }
 
 // Last r < n with base[r] <= t (base non-decreasing, base[0] <= t), found by
@@ -581,125 +638,185 @@ __device__ __forceinline__ uint32_t wave_find(const uint32_t *base, uint32_t n, 
         lo = lo + k * step;
         hi = min(hi, lo + step);
     }
-    return lo;
+    return readfirst(lo);
 }
 
-// Pack pass, one wave per tile: the wave walks the tile's blocks in order,
-// prefetching the next block while it analyses, chooses and packs the
-// current one, and keeps the running payload offset itself -- no
-// workgroup barriers and no per-tile scan.
-template <int WAVES, bool SCANPACK>
-__global__ __launch_bounds__(WAVES * 64) void k_enc_pack_w(EncArgs a) {
+// Units a wave handles: a contiguous run (consecutive units mostly share a
+// segment, so the segment is found once and then walked forward) or every
+// NW-th unit.
+struct UnitRange {
+    uint32_t begin, end, step;
+};
+__device__ __forceinline__ UnitRange unit_range(uint32_t units, uint32_t waves, uint32_t w, bool strided) {
+    const uint64_t W = (uint64_t)blockIdx.x * waves + w, NW = (uint64_t)gridDim.x * waves;
+    UnitRange ur;
+    if (strided) {
+        ur.begin = (uint32_t)W;
+        ur.end = units;
+        ur.step = (uint32_t)NW;
+    } else {
+        ur.begin = (uint32_t)(W * units / NW);
+        ur.end = (uint32_t)((W + 1) * units / NW);
+        ur.step = 1;
+    }
+    return ur;
+}
+
+// The segment of the current tile and its fields, kept across the units of
+// a wave.  seek() returns true when the segment changed (fields to reload).
+struct SegCursor {
+    uint32_t r = 0, t_first = 0, t_next = 0;
+    bool have = false;
+    uint32_t bb = 0, nb = 0, n = 0, lo = 0, hi = 0;
+    uint64_t base = 0, S = 0, bytes = 0;
+    __device__ __forceinline__ bool seek(const uint32_t *tile_base, uint32_t nseg, uint32_t t, uint32_t lane,
+                                         bool jump) {
+        if (have && t < t_next) return false;
+        if (!have || jump) {
+            r = wave_find(tile_base, nseg, t, lane);
+            t_next = readfirst(tile_base[r + 1]);
+        } else {
+            while (t >= t_next) {
+                ++r;
+                t_next = readfirst(tile_base[r + 1]);
+            }
+        }
+        t_first = readfirst(tile_base[r]);
+        have = true;
+        return true;
+    }
+};
+
+// Pack pass, one wave per unit (half a tile: up to 8 blocks, 1024 IDs), the
+// units being small enough that every wave gets several and none is left
+// working alone at the end.  STAGE: the wave first stages the unit's IDs in
+// LDS with every load in flight at once; otherwise it loads block by block,
+// the next block's load in flight while the current one is packed.  Either
+// way it analyses, chooses and packs the blocks in order into the unit's half
+// of the tile's slot.
+template <int WAVES, bool SCANPACK, bool STAGE>
+__global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
+    constexpr uint32_t kIds = kHalf * kBlock;
+    constexpr uint32_t kPerLane = kIds / 64;
+    __shared__ uint32_t s_ids[STAGE ? WAVES : 1][STAGE ? kIds : 1];
     __shared__ uint32_t s_buf[WAVES][132];
     __shared__ uint32_t s_pj[SCANPACK ? WAVES : 1][128];
     __shared__ uint32_t s_dj[SCANPACK ? WAVES : 1][128];
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t total = a.p.tile_base[a.nseg];
-    const uint32_t nw = gridDim.x * WAVES;
-    for (uint32_t t = blockIdx.x * WAVES + w; t < total; t += nw) {
-        const uint32_t r = wave_find(a.p.tile_base, a.nseg, t, lane);
-        const uint32_t g = t - a.p.tile_base[r];
-        const uint32_t bb = a.p.blk_base[r];
-        const uint32_t nb = a.p.blk_base[r + 1] - bb;
-        const uint32_t n = a.p.seg_n[r];
-        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
-        const uint32_t *ids = a.ids + a.seg_off[r];
-        const uint32_t k0 = g * kGroup;
-        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
-        uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-        uint32_t run = 0;  // payload words of the tile so far
-        uint32_t va = 0, vb = 0;
-        if (nblk) fetch_block(ids + (uint64_t)k0 * kBlock, min(kBlock, n - k0 * kBlock), lane, va, vb);
-        for (uint32_t kk = 0; kk < nblk; ++kk) {
-            const uint32_t k = k0 + kk;
-            const uint32_t nk = min(kBlock, n - k * kBlock);
-            uint32_t na = 0, nbv = 0;
-            if (kk + 1 < nblk)
-                fetch_block(ids + (uint64_t)(k + 1) * kBlock, min(kBlock, n - (k + 1) * kBlock), lane, na, nbv);
-            BlockRegs R;
-            BlockStats S;
-            analyze_block(va, vb, nk, lo, hi, lane, false, R, S, a.err);
-            const int given = a.classes ? (int)a.classes[bb + k] : -1;
-            BlockInfo I = choose(R, S, a.mode, given, a.err);
-            if (lane < 2)
-                slot[2 * kk + lane] = lane ? (I.cls | (I.param << 8) | (I.aux << 16)) : S.v0 - lo;
-            if (I.words) {
-                if constexpr (SCANPACK)
-                    pack_block_scan(s_buf[w], s_pj[w], s_dj[w], I, R, S, lane);
-                else
-                    pack_block(s_buf[w], I, R, S, lane);
-                uint32_t *dst = slot + kSlotDirWords + run;
-                if (lane < I.words) dst[lane] = s_buf[w][lane];
-                if (lane + 64 < I.words) dst[lane + 64] = s_buf[w][lane + 64];
+    const uint32_t units = 2 * readfirst(a.p.tile_base[a.nseg]);
+    uint32_t *sid = s_ids[STAGE ? w : 0];
+    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    SegCursor c;
+    for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
+        const uint32_t t = u >> 1, h = u & 1;
+        if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
+            c.bb = readfirst(a.p.blk_base[c.r]);
+            c.nb = readfirst(a.p.blk_base[c.r + 1]) - c.bb;
+            c.n = readfirst(a.p.seg_n[c.r]);
+            c.lo = readfirst(a.seg_lo[c.r]);
+            c.hi = readfirst(a.seg_hi[c.r]);
+            c.base = readfirst64(a.seg_off[c.r]);
+        }
+        const uint32_t g = t - c.t_first;
+        const uint32_t bb = c.bb, nb = c.nb;
+        const uint32_t k0 = g * kGroup + h * kHalf;
+        const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
+        uint32_t run = 0;  // payload words of the unit so far
+        if (nblk) {
+            const uint32_t n = c.n;
+            const uint32_t lo = c.lo, hi = c.hi;
+            const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
+            const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+            const uint32_t cl = a.classes && lane < nblk ? (uint32_t)a.classes[bb + k0 + lane] : 0u;
+            uint32_t va = 0, vb = 0;
+            if constexpr (STAGE) {
+                uint32_t v[kPerLane];
+#pragma unroll
+                for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
+#pragma unroll
+                for (uint32_t i = 0; i < kPerLane; ++i) sid[lane + 64 * i] = v[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
+            } else {
+                fetch_block(src, min(kBlock, cnt), lane, va, vb);
             }
-            run += I.words;
-            va = na;
-            vb = nbv;
+            uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+            uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
+            for (uint32_t kk = 0; kk < nblk; ++kk) {
+                const uint32_t nk = min(kBlock, cnt - kk * kBlock);
+                uint32_t na = 0, nbv = 0;
+                if constexpr (STAGE) {
+                    va = sid[kk * kBlock + lane];
+                    vb = sid[kk * kBlock + 64 + lane];
+                } else if (kk + 1 < nblk) {
+                    fetch_block(src + (kk + 1) * kBlock, min(kBlock, cnt - (kk + 1) * kBlock), lane, na, nbv);
+                }
+                const int given = a.classes ? (int)readlane(cl, kk) : -1;
+                uint32_t *dir = slot + 2 * (h * kHalf + kk), *dst = pay + run;
+                run += nk == kBlock
+                           ? enc_block<true, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, dir, dst, s_buf[w],
+                                                       s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane, a.err)
+                           : enc_block<false, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, dir, dst, s_buf[w],
+                                                        s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane, a.err);
+                if constexpr (!STAGE) {
+                    va = na;
+                    vb = nbv;
+                }
+            }
         }
-        if (lane == 0) a.p.tile_words[t] = run;
+        if (lane == 0) a.p.unit_words[u] = run;
     }
 }
 
-// One workgroup: tile sizes -> offsets, segment starts and headers.
+// One workgroup: unit sizes -> offsets and the batch end.
 __global__ __launch_bounds__(1024) void k_enc_scan(EncArgs a) {
-    finish_offsets(a, a.p.tile_base[a.nseg]);
+    finish_offsets(a, 2 * a.p.tile_base[a.nseg]);
 }
 
-// Place pass: every segment's header and start offset (by its first tile),
-// then every tile's directory entries, group-table entry and payload words,
-// copied from its slot to the final position.
-__global__ __launch_bounds__(256) void k_enc_place(EncArgs a) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t total = a.p.tile_base[a.nseg];
+// Place pass, one wave per tile (tiles are independent, so every wave's
+// chain of dependent loads runs in parallel with all others): the segment's
+// header and start offset (written by its first tile), then the tile's
+// directory entries, group-table entry and payload words, copied from the
+// two halves of its slot to their final position.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t total = readfirst(a.p.tile_base[a.nseg]);
+    const uint32_t t = blockIdx.x * WAVES + w;
+    if (t >= total) return;
     const uint64_t capw = a.out_cap >> 2;
-    uint32_t tb, te;
-    tile_range(total, tb, te);
-    if (tb >= te) return;
-    uint32_t r = upper_bound_m1(a.p.tile_base, a.nseg, tb);
-    uint32_t t_first = a.p.tile_base[r], t_next = a.p.tile_base[r + 1];
-    uint32_t nb = 0, ng = 0;
-    uint64_t P = 0, sw = 0;
-    bool fresh = true;
-    for (uint32_t t = tb; t < te; ++t) {
-        while (t >= t_next) {
-            ++r;
-            t_first = t_next;
-            t_next = a.p.tile_base[r + 1];
-            fresh = true;
+    const uint32_t r = wave_find(a.p.tile_base, a.nseg, t, lane);
+    const uint32_t t_first = readfirst(a.p.tile_base[r]);
+    const uint32_t bb = readfirst(a.p.blk_base[r]);
+    const uint32_t nb = readfirst(a.p.blk_base[r + 1]) - bb;
+    const uint32_t gb = readfirst(a.p.grp_base[r]);
+    const uint32_t ng = readfirst(a.p.grp_base[r + 1]) - gb;
+    const uint64_t P = readfirst64(a.p.unit_off[2 * t_first]);
+    const uint64_t sw = (16ull * r + 8ull * bb + 4ull * gb + 4ull * P) >> 2;
+    const uint32_t g = t - t_first;
+    if (g == 0 && lane < 4) {
+        if (lane == 0) a.seg_byte_off[r] = sw << 2;
+        if (sw + 4 <= capw) {
+            const uint32_t hv = lane == 0 ? a.p.seg_n[r] : lane == 1 ? a.seg_lo[r] : lane == 2 ? a.seg_hi[r] : kMagic;
+            a.out[sw + lane] = hv;
         }
-        if (fresh) {
-            nb = a.p.blk_base[r + 1] - a.p.blk_base[r];
-            ng = a.p.grp_base[r + 1] - a.p.grp_base[r];
-            P = a.p.tile_off[t_first];
-            const uint64_t Sr = 16ull * r + 8ull * a.p.blk_base[r] + 4ull * a.p.grp_base[r] + 4ull * P;
-            sw = Sr >> 2;
-            fresh = false;
-        }
-        const uint32_t g = t - t_first;
-        if (g == 0 && tid < 4) {
-            if (tid == 0) a.seg_byte_off[r] = sw << 2;
-            if (sw + 4 <= capw) {
-                const uint32_t hv = tid == 0 ? a.p.seg_n[r] : tid == 1 ? a.seg_lo[r] : tid == 2 ? a.seg_hi[r] : kMagic;
-                a.out[sw + tid] = hv;
-            }
-        }
-        const uint32_t k0 = g * kGroup;
-        const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
-        if (!nblk) continue;
-        const uint64_t rel = a.p.tile_off[t] - P;
-        const uint32_t A = a.p.tile_words[t];
-        const uint64_t pwb = sw + 4 + 2ull * nb + ng + rel;
-        const uint64_t dwb = sw + 4 + 2ull * k0;
-        if (pwb + A > capw || sw + 4 + 2ull * nb + ng > capw) {
-            if (tid == 0) raise_err(a.err, kErrCapacity);
-            continue;
-        }
-        const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-        if (tid < 2 * nblk) a.out[dwb + tid] = slot[tid];
-        if (tid == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)rel;
-        for (uint32_t q = tid; q < A; q += blockDim.x) a.out[pwb + q] = slot[kSlotDirWords + q];
     }
+    const uint32_t k0 = g * kGroup;
+    const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
+    if (!nblk) return;
+    const uint64_t rel = readfirst64(a.p.unit_off[2 * t]) - P;
+    const uint32_t A0 = readfirst(a.p.unit_words[2 * t]), A1 = readfirst(a.p.unit_words[2 * t + 1]);
+    const uint64_t pwb = sw + 4 + 2ull * nb + ng + rel;
+    const uint64_t dwb = sw + 4 + 2ull * k0;
+    if (pwb + A0 + A1 > capw || sw + 4 + 2ull * nb + ng > capw) {
+        if (lane == 0) raise_err(a.err, kErrCapacity);
+        return;
+    }
+    const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+    if (lane < 2 * nblk) a.out[dwb + lane] = slot[lane];
+    if (lane == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)rel;
+    for (uint32_t q = lane; q < A0; q += 64) a.out[pwb + q] = slot[kSlotDirWords + q];
+    for (uint32_t q = lane; q < A1; q += 64) a.out[pwb + A0 + q] = slot[kSlotDirWords + kSlotHalfWords + q];
 }
 
 // ------------------------------------------------------------------ select / features
@@ -954,12 +1071,6 @@ __global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
     }
 }
 
-// Segment and header fields of one decoder tile.
-struct DecTile {
-    uint64_t S, bytes, oo;
-    uint32_t n, g, lo, hi;
-};
-
 struct DecArgs {
     const uint8_t *in;
     const uint64_t *seg_byte_off;
@@ -970,6 +1081,7 @@ struct DecArgs {
     uint32_t *out;
     uint64_t out_cap;
     uint32_t *err;
+    uint32_t strided;       // unit order of the staged decoder (else contiguous per wave)
 };
 
 // w-bit field at bit pos of the staged words (funnel shift of two words).
@@ -986,222 +1098,46 @@ __device__ __forceinline__ uint32_t block_words(uint32_t cls, uint32_t param, ui
     return cdiv32(m * param, 32) + cdiv32(E, 4) + cdiv32(E * (aux >> 8), 32);
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_decode(DecArgs a) {
-    constexpr int BPW = (int)kGroup / WAVES;
-    __shared__ uint32_t s_cls[kGroup], s_param[kGroup], s_aux[kGroup], s_first[kGroup + 1];
-    __shared__ uint32_t s_off[kGroup], s_words[kGroup];
-    __shared__ uint32_t s_ok;
-    __shared__ uint32_t s_buf[WAVES][132];
-    __shared__ uint32_t s_val[WAVES][128];
-    __shared__ DecTile s_tm[kMetaChunk];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t total = a.tile_base[a.nseg];
-    const uint32_t G = gridDim.x;
-    for (uint32_t base = blockIdx.x; base < total; base += G * kMetaChunk) {
-    // strided tiles; segment lookups and header reads of the chunk first,
-    // one thread per tile (segments without tiles never match a tile)
-    if (tid < kMetaChunk) {
-        const uint32_t t = base + tid * G;
-        if (t < total) {
-            const uint32_t r = upper_bound_m1(a.tile_base, a.nseg, t);
-            DecTile m;
-            m.g = t - a.tile_base[r];
-            m.n = a.seg_n[r];
-            m.S = a.seg_byte_off[r];
-            m.bytes = a.seg_byte_off[r + 1] - m.S;
-            m.oo = a.out_off[r];
-            const uint32_t *h = (const uint32_t *)(a.in + m.S);
-            m.lo = h[1];
-            m.hi = h[2];
-            s_tm[tid] = m;
-        }
-    }
-    __syncthreads();
-    for (uint32_t it = 0; it < kMetaChunk; ++it) {
-        const uint32_t t = base + it * G;
-        if (t >= total) break;
-        const DecTile m = s_tm[it];
-        const uint32_t n = m.n, lo = m.lo, hi = m.hi;
-        const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
-        const uint32_t *seg = (const uint32_t *)(a.in + m.S);
-        const uint32_t metaw = 4 + 2 * nb + ng;
-        const uint64_t availw = m.bytes / 4 - metaw;
-        const uint64_t oo = m.oo;
-        const uint32_t g = m.g;
-        const uint32_t k0 = g * kGroup;
-        const uint32_t nblk = min(kGroup, nb - k0);
-        if (w == 0) {
-            bool bad = false;
-            uint32_t words = 0;
-            if (lane <= nblk && k0 + lane < nb) {
-                const uint32_t e0 = seg[4 + 2 * (k0 + lane)], e1 = seg[4 + 2 * (k0 + lane) + 1];
-                s_first[lane] = e0;
-                if (lane < nblk) {
-                    const uint32_t cls = e1 & 0xFFu, param = (e1 >> 8) & 0xFFu, aux = e1 >> 16;
-                    const uint32_t k = k0 + lane;
-                    const uint32_t nk = min(kBlock, n - k * kBlock), m = nk - 1;
-                    if (cls == kClsBitmap) {
-                        bad = param != 0 || aux > kBitmapMaxSpan;
-                    } else if (cls <= 33) {
-                        bad = param != cls - 1 || aux != 0;
-                    } else if (cls == kClsPfor) {
-                        const uint32_t E = aux & 0xFFu, h = aux >> 8;
-                        bad = param > 32 || param + h > 32 || 10 * E > m;
-                    } else {
-                        bad = true;
-                    }
-                    words = bad ? 0u : block_words(cls, param, aux, m);
-                    bad |= words > kBlock;
-                    s_cls[lane] = cls;
-                    s_param[lane] = param;
-                    s_aux[lane] = aux;
-                    s_words[lane] = words;
-                    // first value inside [lo, hi)
-                    bad |= (uint64_t)lo + e0 >= (uint64_t)hi;
-                }
-            }
-            const uint32_t incl = wave_incl_scan(lane < nblk ? words : 0u);
-            const uint32_t A = readlane(incl, 63);
-            const uint32_t gt = seg[4 + 2 * nb + g];
-            if (lane < nblk) s_off[lane] = gt + incl - words;
-            bool ok = ballot(bad) == 0ull;
-            ok = ok && (uint64_t)gt + A <= availw;
-            if (g + 1 < ng) ok = ok && seg[4 + 2 * nb + g + 1] == gt + A;
-            else ok = ok && (uint64_t)gt + A == availw;
-            if (lane == 0) {
-                s_ok = ok ? 1u : 0u;
-                if (!ok) raise_err(a.err, kErrCorrupt);
-            }
-        }
-        __syncthreads();
-        if (s_ok) {
-            const uint32_t *pay = seg + metaw;
-            // issue the payload loads of all of this wave's blocks first
-            uint32_t pa[BPW], pb[BPW];
-#pragma unroll
-            for (int i = 0; i < BPW; ++i) {
-                const uint32_t kk = w + (uint32_t)i * WAVES;
-                const uint32_t words = kk < nblk ? s_words[kk] : 0u;
-                const uint32_t *src = pay + (kk < nblk ? s_off[kk] : 0u);
-                pa[i] = lane < words ? src[lane] : 0u;
-                pb[i] = lane + 64 < words ? src[lane + 64] : 0u;
-            }
-#pragma unroll
-            for (int i = 0; i < BPW; ++i) {
-                const uint32_t kk = w + (uint32_t)i * WAVES;
-                if (kk >= nblk) continue;
-                const uint32_t k = k0 + kk;
-                const uint32_t nk = min(kBlock, n - k * kBlock), m = nk - 1;
-                const uint32_t cls = s_cls[kk], param = s_param[kk], aux = s_aux[kk];
-                const uint32_t v0 = lo + s_first[kk];
-                uint32_t *buf = s_buf[w];
-                uint32_t *val = s_val[w];
-                buf[lane] = pa[i];
-                buf[lane + 64] = pb[i];
-                if (lane < 4) buf[128 + lane] = 0u;
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                bool bad = false;
-                uint32_t xa = 0, xb = 0;  // decoded values
-                const bool ina = lane < nk, inb = lane + 64 < nk;
-                if (cls == kClsBitmap) {
-                    // 64 candidate positions per step; set bits are ranked
-                    // with a ballot and written to their output slots
-                    const uint32_t nch = (aux + 63) >> 6;
-                    uint32_t cnt = 1;
-                    if (lane == 0) val[0] = v0;
-                    for (uint32_t c = 0; c < nch; ++c) {
-                        const uint32_t word = lane < 32 ? buf[2 * c] : buf[2 * c + 1];
-                        const bool set = (word >> (lane & 31)) & 1u;
-                        const uint64_t mk = ballot(set);
-                        const uint32_t rank = popc64(mk & lanemask_lt());
-                        if (set && cnt + rank < 128) val[cnt + rank] = v0 + 64 * c + lane + 1;
-                        cnt += popc64(mk);
-                    }
-                    // bits beyond the span must be clear, and there must be m of them
-                    const uint32_t tailw = aux >> 5, tailb = aux & 31;
-                    bad |= tailb && lane == 0 && (buf[tailw] >> tailb) != 0u;
-                    bad |= cnt - 1 != m;
-                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    xa = val[lane];
-                    xb = val[lane + 64];
-                    // the last value, checked in 64 bits (no wrap)
-                    if (cnt - 1 == m) {
-                        const uint32_t lastv = m ? (nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65)) : v0;
-                        bad |= (uint64_t)v0 + (lastv - v0) >= (uint64_t)hi;
-                    }
-                } else {
-                    const uint32_t b = cls <= 33 ? cls - 1 : param;
-                    const uint32_t ja = lane, jb = 64 + lane;
-                    uint32_t da = (ina && ja >= 1 && b) ? get_field(buf, (ja - 1) * b, b) : 0u;
-                    uint32_t db = (inb && b) ? get_field(buf, (jb - 1) * b, b) : 0u;
-                    if (cls == kClsPfor) {
-                        const uint32_t E = aux & 0xFFu, h = aux >> 8;
-                        const uint32_t lw = cdiv32(m * b, 32), qw = cdiv32(E, 4);
-                        val[lane] = 0u;
-                        val[lane + 64] = 0u;
-                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        uint32_t p = 0;
-                        if (lane < E) {
-                            p = (buf[lw + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu;
-                            const uint32_t hv = h ? get_field(buf + lw + qw, lane * h, h) : 0u;
-                            if (p < m) val[p + 1] = b >= 32 ? 0u : (hv << b);
-                        }
-                        const uint32_t pp = lane_prev(p, 0u);
-                        bad |= lane < E && (p >= m || (lane > 0 && p <= pp));
-                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        da |= val[lane];
-                        db |= val[lane + 64];
-                    }
-                    bad |= (ina && ja >= 1 && da == 0) || (inb && db == 0);
-                    const uint32_t sa = wave_incl_scan(da);
-                    const uint32_t ta = readlane(sa, 63);
-                    const uint32_t sb = wave_incl_scan(db) + ta;
-                    xa = v0 + sa;
-                    xb = v0 + sb;
-                    // a wrap shows as a decrease against the previous value
-                    const uint32_t a63 = readlane(xa, 63);
-                    const uint32_t prva = lane_prev(xa, 0u);
-                    const uint32_t prvb = lane_prev(xb, a63);
-                    bad |= (ina && lane >= 1 && xa <= prva) || (inb && xb <= prvb);
-                }
-                // last value below hi and below the next block's first value
-                const uint32_t last = nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65);
-                const bool has_next = k + 1 < nb;
-                const uint32_t nxt = has_next ? lo + s_first[kk + 1] : 0u;
-                bad |= last >= hi || (has_next && last >= nxt);
-                if (ballot(bad) != 0ull) {
-                    if (lane == 0) raise_err(a.err, kErrCorrupt);
-                } else {
-                    const uint64_t ob = oo + (uint64_t)k * kBlock;
-                    if (ina && ob + lane < a.out_cap) a.out[ob + lane] = xa;
-                    if (inb && ob + 64 + lane < a.out_cap) a.out[ob + 64 + lane] = xb;
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        __syncthreads();
-    }
-    }
-}
-
-// Decodes and validates one block whose payload words are pa (word lane) and
-// pb (word 64+lane); writes its IDs to out[ob ..] unless it is damaged.
-__device__ __forceinline__ void decode_one_block(uint32_t *buf, uint32_t *val, uint32_t pa, uint32_t pb,
+// Decodes and validates one block whose bw payload words start at buf (LDS;
+// words past bw may hold anything and are never taken as payload); writes
+// its IDs to out[ob ..] unless it is damaged.
+// FULL: a block of exactly 128 IDs, where every per-lane validity test folds
+// away at compile time.
+template <bool FULL>
+__device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t bw, uint32_t *val,
                                                  uint32_t cls, uint32_t param, uint32_t aux,
                                                  uint32_t v0, uint32_t nk, uint32_t hi, bool has_next,
                                                  uint32_t nxt, uint32_t *out, uint64_t ob,
                                                  uint64_t out_cap, uint32_t *err, uint32_t lane) {
+    if constexpr (FULL) {
+        nk = kBlock;
+        if (cls >= 2 && cls <= 25) {
+            // bit-pack, width 1..24: 127 deltas sum to under 2^31, so the
+            // 32-bit prefix sums cannot wrap; with every delta >= 1 the IDs
+            // increase, and only the last one has to be checked (in 64 bits)
+            const uint32_t w = cls - 1;
+            const uint32_t da = lane ? get_field(buf, (lane - 1) * w, w) : 0u;
+            const uint32_t db = get_field(buf, (63 + lane) * w, w);
+            const uint64_t zero = ballot((lane != 0) & (da == 0u)) | ballot(db == 0u);
+            const uint32_t sa = wave_incl_scan(da);
+            const uint32_t sb = wave_incl_scan(db) + readlane(sa, 63);
+            const uint64_t last = (uint64_t)v0 + readlane(sb, 63);
+            if ((zero != 0ull) | (last >= hi) | (has_next & (last >= nxt))) {
+                if (lane == 0) raise_err(err, kErrCorrupt);
+            } else if (ob + kBlock <= out_cap) {
+                out[ob + lane] = v0 + sa;
+                out[ob + 64 + lane] = v0 + sb;
+            } else {
+                if (ob + lane < out_cap) out[ob + lane] = v0 + sa;
+                if (ob + 64 + lane < out_cap) out[ob + 64 + lane] = v0 + sb;
+            }
+            __builtin_amdgcn_wave_barrier();
+            return;
+        }
+    } else {
+        nk = readfirst(nk);
+    }
     const uint32_t m = nk - 1;
-    buf[lane] = pa;
-    buf[lane + 64] = pb;
-    if (lane < 4) buf[128 + lane] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
     bool bad = false;
     uint32_t xa = 0, xb = 0;
     const bool ina = lane < nk, inb = lane + 64 < nk;
@@ -1210,7 +1146,8 @@ __device__ __forceinline__ void decode_one_block(uint32_t *buf, uint32_t *val, u
         uint32_t cnt = 1;
         if (lane == 0) val[0] = v0;
         for (uint32_t c = 0; c < nch; ++c) {
-            const uint32_t word = lane < 32 ? buf[2 * c] : buf[2 * c + 1];
+            const uint32_t wi = lane < 32 ? 2 * c : 2 * c + 1;
+            const uint32_t word = wi < bw ? buf[wi] : 0u;
             const bool set = (word >> (lane & 31)) & 1u;
             const uint64_t mk = ballot(set);
             const uint32_t rank = popc64(mk & lanemask_lt());
@@ -1275,39 +1212,68 @@ __device__ __forceinline__ void decode_one_block(uint32_t *buf, uint32_t *val, u
     __builtin_amdgcn_wave_barrier();
 }
 
-// Decode, one wave per tile: the wave reads and checks the tile's directory
-// entries (one lane per block), then decodes the blocks in order while the
-// next block's payload is already in flight.
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_decode_w(DecArgs a) {
-    __shared__ uint32_t s_buf[WAVES][132];
+__device__ __forceinline__ void decode_block(const uint32_t *buf, uint32_t bw, uint32_t *val, uint32_t cls,
+                                             uint32_t param, uint32_t aux, uint32_t v0, uint32_t nk,
+                                             uint32_t hi, bool has_next, uint32_t nxt, uint32_t *out,
+                                             uint64_t ob, uint64_t out_cap, uint32_t *err, uint32_t lane) {
+    if (nk == kBlock)
+        decode_one_block<true>(buf, bw, val, cls, param, aux, v0, nk, hi, has_next, nxt, out, ob, out_cap,
+                               err, lane);
+    else
+        decode_one_block<false>(buf, bw, val, cls, param, aux, v0, nk, hi, has_next, nxt, out, ob, out_cap,
+                                err, lane);
+}
+
+// Decode, one wave per unit (half a group: up to 8 blocks).  The wave reads
+// and checks the group's directory entries (one lane per block) and table
+// words, then decodes the unit's blocks in order.  STAGE: the unit's payload
+// words (at most 1024, since every block holds at most 128) are first staged
+// in LDS with every load in flight at once; otherwise they are loaded block
+// by block, the next block's words in flight while the current one decodes.
+template <int WAVES, bool STAGE>
+__global__ __launch_bounds__(WAVES * 64) void k_decode_u(DecArgs a) {
+    constexpr uint32_t kWin = kHalf * kBlock;
+    constexpr uint32_t kPerLane = kWin / 64;
+    __shared__ uint32_t s_win[WAVES][STAGE ? kWin + 4 : 132];
     __shared__ uint32_t s_val[WAVES][128];
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t total = a.tile_base[a.nseg];
-    const uint32_t nw = gridDim.x * WAVES;
-    uint32_t *buf = s_buf[w];
+    const uint32_t units = 2 * readfirst(a.tile_base[a.nseg]);
+    uint32_t *win = s_win[w];
     uint32_t *val = s_val[w];
-    for (uint32_t t = blockIdx.x * WAVES + w; t < total; t += nw) {
-        const uint32_t r = wave_find(a.tile_base, a.nseg, t, lane);
-        const uint32_t g = t - a.tile_base[r];
-        const uint32_t n = a.seg_n[r];
+    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    SegCursor c;
+    for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
+        const uint32_t t = u >> 1, h = u & 1;
+        if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
+            c.n = readfirst(a.seg_n[c.r]);
+            c.S = readfirst64(a.seg_byte_off[c.r]);
+            c.bytes = readfirst64(a.seg_byte_off[c.r + 1]) - c.S;
+            c.base = readfirst64(a.out_off[c.r]);
+            const uint32_t *sg = (const uint32_t *)(a.in + c.S);
+            c.lo = readfirst(sg[1]);
+            c.hi = readfirst(sg[2]);
+        }
+        const uint32_t g = t - c.t_first;
+        const uint32_t n = c.n;
         const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
-        const uint64_t S = a.seg_byte_off[r];
-        const uint64_t bytes = a.seg_byte_off[r + 1] - S;
-        const uint32_t *seg = (const uint32_t *)(a.in + S);
-        const uint32_t lo = seg[1], hi = seg[2];
+        const uint32_t k0 = g * kGroup;
+        const uint32_t gblk = min(kGroup, nb - k0);
+        const uint32_t hb = h * kHalf;
+        if (hb >= gblk) continue;
+        const uint32_t nblk = min(kHalf, gblk - hb);
+        const uint64_t bytes = c.bytes;
+        const uint32_t *seg = (const uint32_t *)(a.in + c.S);
+        const uint32_t lo = c.lo, hi = c.hi;
         const uint32_t metaw = 4 + 2 * nb + ng;
         const uint64_t availw = bytes / 4 - metaw;
-        const uint64_t oo = a.out_off[r];
-        const uint32_t k0 = g * kGroup;
-        const uint32_t nblk = min(kGroup, nb - k0);
-        // lane i < nblk: block k0+i; lane nblk: the next block's first value
+        const uint64_t oo = c.base;
+        // lane i < gblk: block k0+i of the group; lane gblk: the next block's first value
         bool bad = false;
         uint32_t words = 0, cls = 0, param = 0, aux = 0, first = 0;
-        if (lane <= nblk && k0 + lane < nb) {
+        if (lane <= gblk && k0 + lane < nb) {
             first = seg[4 + 2 * (k0 + lane)];
             const uint32_t e1 = seg[4 + 2 * (k0 + lane) + 1];
-            if (lane < nblk) {
+            if (lane < gblk) {
                 cls = e1 & 0xFFu;
                 param = (e1 >> 8) & 0xFFu;
                 aux = e1 >> 16;
@@ -1317,8 +1283,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_w(DecArgs a) {
                 } else if (cls <= 33) {
                     bad = param != cls - 1 || aux != 0;
                 } else if (cls == kClsPfor) {
-                    const uint32_t E = aux & 0xFFu, h = aux >> 8;
-                    bad = param > 32 || param + h > 32 || 10 * E > m;
+                    const uint32_t E = aux & 0xFFu, hh = aux >> 8;
+                    bad = param > 32 || param + hh > 32 || 10 * E > m;
                 } else {
                     bad = true;
                 }
@@ -1327,9 +1293,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_w(DecArgs a) {
                 bad |= (uint64_t)lo + first >= (uint64_t)hi;
             }
         }
-        const uint32_t incl = wave_incl_scan(lane < nblk ? words : 0u);
+        const uint32_t incl = wave_incl_scan(lane < gblk ? words : 0u);
         const uint32_t A = readlane(incl, 63);
-        const uint32_t gt = seg[4 + 2 * nb + g];
+        const uint32_t gt = readfirst(seg[4 + 2 * nb + g]);
         const uint32_t off = gt + incl - words;
         bool ok = ballot(bad) == 0ull;
         ok = ok && (uint64_t)gt + A <= availw;
@@ -1339,26 +1305,50 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_w(DecArgs a) {
             if (lane == 0) raise_err(a.err, kErrCorrupt);
             continue;
         }
+        const uint32_t ub = readlane(off, hb);
         const uint32_t *pay = seg + metaw;
-        uint32_t wc = readlane(words, 0), oc = readlane(off, 0);
-        uint32_t pa = lane < wc ? pay[oc + lane] : 0u;
-        uint32_t pb = lane + 64 < wc ? pay[oc + lane + 64] : 0u;
+        uint32_t pa = 0, pb = 0;
+        if constexpr (STAGE) {
+            const uint32_t ue = hb + nblk < gblk ? readlane(off, hb + nblk) : gt + A;
+            const uint32_t Au = ue - ub;
+            uint32_t v[kPerLane];
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < Au ? pay[ub + lane + 64 * i] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) win[lane + 64 * i] = v[i];
+            if (lane < 4) win[kWin + lane] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            const uint32_t wc = readlane(words, hb);
+            pa = lane < wc ? pay[ub + lane] : 0u;
+            pb = lane + 64 < wc ? pay[ub + lane + 64] : 0u;
+        }
         for (uint32_t kk = 0; kk < nblk; ++kk) {
-            const uint32_t k = k0 + kk;
-            uint32_t na = 0, nbw = 0;
-            if (kk + 1 < nblk) {
-                const uint32_t wn = readlane(words, kk + 1), on = readlane(off, kk + 1);
-                na = lane < wn ? pay[on + lane] : 0u;
-                nbw = lane + 64 < wn ? pay[on + lane + 64] : 0u;
-            }
+            const uint32_t j = hb + kk, k = k0 + j;
             const bool has_next = k + 1 < nb;
-            const uint32_t nxt = has_next ? lo + readlane(first, kk + 1) : 0u;
-            decode_one_block(buf, val, pa, pb, readlane(cls, kk), readlane(param, kk),
-                             readlane(aux, kk), lo + readlane(first, kk),
-                             min(kBlock, n - k * kBlock), hi, has_next, nxt, a.out,
-                             oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
-            pa = na;
-            pb = nbw;
+            const uint32_t nxt = has_next ? lo + readlane(first, j + 1) : 0u;
+            const uint32_t *buf = win;
+            if constexpr (STAGE) {
+                buf = win + (readlane(off, j) - ub);
+            } else {
+                uint32_t na = 0, nbw = 0;
+                if (kk + 1 < nblk) {
+                    const uint32_t wn = readlane(words, j + 1), on = readlane(off, j + 1);
+                    na = lane < wn ? pay[on + lane] : 0u;
+                    nbw = lane + 64 < wn ? pay[on + lane + 64] : 0u;
+                }
+                win[lane] = pa;
+                win[lane + 64] = pb;
+                if (lane < 4) win[128 + lane] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                pa = na;
+                pb = nbw;
+            }
+            decode_block(buf, readlane(words, j), val, readlane(cls, j), readlane(param, j), readlane(aux, j),
+                         lo + readlane(first, j), min(kBlock, n - k * kBlock), hi, has_next, nxt, a.out,
+                         oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
         }
     }
 }
@@ -1389,6 +1379,18 @@ static inline uint32_t persistent_grid(const bfsc_ctx *ctx, uint32_t per_cu, uin
     uint64_t g = (uint64_t)ctx->n_cu * per_cu;
     if (g > max_tiles) g = max_tiles;
     return (uint32_t)(g ? g : 1);
+}
+
+// Persistent grid for one kernel: never more workgroups per CU than can be
+// resident together (a late-starting workgroup would add a whole extra
+// round at the end of the pass).
+static inline uint32_t resident_grid(const bfsc_ctx *ctx, const void *fn, uint32_t threads,
+                                     uint32_t per_cu, uint64_t units) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, (int)threads, 0) == hipSuccess && occ > 0 &&
+        (uint32_t)occ < per_cu)
+        per_cu = (uint32_t)occ;
+    return persistent_grid(ctx, per_cu, units);
 }
 
 int launch_plan_prep(const bfsc_batch *b, const Plan &p, uint32_t *err, bool zero_status,
@@ -1422,28 +1424,34 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     a.seg_byte_off = seg_byte_off;
     a.p = p;
     a.err = ctx->err;
+    a.strided = (ctx->tune.enc_pack >> 2) & 1u;
     const uint32_t waves = ctx->tune.enc_waves;
-    const uint32_t grid = persistent_grid(ctx, ctx->tune.enc_wg_per_cu, p.max_tiles);
+    const uint64_t units = 2ull * p.max_tiles;
+    const uint32_t per_cu = ctx->tune.enc_wg_per_cu;
     const int slot = timing_begin(ctx, BFSC_OP_ENCODE, s);
     switch (waves) {
+#define BFSC_PACK_LAUNCH(K, W)                                                               \
+    hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \
+                       dim3(W * 64), 0, s, a)
 #define BFSC_PACK_CASE(W)                                                                  \
-    switch (ctx->tune.enc_pack) {                                                          \
-        case 1: hipLaunchKernelGGL((k_enc_pack<W, true>), dim3(grid), dim3(W * 64), 0, s, a); break;   \
-        case 2: hipLaunchKernelGGL((k_enc_pack_w<W, false>), dim3(grid), dim3(W * 64), 0, s, a); break; \
-        case 3: hipLaunchKernelGGL((k_enc_pack_w<W, true>), dim3(grid), dim3(W * 64), 0, s, a); break;  \
-        default: hipLaunchKernelGGL((k_enc_pack<W, false>), dim3(grid), dim3(W * 64), 0, s, a); break;  \
+    switch (ctx->tune.enc_pack & 3u) {                                                     \
+        case 1: BFSC_PACK_LAUNCH((k_enc_pack_u<W, true, true>), W); break;                 \
+        case 2: BFSC_PACK_LAUNCH((k_enc_pack_u<W, false, false>), W); break;               \
+        case 3: BFSC_PACK_LAUNCH((k_enc_pack_u<W, true, false>), W); break;                \
+        default: BFSC_PACK_LAUNCH((k_enc_pack_u<W, false, true>), W); break;               \
     }
         case 1: BFSC_PACK_CASE(1) break;
         case 2: BFSC_PACK_CASE(2) break;
         case 8: BFSC_PACK_CASE(8) break;
         case 16: BFSC_PACK_CASE(16) break;
         default: BFSC_PACK_CASE(4) break;
+#undef BFSC_PACK_LAUNCH
 #undef BFSC_PACK_CASE
     }
     timing_end(ctx, slot, s);
     hipLaunchKernelGGL(k_enc_scan, dim3(1), dim3(1024), 0, s, a);
     const int slot2 = timing_begin(ctx, BFSC_OP_ENCODE_PLACE, s);
-    hipLaunchKernelGGL(k_enc_place, dim3(persistent_grid(ctx, 8, p.max_tiles)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_enc_place<4>, dim3((uint32_t)((p.max_tiles + 3) / 4)), dim3(256), 0, s, a);
     timing_end(ctx, slot2, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
@@ -1503,14 +1511,19 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     a.out = out_ids;
     a.out_cap = out_cap;
     a.err = ctx->err;
+    a.strided = (ctx->tune.dec_mode >> 1) & 1u;
     const uint64_t mt = plan_max_tiles(max_ids, nseg);
-    const uint32_t grid = persistent_grid(ctx, ctx->tune.dec_wg_per_cu, mt);
+    const uint64_t units = 2 * mt;
+    const uint32_t per_cu = ctx->tune.dec_wg_per_cu;
     const int slot = timing_begin(ctx, BFSC_OP_DECODE, s);
+#define BFSC_DEC_LAUNCH(K, W)                                                                \
+    hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \
+                       dim3(W * 64), 0, s, a)
 #define BFSC_DEC_CASE(W)                                                                   \
-    if (ctx->tune.dec_mode)                                                                \
-        hipLaunchKernelGGL((k_decode_w<W>), dim3(grid), dim3(W * 64), 0, s, a);            \
+    if (ctx->tune.dec_mode & 1u)                                                           \
+        BFSC_DEC_LAUNCH((k_decode_u<W, false>), W);                                        \
     else                                                                                   \
-        hipLaunchKernelGGL((k_decode<W>), dim3(grid), dim3(W * 64), 0, s, a);
+        BFSC_DEC_LAUNCH((k_decode_u<W, true>), W);
     switch (ctx->tune.dec_waves) {
         case 1: BFSC_DEC_CASE(1) break;
         case 2: BFSC_DEC_CASE(2) break;
@@ -1518,6 +1531,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
         case 16: BFSC_DEC_CASE(16) break;
         default: BFSC_DEC_CASE(4) break;
     }
+#undef BFSC_DEC_LAUNCH
 #undef BFSC_DEC_CASE
     timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;

@@ -51,6 +51,11 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
 __device__ __forceinline__ uint32_t readfirst(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
+// Wave-uniform 64-bit value moved to scalar registers (the compiler then
+// treats everything derived from it as uniform: scalar loops and branches).
+__device__ __forceinline__ uint64_t readfirst64(uint64_t v) {
+    return ((uint64_t)readfirst((uint32_t)(v >> 32)) << 32) | readfirst((uint32_t)v);
+}
 
 __device__ __forceinline__ uint32_t shfl_up(uint32_t v, int d) { return __shfl_up(v, d, 64); }
 __device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return __shfl_down(v, d, 64); }
@@ -139,12 +144,15 @@ __device__ __forceinline__ uint32_t upper_bound_m1(const uint32_t *base, uint32_
 
 // Per-batch tiling computed by the prep kernel into the workspace.  A tile is
 // one group of up to 16 blocks of one segment; an empty segment gets one
-// tile without blocks (so that someone writes its header).  The encoder packs
-// every tile into a private slot (directory words, then payload words), then
-// one workgroup turns the tile sizes into output offsets, then the slots are
+// tile without blocks (so that someone writes its header).  The pack pass
+// works on units, the two halves of a tile (8 blocks each), and puts each
+// unit's payload into its own half of the tile's private slot; one
+// workgroup then turns the unit sizes into output offsets, and the slots are
 // placed: no workgroup ever waits for another.
+constexpr uint32_t kHalf = kGroup / 2;                 // blocks per pack unit
 constexpr uint32_t kSlotDirWords = 2 * kGroup;
-constexpr uint32_t kSlotWords = kSlotDirWords + kGroup * kBlock;
+constexpr uint32_t kSlotHalfWords = kHalf * kBlock;    // payload words of a unit, at most
+constexpr uint32_t kSlotWords = kSlotDirWords + 2 * kSlotHalfWords;
 
 struct Plan {
     uint32_t *blk_base;   // [nseg+1] first global block of each segment
@@ -152,8 +160,8 @@ struct Plan {
     uint32_t *tile_base;  // [nseg+1] first tile
     uint32_t *seg_n;      // [nseg]   IDs per segment (0 for a rejected segment)
     uint32_t *counter;    // [4]      [0]: workgroups done with the pack pass
-    uint32_t *tile_words; // [max_tiles] payload words per tile
-    uint64_t *tile_off;   // [max_tiles] exclusive prefix of tile_words
+    uint32_t *unit_words; // [2 max_tiles] payload words per unit (unit 2t + h: half h of tile t)
+    uint64_t *unit_off;   // [2 max_tiles] exclusive prefix of unit_words
     uint32_t *slots;      // [max_tiles][kSlotWords] (encode only)
     uint32_t max_tiles;
 };
@@ -182,10 +190,10 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     off = align256(off + n1 * 4);
     if (p) p->counter = (uint32_t *)(b + off);
     off = align256(off + 16);
-    if (p) p->tile_words = (uint32_t *)(b + off);
-    off = align256(off + mt * 4);
-    if (p) p->tile_off = (uint64_t *)(b + off);
-    off = align256(off + mt * 8);
+    if (p) p->unit_words = (uint32_t *)(b + off);
+    off = align256(off + 2 * mt * 4);
+    if (p) p->unit_off = (uint64_t *)(b + off);
+    off = align256(off + 2 * mt * 8);
     if (p) p->slots = slots ? (uint32_t *)(b + off) : nullptr;
     if (slots) off = align256(off + mt * (size_t)kSlotWords * 4);
     if (p) p->max_tiles = (uint32_t)mt;

@@ -309,12 +309,11 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
     const int timing = ctx->timing;
     ctx->timing = 0;
     // {waves per workgroup, workgroups per CU, pack variant}
-    static const uint32_t kEnc[][3] = {{4, 8, 0}, {8, 8, 0}, {8, 8, 1}, {2, 8, 2}, {4, 4, 2},
-                                       {4, 8, 2}, {4, 16, 2}, {8, 4, 2}, {8, 8, 2}, {4, 8, 3},
-                                       {8, 8, 3}};
+    static const uint32_t kEnc[][3] = {{4, 8, 6}, {4, 8, 4}, {4, 8, 2}, {4, 8, 7}, {2, 16, 6},
+                                       {8, 4, 6}, {4, 8, 0}};
     // {waves per workgroup, workgroups per CU, decoder variant}
-    static const uint32_t kDec[][3] = {{4, 8, 0}, {8, 4, 0}, {2, 8, 1}, {4, 4, 1}, {4, 8, 1},
-                                       {4, 16, 1}, {8, 4, 1}, {8, 8, 1}};
+    static const uint32_t kDec[][3] = {{4, 8, 3}, {4, 8, 2}, {4, 8, 1}, {2, 16, 3}, {8, 4, 3},
+                                       {4, 8, 0}};
     bfsc_tune best = keep;
     float best_e = 1e30f, best_d = 1e30f;
     for (const auto &c : kEnc) {
