@@ -114,3 +114,29 @@ def test_learned_select_resolves_and_encodes_exactly(ctx):
     assert st == 0
     np.testing.assert_array_equal(stream, want)
     np.testing.assert_array_equal(off, want_off)
+
+
+def test_trained_selector_on_gpu_gains_over_plain(ctx):
+    """The committed network on held-out frontiers, run by the GPU kernels:
+    its resolved choice encodes byte-exactly, gains over plain packing and
+    stays within 2% of exhaustive size."""
+    import os
+    from test_selector_trained import WEIGHTS, held_out_batches
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("selector not trained")
+    ctx.mlp_set_weights(np.load(WEIGHTS, allow_pickle=False))
+    plain = exh = learned = 0
+    for b in held_out_batches():
+        print("trained selector n=%d nseg=%d" % (b.n_ids, b.nseg), flush=True)
+        st, cls, fb = gpu_select(ctx, b, 2)
+        assert st == 0
+        want, want_off = oracle.encode(b, classes=cls)
+        st, stream, off = gpu_encode(ctx, b, classes=cls)
+        assert st == 0
+        np.testing.assert_array_equal(stream, want)
+        np.testing.assert_array_equal(off, want_off)
+        learned += stream.size
+        plain += oracle.encode(b, mode=oracle.PLAIN_BP)[0].size
+        exh += oracle.encode(b, mode=oracle.EXHAUSTIVE)[0].size
+    assert learned <= 0.85 * plain, (learned, plain)
+    assert learned <= 1.02 * exh, (learned, exh)
