@@ -130,7 +130,9 @@ def main():
     ap.add_argument("--roots", type=int, default=8)
     ap.add_argument("--nseg", type=int, default=16)
     ap.add_argument("--bounds", choices=["equal", "zipf"], default="equal")
-    ap.add_argument("--mode", choices=["exhaustive", "plain"], default="exhaustive")
+    ap.add_argument("--mode", choices=["exhaustive", "plain", "learned"], default="exhaustive",
+                    help="codec choice: exhaustive search, plain minimal width, or the trained "
+                         "selector (exhaustive fallback where its choice is invalid)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -150,7 +152,7 @@ def main():
     import inputs
     import paper_1704_00513_amd as P
 
-    mode = P.SEL_EXHAUSTIVE if args.mode == "exhaustive" else P.SEL_PLAIN_BP
+    mode = {"exhaustive": P.SEL_EXHAUSTIVE, "plain": P.SEL_PLAIN_BP, "learned": P.SEL_LEARNED}[args.mode]
     kind = inputs.RMAT if args.graph == "rmat" else inputs.UNIFORM
     t0 = time.time()
     g = inputs.graph(kind, args.scale, 16, args.seed)
@@ -171,8 +173,22 @@ def main():
     ws_e = ctx.workspace(P.OP_ENCODE, b.max_ids, b.nseg)
     ws_d = ctx.workspace(P.OP_DECODE, b.max_ids, b.nseg)
 
+    cls = None
+    if mode == P.SEL_LEARNED:
+        wpath = os.path.join(ROOT, "paper_1704_00513_amd", "selector_weights.npy")
+        if not os.path.exists(wpath):
+            sys.exit("--mode learned needs the trained selector (python -m paper_1704_00513_amd.train)")
+        ctx.mlp_set_weights(np.load(wpath, allow_pickle=False))
+        cls = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda")
+        fb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ws_s = ctx.workspace(P.OP_SELECT, b.max_ids, b.nseg)
+
     def step():
-        ctx.encode(b, out, sbo, mode=mode, ws=ws_e)
+        if cls is not None:
+            ctx.select(b, P.SEL_LEARNED, cls, fallbacks=fb, ws=ws_s)
+            ctx.encode(b, out, sbo, classes=cls, ws=ws_e)
+        else:
+            ctx.encode(b, out, sbo, mode=mode, ws=ws_e)
         ctx.decode(out, sbo, b.nseg, N, dec, doff, ws=ws_d)
 
     if args.tune:
@@ -186,7 +202,8 @@ def main():
     assert torch.equal(dec[:N], b.ids[:N]), "round trip differs"
     sbo_h = sbo.cpu().numpy().view(np.uint64)
     comp = int(sbo_h[-1])
-    check_segments(out, sbo_h, b, host, mode)
+    check_segments(out, sbo_h, b, host, mode, cls=None if cls is None else cls.cpu().numpy())
+    levels = ratio_per_level(sbo_h, host)
 
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -237,6 +254,7 @@ def main():
                    "n_ids": N, "segments": b.nseg, "levels": bfs["bfs_levels"],
                    "tune": ctx.get_tune()},
         "ratio": round(4.0 * N / comp, 4),
+        "ratio_per_level": levels,
         "compressed_bytes": comp,
         "encode_ms": round(enc_avg, 4),
         "encode_place_ms": round(place_avg, 4),
@@ -263,6 +281,7 @@ def main():
         res["extra"] = extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(b, host, args.cpu_seconds, mode)
+        res["cpu_baseline_all_cores"] = cpu_baseline_threads(b, host, args.cpu_seconds, mode)
     print(json.dumps(res), flush=True)
     ctx.close()
 
@@ -281,7 +300,26 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
 
     # learned selector (weights trained by paper_1704_00513_amd/train.py)
     wpath = os.path.join(ROOT, "paper_1704_00513_amd", "selector_weights.npy")
-    if os.path.exists(wpath):
+    if mode == P.SEL_LEARNED:
+        def xstep():
+            ctx.encode(b, buf, sbo, mode=P.SEL_EXHAUSTIVE)
+            ctx.decode(buf, sbo, b.nseg, N, dec, doff)
+
+        xstep()
+        ctx.sync()
+        assert torch.equal(dec[:N], b.ids[:N]), "exhaustive round trip differs"
+        xcomp = int(sbo[-1].item())
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            xstep()
+        torch.cuda.synchronize()
+        xms = (time.perf_counter() - t) * 1e3 / steps
+        out["exhaustive"] = {"value_GBps": round(4.0 * N / (xms * 1e-3) / 1e9, 2),
+                             "ms_per_step": round(xms, 4), "compressed_bytes": xcomp,
+                             "learned_size_gap_pct": round(100.0 * (comp - xcomp) / xcomp, 3),
+                             "learned_vs_exhaustive_speed": round(xms / ms_step, 3)}
+    elif os.path.exists(wpath):
         ctx.mlp_set_weights(np.load(wpath, allow_pickle=False))
         cls = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda")
         fb = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -311,13 +349,17 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
                           "fallback_rate": round(int(fb.item()) / steps / max(1, nblk), 5),
                           "vs_exhaustive_speed": round(ms_step / lms, 3)}
 
-    # one launch per segment (the same kernels, a one-segment batch each)
+    # one launch per segment (the same kernels, a one-segment batch each); on
+    # batches with more than 4096 non-empty segments, a seeded sample of 4096
+    # of them, and the rate compared with the batched one over the same IDs
     segs = []
     so = host["seg_off"]
-    for r in range(b.nseg):
+    nonempty = np.nonzero(np.diff(so.astype(np.int64)))[0]
+    sampled = nonempty.size > 4096
+    if sampled:
+        nonempty = np.sort(np.random.default_rng(3).choice(nonempty, 4096, replace=False))
+    for r in nonempty:
         s, e = int(so[r]), int(so[r + 1])
-        if e == s:
-            continue
         sb = P.DeviceBatch(b.ids[s:e], torch.tensor([0, e - s], dtype=torch.int64, device="cuda"),
                            b.seg_lo[r:r + 1], b.seg_hi[r:r + 1], b.seg_level[r:r + 1], max_ids=e - s)
         o = torch.zeros(P.Context.encode_bound(e - s, 1), dtype=torch.uint8, device="cuda")
@@ -326,9 +368,12 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
     ws_e = ctx.workspace(P.OP_ENCODE, max(x[5] for x in segs), 1, key="perseg_e")
     ws_d = ctx.workspace(P.OP_DECODE, max(x[5] for x in segs), 1, key="perseg_d")
 
+    # the plain single-segment form: exhaustive choice, one launch per segment
+    seg_mode = P.SEL_EXHAUSTIVE if mode == P.SEL_LEARNED else mode
+
     def pstep():
         for sb, o, sbo1, d, doff1, n in segs:
-            ctx.encode(sb, o, sbo1, mode=mode, ws=ws_e)
+            ctx.encode(sb, o, sbo1, mode=seg_mode, ws=ws_e)
             ctx.decode(o, sbo1, 1, n, d, doff1, ws=ws_d)
 
     pstep()
@@ -339,9 +384,14 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
         pstep()
     torch.cuda.synchronize()
     pms = (time.perf_counter() - t) * 1e3 / 3
-    out["per_segment_launches"] = {"segments": len(segs), "ms_per_step": round(pms, 3),
-                                   "value_GBps": round(4.0 * N / (pms * 1e-3) / 1e9, 2),
-                                   "batched_speedup": round(pms / ms_step, 2)}
+    nseg_ids = sum(x[5] for x in segs)
+    pg = 4.0 * nseg_ids / (pms * 1e-3) / 1e9
+    out["per_segment_launches"] = {"segments": len(segs), "sampled": bool(sampled), "ids": int(nseg_ids),
+                                   "ms_per_step": round(pms, 3), "value_GBps": round(pg, 2),
+                                   "batched_speedup": round(4.0 * N / (ms_step * 1e-3) / 1e9 / pg, 2)}
+
+    out["per_level_root0"] = per_level(ctx, P, torch, b, host, mode, cls_mode=mode)
+    out["mall_cold"] = mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps)
 
     # per-level pipeline for the first root: graph replay vs eager launches
     dg = P.DeviceGraph.from_host(g)
@@ -367,9 +417,97 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
     return out
 
 
-def check_segments(out, sbo_h, b, host, mode, n_check=24):
+def per_level(ctx, P, torch, b, host, mode, cls_mode, reps=10):
+    """The first root's levels, one batch per level: IDs, ratio, enc+dec time
+    and rate, and the exhaustive class histogram (bitmap / bit-pack / PFOR)."""
+    lev, so = host["seg_level"], host["seg_off"].astype(np.int64)
+    end0 = next((i for i in range(1, lev.size) if lev[i] < lev[i - 1]), lev.size)
+    res = []
+    for L in np.unique(lev[:end0]):
+        idx = np.nonzero(lev[:end0] == L)[0]
+        r0, r1 = int(idx[0]), int(idx[-1]) + 1
+        s, e = int(so[r0]), int(so[r1])
+        if e == s:
+            continue
+        n = e - s
+        sb = P.DeviceBatch(b.ids[s:e], torch.from_numpy(so[r0:r1 + 1] - s).cuda(), b.seg_lo[r0:r1],
+                           b.seg_hi[r0:r1], b.seg_level[r0:r1], max_ids=n)
+        nseg = r1 - r0
+        cls = torch.zeros(sb.n_blocks_max, dtype=torch.uint8, device="cuda")
+        ctx.select(sb, P.SEL_EXHAUSTIVE, cls)
+        nblk = int(sum((np.diff(so[r0:r1 + 1]) + 127) // 128))
+        c = np.bincount(cls[:nblk].cpu().numpy(), minlength=35)
+        o = torch.zeros(P.Context.encode_bound(n, nseg), dtype=torch.uint8, device="cuda")
+        sbo = torch.zeros(nseg + 1, dtype=torch.int64, device="cuda")
+        d = torch.empty(n, dtype=torch.int32, device="cuda")
+        doff = torch.zeros(nseg + 1, dtype=torch.int64, device="cuda")
+        lcls = torch.zeros(sb.n_blocks_max, dtype=torch.uint8, device="cuda") if mode == P.SEL_LEARNED else None
+
+        def one():
+            if lcls is not None:
+                ctx.select(sb, P.SEL_LEARNED, lcls)
+                ctx.encode(sb, o, sbo, classes=lcls)
+            else:
+                ctx.encode(sb, o, sbo, mode=mode)
+            ctx.decode(o, sbo, nseg, n, d, doff)
+
+        one()
+        ctx.sync()
+        assert torch.equal(d, sb.ids[:n]), "level %d round trip differs" % L
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            one()
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t) * 1e6 / reps
+        comp = int(sbo[-1].item())
+        res.append({"level": int(L), "ids": n, "ratio": round(4.0 * n / comp, 3), "us": round(us, 1),
+                    "GBps": round(4.0 * n / (us * 1e-6) / 1e9, 2),
+                    "classes": {"bitmap": int(c[0]), "bitpack": int(c[1:34].sum()), "pfor": int(c[34])}})
+    return res
+
+
+def mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps):
+    """Encode + decode with a 1 GiB scratch write before every step, so that
+    nothing of the batch is left in the 256 MB MALL; only the codec is timed
+    (stream events around it)."""
+    scratch = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    lcls = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda") if mode == P.SEL_LEARNED else None
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for i in range(steps):
+        scratch.fill_(i)
+        ev[i][0].record()
+        if lcls is not None:
+            ctx.select(b, P.SEL_LEARNED, lcls)
+            ctx.encode(b, buf, sbo, classes=lcls)
+        else:
+            ctx.encode(b, buf, sbo, mode=mode)
+        ctx.decode(buf, sbo, b.nseg, N, dec, doff)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(z) for a, z in ev)
+    med = ms[len(ms) // 2]
+    return {"ms_per_step_median": round(med, 4), "value_GBps": round(4.0 * N / (med * 1e-3) / 1e9, 2)}
+
+
+def ratio_per_level(sbo_h, host):
+    """[level, IDs, compression ratio] over all segments of each BFS level
+    (levels of the different roots pooled)."""
+    sizes = np.diff(host["seg_off"].astype(np.int64))
+    nbytes = np.diff(sbo_h.astype(np.int64))
+    lev = host["seg_level"].astype(np.int64)
+    out = []
+    for L in np.unique(lev):
+        k = lev == L
+        n = int(sizes[k].sum())
+        out.append([int(L), n, round(4.0 * n / max(1, int(nbytes[k].sum())), 3)])
+    return out
+
+
+def check_segments(out, sbo_h, b, host, mode, n_check=24, cls=None):
     """Sampled segments of the full-size batch: GPU bytes equal the oracle's
-    encoding of that segment alone (segments are independent)."""
+    encoding of that segment alone (segments are independent), with the
+    GPU's own per-block choice when a trained selector made it."""
     import oracle
     ids = b.ids[:b.max_ids].cpu().numpy().view(np.uint32)
     R = b.nseg
@@ -378,19 +516,30 @@ def check_segments(out, sbo_h, b, host, mode, n_check=24):
     big = np.argsort(sizes)[-4:]
     pick = np.unique(np.concatenate([big, rng.choice(R, min(R, n_check), replace=False)]))
     data = out[:int(sbo_h[-1])].cpu().numpy()
+    blk0 = np.concatenate([[0], np.cumsum((sizes + 127) // 128)])
     for r in pick:
         s, e = int(host["seg_off"][r]), int(host["seg_off"][r + 1])
         ob = oracle.Batch(ids[s:e], [0, e - s], [host["seg_lo"][r]], [host["seg_hi"][r]],
                           [host["seg_level"][r]])
-        want, _ = oracle.encode(ob, mode=mode)
+        if cls is None:
+            want, _ = oracle.encode(ob, mode=mode)
+        else:
+            k0 = int(blk0[r])
+            want, _ = oracle.encode(ob, classes=cls[k0:k0 + (e - s + 127) // 128])
         got = data[int(sbo_h[r]):int(sbo_h[r + 1])]
         assert np.array_equal(got, want), "segment %d differs from the oracle" % r
 
 
 def cpu_baseline(b, host, seconds, mode):
     """The oracle's encode + decode on a bounded sample of the same batch,
-    single thread on this host, scaled to GB/s of raw bytes."""
+    single thread on this host, scaled to GB/s of raw bytes.  With the trained
+    selector, the oracle's own path: fp64 forward pass, resolve, encode."""
     import oracle
+    from oracle import mlp
+    theta = None
+    if mode == 2:
+        theta = np.load(os.path.join(ROOT, "paper_1704_00513_amd", "selector_weights.npy"),
+                        allow_pickle=False).astype(np.float64)
     ids = b.ids[:b.max_ids].cpu().numpy().view(np.uint32)
     R = b.nseg
     order = np.random.default_rng(1).permutation(R)
@@ -402,7 +551,11 @@ def cpu_baseline(b, host, seconds, mode):
         ob = oracle.Batch(ids[s:e], [0, e - s], [host["seg_lo"][r]], [host["seg_hi"][r]],
                           [host["seg_level"][r]])
         t = time.perf_counter()
-        stream, sbo = oracle.encode(ob, mode=mode)
+        if theta is None:
+            stream, sbo = oracle.encode(ob, mode=mode)
+        else:
+            pred = mlp.predict(theta, mlp.features_to_f64(oracle.features(ob)))
+            stream, sbo = oracle.encode(ob, classes=oracle.resolve(ob, pred)[0])
         st, got, _ = oracle.decode(stream, sbo)
         t_used += time.perf_counter() - t
         assert st == 0
@@ -415,6 +568,47 @@ def cpu_baseline(b, host, seconds, mode):
             "sample": "%d random segments (%d IDs, %.1f%% of the batch), encode+decode, %.1f s"
                       % (segs, done_ids, 100.0 * done_ids / max(1, b.max_ids), t_used),
             "cpu": cpu_model()}
+
+
+def cpu_baseline_threads(b, host, seconds, mode):
+    """The same oracle calls spread over every host core (one segment per
+    task; the oracle's C code runs without the interpreter lock)."""
+    import concurrent.futures as cf
+    import oracle
+    from oracle import mlp
+    theta = None
+    if mode == 2:
+        theta = np.load(os.path.join(ROOT, "paper_1704_00513_amd", "selector_weights.npy"),
+                        allow_pickle=False).astype(np.float64)
+    ids = b.ids[:b.max_ids].cpu().numpy().view(np.uint32)
+    T = max(1, len(os.sched_getaffinity(0)))
+    order = [r for r in np.random.default_rng(1).permutation(b.nseg)
+             if host["seg_off"][r + 1] > host["seg_off"][r]]
+
+    def work(r):
+        s, e = int(host["seg_off"][r]), int(host["seg_off"][r + 1])
+        ob = oracle.Batch(ids[s:e], [0, e - s], [host["seg_lo"][r]], [host["seg_hi"][r]],
+                          [host["seg_level"][r]])
+        if theta is None:
+            stream, sbo = oracle.encode(ob, mode=mode)
+        else:
+            pred = mlp.predict(theta, mlp.features_to_f64(oracle.features(ob)))
+            stream, sbo = oracle.encode(ob, classes=oracle.resolve(ob, pred)[0])
+        st, _, _ = oracle.decode(stream, sbo)
+        assert st == 0
+        return e - s
+
+    done, segs = 0, 0
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(T) as ex:
+        for k in range(0, len(order), 4 * T):
+            done += sum(ex.map(work, order[k:k + 4 * T]))
+            segs += len(order[k:k + 4 * T])
+            if time.perf_counter() - t >= seconds:
+                break
+    el = time.perf_counter() - t
+    return {"value": round(4.0 * done / el / 1e9, 4), "unit": "GB/s", "cores": T, "kind": "oracle",
+            "sample": "%d random segments (%d IDs), encode+decode, %.1f s" % (segs, done, el)}
 
 
 def cpu_model():

@@ -230,6 +230,18 @@ int bfsc_mlp_get_weights(bfsc_ctx *ctx, float *host_params);
 int bfsc_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, void *ws,
                      void *stream);
 
+/* The same network evaluated on the matrix cores (v_mfma_f32_16x16x16_f16,
+ * 16 features at a time; fp16 weights and activations, fp32 accumulation and
+ * biases): the inference used by the learned selector.  Writes logits
+ * f32[n][35] and/or the predicted class u8[n] (largest logit, lowest class
+ * on ties, 255 if any logit is NaN); either output may be NULL.  Only the
+ * order of the fp32 additions differs from bfsc_mlp_forward.  The selector
+ * definition (8 -> 64 ReLU -> 64 ReLU -> 35 over per-block features) follows
+ * the learned-codec configuration; the paper's own codec choice was a fixed
+ * table ("Compression techniques" section). */
+int bfsc_mlp_infer(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, uint8_t *classes,
+                   void *stream);
+
 /* Gradient f32[7011] (device) of the mean softmax cross-entropy over
  * (X u16[n][8], y u8[n]), straight-through at the fp16 rounding points;
  * *loss_dev (f32, device, may be NULL) receives the loss. */

@@ -308,6 +308,11 @@ class Context:
         check(_lib.load().bfsc_mlp_grad(self.h, ptr(X), ptr(y), int(n), ptr(grads), ptr(loss), ptr(ws),
                                         _stream(stream)), "bfsc_mlp_grad")
 
+    def mlp_infer(self, X, n, logits=None, classes=None, stream=None):
+        """Logits and/or predicted classes from the matrix-core inference kernel."""
+        check(_lib.load().bfsc_mlp_infer(self.h, ptr(X), int(n), ptr(logits), ptr(classes),
+                                         _stream(stream)), "bfsc_mlp_infer")
+
     def mlp_train_step(self, X, y, n, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, ws=None,
                        stream=None):
         ws = ws if ws is not None else self.workspace(OP_MLP, n, 0, key="mlp")

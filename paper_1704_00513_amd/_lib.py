@@ -75,6 +75,7 @@ _SIGS = {
     "bfsc_mlp_set_weights": [vp, vp],
     "bfsc_mlp_get_weights": [vp, vp],
     "bfsc_mlp_forward": [vp, vp, u32, vp, vp, vp],
+    "bfsc_mlp_infer": [vp, vp, u32, vp, vp, vp],
     "bfsc_mlp_grad": [vp, vp, vp, u32, vp, vp, vp, vp],
     "bfsc_mlp_train_step": [vp, vp, vp, u32, P(Adam), vp, vp, vp],
     "bfsc_get_tune": [vp, P(Tune)],

@@ -7,6 +7,7 @@
 #include <new>
 
 #include "common.hpp"
+#include "mlp_mfma.hpp"
 
 using namespace bfsc;
 
@@ -78,13 +79,15 @@ int bfsc_create(bfsc_ctx **out, int device) {
         hipMalloc((void **)&c->adam_m, np * 4) != hipSuccess ||
         hipMalloc((void **)&c->adam_v, np * 4) != hipSuccess ||
         hipMalloc((void **)&c->mlp_grad, np * 4) != hipSuccess ||
-        hipMalloc((void **)&c->mlp_w16, np * 2) != hipSuccess) {
+        hipMalloc((void **)&c->mlp_w16, np * 2) != hipSuccess ||
+        hipMalloc(&c->mlp_mfma, sizeof(MlpMfma)) != hipSuccess) {
         bfsc_destroy(c);
         return BFSC_E_HIP;
     }
     if (hipMemset(c->err, 0, 256) != hipSuccess || hipMemset(c->mlp_params, 0, np * 4) != hipSuccess ||
         hipMemset(c->adam_m, 0, np * 4) != hipSuccess || hipMemset(c->adam_v, 0, np * 4) != hipSuccess ||
-        hipMemset(c->mlp_w16, 0, np * 2) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipMemset(c->mlp_w16, 0, np * 2) != hipSuccess ||
+        hipMemset(c->mlp_mfma, 0, sizeof(MlpMfma)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         bfsc_destroy(c);
         return BFSC_E_HIP;
     }
@@ -109,6 +112,7 @@ int bfsc_destroy(bfsc_ctx *ctx) {
     hipFree(ctx->adam_v);
     hipFree(ctx->mlp_grad);
     hipFree(ctx->mlp_w16);
+    hipFree(ctx->mlp_mfma);
     for (uint32_t i = 0; i < ctx->ev_created; ++i) {
         hipEventDestroy(ctx->ev_a[i]);
         hipEventDestroy(ctx->ev_b[i]);
@@ -248,6 +252,13 @@ int bfsc_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits
     if (!ctx || (!X && n) || (!logits && n)) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     return launch_mlp_forward(ctx, X, n, logits, S(stream));
+}
+
+int bfsc_mlp_infer(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, uint8_t *classes,
+                   void *stream) {
+    if (!ctx || (!X && n)) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_mlp_infer(ctx, X, n, logits, classes, S(stream));
 }
 
 int bfsc_mlp_grad(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n, float *grads,

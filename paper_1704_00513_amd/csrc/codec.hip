@@ -12,6 +12,7 @@
 // workgroup to finish scans the tile sizes) + place pass.  Decode is one pass:
 // the group table gives every tile its payload offset.
 #include "common.hpp"
+#include "mlp_mfma.hpp"
 
 namespace bfsc {
 
@@ -832,8 +833,7 @@ struct SelArgs {
     uint8_t *classes;
     uint16_t *feat;           // features out (may be NULL)
     uint64_t *fallbacks;
-    const _Float16 *w16;      // fp16 weights (learned mode)
-    const float *params;      // fp32 master (biases)
+    const MlpMfma *w;         // the network in MFMA operand order (learned mode)
     Plan p;
     uint32_t *err;
 };
@@ -860,16 +860,19 @@ __device__ __forceinline__ void block_features(const BlockStats &S, uint32_t seg
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
     constexpr int BPW = (int)kGroup / WAVES;
-    // learned-mode scratch: features and hidden activations of the tile
-    __shared__ float s_x[kGroup][kIn];
-    __shared__ float s_h1[kGroup][kH];
-    __shared__ float s_h2[kGroup][kH];
-    __shared__ float s_z[kGroup][kOut + 1];
+    // learned mode: the network, and the tile's features (fp16 bits) and
+    // the per-block facts that resolve needs
+    __shared__ MlpMfma s_w;
+    __shared__ uint16_t s_x[kGroup][kIn];
     __shared__ uint32_t s_wmin[kGroup], s_span[kGroup];
     __shared__ uint32_t s_ex[kGroup];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t total = a.p.tile_base[a.nseg];
     const bool learned = a.mode == BFSC_SEL_LEARNED;
+    if (learned) {
+        mlp_mfma_stage(&s_w, a.w, tid, WAVES * 64);
+        __syncthreads();
+    }
     __shared__ EncTile s_tm[kMetaChunk];
     const uint32_t G = gridDim.x;
     for (uint32_t base = blockIdx.x; base < total; base += G * kMetaChunk) {
@@ -917,7 +920,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
                         for (int q = 1; q < 8; ++q) fv = lane == (uint32_t)q ? f[q] : fv;
                         const uint16_t hb = f16bits(fv);
                         if (a.feat) a.feat[(uint64_t)(gb + kk) * 8 + lane] = hb;
-                        s_x[kk][lane] = (float)__builtin_bit_cast(_Float16, hb);
+                        s_x[kk][lane] = hb;
                     }
                 }
                 if (learned) {
@@ -936,58 +939,41 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
         }
         if (!learned) continue;
         __syncthreads();
-        // MLP on the tile's blocks (fp16 weights, fp32 accumulation)
-        const uint32_t nthr = WAVES * 64;
-        for (uint32_t o = tid; o < kGroup * kH; o += nthr) {
-            const uint32_t bi = o / kH, u = o % kH;
-            if (bi < nblk) {
-                float acc = 0.0f;
+        // the network on the tile's blocks, one wave on the matrix cores
+        // (block b is sample b; rows past the tile's blocks are zero)
+        if (w == 0) {
+            const uint32_t smp = lane & 15;
+            half4_t x = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+            if (lane < 32 && smp < nblk) {
 #pragma unroll
-                for (int i = 0; i < kIn; ++i) acc += (float)a.w16[kW1 + u * kIn + i] * s_x[bi][i];
-                const float z = acc + a.params[kB1 + u];
-                s_h1[bi][u] = (float)(_Float16)fmaxf(z, 0.0f);
+                for (int j = 0; j < 4; ++j) x[j] = __builtin_bit_cast(_Float16, s_x[smp][(lane >> 4) * 4 + j]);
             }
-        }
-        __syncthreads();
-        for (uint32_t o = tid; o < kGroup * kH; o += nthr) {
-            const uint32_t bi = o / kH, u = o % kH;
-            if (bi < nblk) {
-                float acc = 0.0f;
-                for (int i = 0; i < kH; ++i) acc += (float)a.w16[kW2 + u * kH + i] * s_h1[bi][i];
-                const float z = acc + a.params[kB2 + u];
-                s_h2[bi][u] = (float)(_Float16)fmaxf(z, 0.0f);
+            float4_t z[3];
+            mlp16(s_w, x, lane, z);
+            const uint32_t best = mlp16_argmax(z, lane);
+            if (lane < nblk) {
+                const uint32_t bi = lane;
+                uint32_t res;
+                const uint32_t wmin = s_wmin[bi], span = s_span[bi];
+                bool fb = false;
+                if (best == 255u) {
+                    fb = true;
+                    res = s_ex[bi];
+                } else if (best == kClsBitmap) {
+                    if (span <= kBitmapMaxSpan) {
+                        res = kClsBitmap;
+                    } else {
+                        fb = true;
+                        res = s_ex[bi];
+                    }
+                } else if (best <= 33) {
+                    res = 1u + wmin;
+                } else {
+                    res = kClsPfor;
+                }
+                if (a.classes) a.classes[gb + bi] = (uint8_t)res;
+                if (fb && a.fallbacks) atomicAdd((unsigned long long *)a.fallbacks, 1ull);
             }
-        }
-        __syncthreads();
-        for (uint32_t o = tid; o < kGroup * kOut; o += nthr) {
-            const uint32_t bi = o / kOut, c = o % kOut;
-            if (bi < nblk) {
-                float acc = 0.0f;
-                for (int i = 0; i < kH; ++i) acc += (float)a.w16[kW3 + c * kH + i] * s_h2[bi][i];
-                s_z[bi][c] = acc + a.params[kB3 + c];
-            }
-        }
-        __syncthreads();
-        if (tid < nblk) {
-            const uint32_t bi = tid;
-            uint32_t best = 0;
-            float bz = s_z[bi][0];
-            bool nan = bz != bz;
-            for (uint32_t c = 1; c < (uint32_t)kOut; ++c) {
-                const float z = s_z[bi][c];
-                nan |= z != z;
-                if (z > bz) { bz = z; best = c; }
-            }
-            uint32_t res;
-            const uint32_t wmin = s_wmin[bi], span = s_span[bi];
-            bool fb = false;
-            if (nan) { fb = true; res = s_ex[bi]; }
-            else if (best == kClsBitmap) {
-                if (span <= kBitmapMaxSpan) res = kClsBitmap; else { fb = true; res = s_ex[bi]; }
-            } else if (best <= 33) res = 1u + wmin;
-            else res = kClsPfor;
-            if (a.classes) a.classes[gb + bi] = (uint8_t)res;
-            if (fb && a.fallbacks) atomicAdd((unsigned long long *)a.fallbacks, 1ull);
         }
         __syncthreads();
     }
@@ -1469,8 +1455,7 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
     a.classes = classes;
     a.feat = feat;
     a.fallbacks = fallbacks;
-    a.w16 = ctx->mlp_w16;
-    a.params = ctx->mlp_params;
+    a.w = (const MlpMfma *)ctx->mlp_mfma;
     a.p = p;
     a.err = ctx->err;
     const uint32_t grid = persistent_grid(ctx, 4, p.max_tiles);

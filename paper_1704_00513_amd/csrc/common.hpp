@@ -212,6 +212,7 @@ struct bfsc_ctx {
     float *adam_m, *adam_v; // device [7011]
     float *mlp_grad;        // device [7011]
     _Float16 *mlp_w16;      // device fp16 copy of the parameters [7011]
+    void *mlp_mfma;         // device: the fp16 weights in MFMA operand order + biases
     uint32_t adam_t;
     bfsc_tune tune;
     // per-kernel event timing (bfsc_timing_enable / bfsc_timing_read)
@@ -254,6 +255,8 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
 int launch_level_inc(int32_t *level_dev, hipStream_t s);
 size_t mlp_ws_bytes(uint32_t n);
 int launch_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, hipStream_t s);
+int launch_mlp_infer(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, uint8_t *cls,
+                     hipStream_t s);
 int launch_mlp_grad(bfsc_ctx *ctx, const uint16_t *X, const uint8_t *y, uint32_t n, float *grads,
                     float *loss, void *ws, hipStream_t s);
 int launch_adam(bfsc_ctx *ctx, const float *grads, const bfsc_adam *opt, hipStream_t s);

@@ -12,6 +12,7 @@
 // One workgroup of 256 threads handles 64 samples; per-workgroup gradient
 // partials are reduced by a second kernel in a fixed order (deterministic).
 #include "common.hpp"
+#include "mlp_mfma.hpp"
 
 namespace bfsc {
 
@@ -211,9 +212,88 @@ static void mlp_ws(void *ws, uint32_t n, float **partial, float **ploss) {
     *ploss = (float *)(b + align256(nch * kNParams * 4));
 }
 
+// The fp16 weights in MFMA A-operand lane order, and the fp32 biases (one
+// thread per tile lane).  Tile (t, s) of a layer with M outputs and K inputs
+// holds, in lane l, W[16t + l mod 16][16s + 4(l/16) + j] for j = 0..3, zero
+// outside the matrix.
+__global__ void k_mlp_pack_mfma(const _Float16 *w16, const float *params, MlpMfma *out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMfmaTiles * 64) {
+        const uint32_t tile = i / 64, lane = i % 64;
+        uint32_t t, sk, M, K, base;
+        if (tile < kMfmaT2) {
+            t = tile, sk = 0, M = kH, K = kIn, base = kW1;
+        } else if (tile < kMfmaT3) {
+            t = (tile - kMfmaT2) / 4, sk = (tile - kMfmaT2) % 4, M = kH, K = kH, base = kW2;
+        } else {
+            t = (tile - kMfmaT3) / 4, sk = (tile - kMfmaT3) % 4, M = kOut, K = kH, base = kW3;
+        }
+        const uint32_t m = 16 * t + lane % 16;
+        half4_t v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t k = 16 * sk + 4 * (lane / 16) + j;
+            v[j] = (m < M && k < K) ? w16[base + m * K + k] : (_Float16)0.0f;
+        }
+        out->w[tile][lane] = v;
+    }
+    if (i < kMfmaBias) {
+        float b = 0.0f;
+        if (i < 64) b = params[kB1 + i];
+        else if (i < 128) b = params[kB2 + i - 64];
+        else if (i - 128 < (uint32_t)kOut) b = params[kB3 + i - 128];
+        out->b[i] = b;
+    }
+}
+
+static int launch_mlp_pack(bfsc_ctx *ctx, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack_mfma, dim3((kMfmaTiles * 64 + 255) / 256), dim3(256), 0, s,
+                       ctx->mlp_w16, ctx->mlp_params, (MlpMfma *)ctx->mlp_mfma);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
 int launch_round16(bfsc_ctx *ctx, hipStream_t s) {
     hipLaunchKernelGGL(k_round16, dim3((kNParams + 255) / 256), dim3(256), 0, s, ctx->mlp_params,
                        ctx->mlp_w16);
+    if (hipGetLastError() != hipSuccess) return BFSC_E_HIP;
+    return launch_mlp_pack(ctx, s);
+}
+
+// Inference on the matrix cores: every wave takes 16 samples at a time.
+__global__ __launch_bounds__(256) void k_mlp_infer(const MlpMfma *Wg, const uint16_t *X, uint32_t n,
+                                                   float *logits, uint8_t *cls) {
+    __shared__ MlpMfma W;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    mlp_mfma_stage(&W, Wg, tid, 256);
+    __syncthreads();
+    const uint32_t groups = (n + 15) / 16;
+    for (uint32_t g = blockIdx.x * 4 + w; g < groups; g += gridDim.x * 4) {
+        const uint32_t smp = g * 16 + (lane & 15);
+        half4_t x = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+        if (lane < 32 && smp < n) x = *(const half4_t *)(X + (uint64_t)smp * kIn + (lane >> 4) * 4);
+        float4_t z[3];
+        mlp16(W, x, lane, z);
+        if (logits && smp < n) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t c = 16u * t + (lane >> 4) * 4 + j;
+                    if (c < (uint32_t)kOut) logits[(uint64_t)smp * kOut + c] = z[t][j];
+                }
+        }
+        const uint32_t best = mlp16_argmax(z, lane);
+        if (cls && lane < 16 && smp < n) cls[smp] = (uint8_t)best;
+    }
+}
+
+int launch_mlp_infer(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, uint8_t *cls,
+                     hipStream_t s) {
+    if (n == 0) return BFSC_OK;
+    uint64_t groups = (n + 15) / 16, grid = (groups + 3) / 4;
+    if (grid > (uint64_t)ctx->n_cu * 8) grid = (uint64_t)ctx->n_cu * 8;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)grid), dim3(256), 0, s,
+                       (const MlpMfma *)ctx->mlp_mfma, X, n, logits, cls);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -259,7 +339,8 @@ int launch_adam(bfsc_ctx *ctx, const float *grads, const bfsc_adam *opt, hipStre
     hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, ctx->mlp_params,
                        ctx->adam_m, ctx->adam_v, ctx->mlp_w16, grads, opt->lr, opt->beta1,
                        opt->beta2, opt->eps, c1, c2);
-    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+    if (hipGetLastError() != hipSuccess) return BFSC_E_HIP;
+    return launch_mlp_pack(ctx, s);
 }
 
 }  // namespace bfsc

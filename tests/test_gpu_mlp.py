@@ -54,6 +54,53 @@ def test_forward_logits(ctx):
     np.testing.assert_allclose(got, want, rtol=LOGIT_RTOL, atol=LOGIT_ATOL)
 
 
+@pytest.mark.parametrize("seed", [3, 6])
+def test_mfma_inference_matches_oracle(ctx, seed):
+    """The matrix-core inference (bfsc_mlp_infer): logits within the same
+    tolerance as the vector kernel, and the class equal to the oracle's argmax
+    wherever the oracle's top-2 margin is clear of that tolerance.  n is not a
+    multiple of 16, so the last group of samples is ragged."""
+    t = torch()
+    b, F, y = frontier_features()
+    F = F[:F.shape[0] - 3]
+    theta = inputs.mlp_init(seed)
+    theta[::7] += 0.03
+    ctx.mlp_set_weights(theta)
+    n = F.shape[0]
+    assert n % 16 != 0
+    logits = t.zeros((n, 35), dtype=t.float32, device="cuda")
+    cls = t.zeros(n, dtype=t.uint8, device="cuda")
+    ctx.mlp_infer(to_dev(F, np.uint16, np.int16), n, logits, cls)
+    assert ctx.sync_status() == 0
+    got = logits.cpu().numpy()
+    X = mlp.features_to_f64(F)
+    want, _ = mlp.forward(theta.astype(np.float64), X)
+    np.testing.assert_allclose(got, want, rtol=LOGIT_RTOL, atol=LOGIT_ATOL)
+    pred = mlp.predict(theta.astype(np.float64), X)
+    top2 = np.sort(want, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 2 * (LOGIT_ATOL + LOGIT_RTOL * np.abs(top2[:, 1]))
+    assert clear.mean() > 0.5
+    np.testing.assert_array_equal(cls.cpu().numpy()[clear], pred[clear])
+    # only the class output requested
+    cls2 = t.zeros(n, dtype=t.uint8, device="cuda")
+    ctx.mlp_infer(to_dev(F, np.uint16, np.int16), n, None, cls2)
+    assert t.equal(cls, cls2)
+
+
+def test_mfma_inference_nan_weights_give_255(ctx):
+    t = torch()
+    b, F, y = frontier_features()
+    theta = inputs.mlp_init(5)
+    theta[-1] = np.nan  # bias of the last class
+    ctx.mlp_set_weights(theta)
+    n = F.shape[0]
+    cls = t.zeros(n, dtype=t.uint8, device="cuda")
+    ctx.mlp_infer(to_dev(F, np.uint16, np.int16), n, None, cls)
+    assert ctx.sync_status() == 0
+    assert (cls.cpu().numpy() == 255).all()
+    assert (mlp.predict(theta.astype(np.float64), mlp.features_to_f64(F)) == 255).all()
+
+
 def test_gradient_matches_oracle(ctx):
     t = torch()
     b, F, y = frontier_features()
