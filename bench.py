@@ -184,11 +184,9 @@ def main():
         ws_s = ctx.workspace(P.OP_SELECT, b.max_ids, b.nseg)
 
     def step():
-        if cls is not None:
-            ctx.select(b, P.SEL_LEARNED, cls, fallbacks=fb, ws=ws_s)
-            ctx.encode(b, out, sbo, classes=cls, ws=ws_e)
-        else:
-            ctx.encode(b, out, sbo, mode=mode, ws=ws_e)
+        # the learned choice runs inside the pack pass (matrix-core inference
+        # per unit of 8 blocks)
+        ctx.encode(b, out, sbo, mode=mode, ws=ws_e)
         ctx.decode(out, sbo, b.nseg, N, dec, doff, ws=ws_d)
 
     if args.tune:
@@ -202,6 +200,11 @@ def main():
     assert torch.equal(dec[:N], b.ids[:N]), "round trip differs"
     sbo_h = sbo.cpu().numpy().view(np.uint64)
     comp = int(sbo_h[-1])
+    if cls is not None:
+        # the classes of the separate selection pass, for the oracle check
+        # (the fused pass picks the same ones)
+        ctx.select(b, P.SEL_LEARNED, cls, fallbacks=fb, ws=ws_s)
+        ctx.sync()
     check_segments(out, sbo_h, b, host, mode, cls=None if cls is None else cls.cpu().numpy())
     levels = ratio_per_level(sbo_h, host)
 
@@ -319,21 +322,46 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
                              "ms_per_step": round(xms, 4), "compressed_bytes": xcomp,
                              "learned_size_gap_pct": round(100.0 * (comp - xcomp) / xcomp, 3),
                              "learned_vs_exhaustive_speed": round(xms / ms_step, 3)}
+        # the two-pass form: a selection pass writes the class vector, then the
+        # encoder reads it
+        cls2 = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda")
+        fb2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+        def tstep():
+            ctx.select(b, P.SEL_LEARNED, cls2, fallbacks=fb2)
+            ctx.encode(b, buf, sbo, classes=cls2)
+            ctx.decode(buf, sbo, b.nseg, N, dec, doff)
+
+        tstep()
+        ctx.sync()
+        assert int(sbo[-1].item()) == comp, "two-pass learned size differs from the fused one"
+        fb2.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            tstep()
+        torch.cuda.synchronize()
+        tms = (time.perf_counter() - t) * 1e3 / steps
+        nblk = int(sum((np.diff(host["seg_off"].astype(np.int64)) + 127) // 128))
+        out["learned_two_pass"] = {"value_GBps": round(4.0 * N / (tms * 1e-3) / 1e9, 2),
+                                   "ms_per_step": round(tms, 4),
+                                   "fallback_rate": round(int(fb2.item()) / steps / max(1, nblk), 5)}
     elif os.path.exists(wpath):
         ctx.mlp_set_weights(np.load(wpath, allow_pickle=False))
         cls = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda")
         fb = torch.zeros(1, dtype=torch.int64, device="cuda")
 
         def lstep():
-            ctx.select(b, P.SEL_LEARNED, cls, fallbacks=fb)
-            ctx.encode(b, buf, sbo, classes=cls)
+            ctx.encode(b, buf, sbo, mode=P.SEL_LEARNED)
             ctx.decode(buf, sbo, b.nseg, N, dec, doff)
 
         lstep()
         ctx.sync()
         assert torch.equal(dec[:N], b.ids[:N]), "learned round trip differs"
         lcomp = int(sbo[-1].item())
-        fb.zero_()
+        # fallbacks are counted by the separate selection pass
+        ctx.select(b, P.SEL_LEARNED, cls, fallbacks=fb)
+        ctx.sync()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
@@ -346,7 +374,7 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
                           "ms_per_step": round(lms, 4),
                           "compressed_bytes": lcomp,
                           "size_gap_vs_exhaustive_pct": round(100.0 * (lcomp - comp) / comp, 3),
-                          "fallback_rate": round(int(fb.item()) / steps / max(1, nblk), 5),
+                          "fallback_rate": round(int(fb.item()) / max(1, nblk), 5),
                           "vs_exhaustive_speed": round(ms_step / lms, 3)}
 
     # one launch per segment (the same kernels, a one-segment batch each); on
@@ -390,7 +418,7 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
                                    "ms_per_step": round(pms, 3), "value_GBps": round(pg, 2),
                                    "batched_speedup": round(4.0 * N / (ms_step * 1e-3) / 1e9 / pg, 2)}
 
-    out["per_level_root0"] = per_level(ctx, P, torch, b, host, mode, cls_mode=mode)
+    out["per_level_root0"] = per_level(ctx, P, torch, b, host, mode)
     out["mall_cold"] = mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps)
 
     # per-level pipeline for the first root: graph replay vs eager launches
@@ -417,7 +445,7 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
     return out
 
 
-def per_level(ctx, P, torch, b, host, mode, cls_mode, reps=10):
+def per_level(ctx, P, torch, b, host, mode, reps=10):
     """The first root's levels, one batch per level: IDs, ratio, enc+dec time
     and rate, and the exhaustive class histogram (bitmap / bit-pack / PFOR)."""
     lev, so = host["seg_level"], host["seg_off"].astype(np.int64)
@@ -441,14 +469,8 @@ def per_level(ctx, P, torch, b, host, mode, cls_mode, reps=10):
         sbo = torch.zeros(nseg + 1, dtype=torch.int64, device="cuda")
         d = torch.empty(n, dtype=torch.int32, device="cuda")
         doff = torch.zeros(nseg + 1, dtype=torch.int64, device="cuda")
-        lcls = torch.zeros(sb.n_blocks_max, dtype=torch.uint8, device="cuda") if mode == P.SEL_LEARNED else None
-
         def one():
-            if lcls is not None:
-                ctx.select(sb, P.SEL_LEARNED, lcls)
-                ctx.encode(sb, o, sbo, classes=lcls)
-            else:
-                ctx.encode(sb, o, sbo, mode=mode)
+            ctx.encode(sb, o, sbo, mode=mode)
             ctx.decode(o, sbo, nseg, n, d, doff)
 
         one()
@@ -472,16 +494,11 @@ def mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps):
     nothing of the batch is left in the 256 MB MALL; only the codec is timed
     (stream events around it)."""
     scratch = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
-    lcls = torch.zeros(b.n_blocks_max, dtype=torch.uint8, device="cuda") if mode == P.SEL_LEARNED else None
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for i in range(steps):
         scratch.fill_(i)
         ev[i][0].record()
-        if lcls is not None:
-            ctx.select(b, P.SEL_LEARNED, lcls)
-            ctx.encode(b, buf, sbo, classes=lcls)
-        else:
-            ctx.encode(b, buf, sbo, mode=mode)
+        ctx.encode(b, buf, sbo, mode=mode)
         ctx.decode(buf, sbo, b.nseg, N, dec, doff)
         ev[i][1].record()
     torch.cuda.synchronize()

@@ -194,7 +194,11 @@ int bfsc_encode_bound(uint64_t n_ids, uint32_t nseg, size_t *bytes);
 
 /* Compresses a batch (the compress step before each exchange of the
  * BFS-with-compression algorithm).  classes: u8 per block as produced by
- * bfsc_select, or NULL to choose with `mode` inside the encoder.  Writes the
+ * bfsc_select, or NULL to choose with `mode` inside the encoder; with
+ * BFSC_SEL_LEARNED and NULL classes the network runs inside the pack pass
+ * (on the matrix cores, per unit of 8 blocks) and the stream equals the one
+ * that bfsc_select + bfsc_encode produce (fallbacks are not counted).  The
+ * batch's seg_level is then a feature and must be given.  Writes the
  * segments back to back into out (capacity out_cap bytes) and
  * seg_byte_off u64[nseg+1] (device): segment r occupies
  * out[seg_byte_off[r] .. seg_byte_off[r+1]).  Overflow latches

@@ -211,7 +211,7 @@ int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int 
     plan_layout(ws, b->max_ids, b->nseg, true, &p);
     int st = launch_plan_prep(b, p, ctx->err, true, S(stream));
     if (st) return st;
-    if (mode == BFSC_SEL_LEARNED && !classes) return BFSC_E_INVAL;  // select first, then encode
+    if (mode == BFSC_SEL_LEARNED && !classes && !b->seg_level) return BFSC_E_INVAL;
     return launch_encode(ctx, b, classes, mode, out, out_cap, seg_byte_off, p, S(stream));
 }
 

@@ -387,6 +387,8 @@ struct EncArgs {
     Plan p;
     uint32_t *err;
     uint32_t strided;       // unit order of the staged pack pass (else contiguous per wave)
+    const int32_t *seg_level;  // BFS level per segment (learned choice: a feature)
+    const MlpMfma *w;          // the network in MFMA operand order (learned choice)
 };
 
 // Segment and metadata of one encoder tile.
@@ -471,6 +473,25 @@ __device__ void finish_offsets(const EncArgs &a, uint32_t units) {
     }
 }
 
+__device__ __forceinline__ uint16_t f16bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+// Eight selector features of a block (identical arithmetic to the spec in bfsc.h).
+__device__ __forceinline__ void block_features(const BlockStats &S, uint32_t seg_n, int32_t level,
+                                               float f[8]) {
+    const int32_t L = level < 0 ? 0 : (level > 63 ? 63 : level);
+    f[0] = (float)S.nk / 128.0f;
+    f[1] = S.m ? (float)bitlen32(S.dmin) / 32.0f : 0.0f;
+    f[2] = S.m ? (float)S.wmin / 32.0f : 0.0f;
+    f[3] = S.m ? (float)bitlen32(S.span / S.m) / 32.0f : 0.0f;
+    f[4] = (float)bitlen32(S.span) / 32.0f;
+    f[5] = __fdiv_rn((float)S.nk, (float)((uint64_t)S.span + 1ull));
+    f[6] = (float)L / 64.0f;
+    f[7] = (float)bitlen32(seg_n) / 32.0f;
+}
+
 // ORs a field (v < 2^32, at most 32 bits) into the LDS words at bit pos, the
 // spilled high part into the next word unconditionally (it is 0 when the
 // field does not cross a word boundary): no branches.
@@ -480,13 +501,47 @@ __device__ __forceinline__ void or_field(uint32_t *buf, uint32_t pos, uint32_t v
     atomicOr(&buf[wi + 1], sh ? v >> (32 - sh) : 0u);
 }
 
-// Full block (128 IDs) whose class the encoder picks itself (plain minimal
-// width or exhaustive): the same choice as choose(), computed with scalar
-// selects, and bit-pack / bitmap payloads packed without branches.  A PFOR
-// choice (which always has exceptions) is packed by the general routine.
+// PFOR payload of a full block into zeroed LDS words: the low b bits of every
+// delta as a bit-pack at width b, then the E exception positions (bytes,
+// j - 1, ascending) and their high parts (h bits each).  Only the lanes that
+// hold an exception (at most 12) write the last two parts.
+__device__ __forceinline__ void pack_pfor_full(uint32_t *buf, uint32_t da, uint32_t db, uint32_t b,
+                                               uint32_t E, uint32_t h, uint32_t lane) {
+    constexpr uint32_t m = kBlock - 1;
+    const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : (1u << b) - 1u;
+    or_field(buf, (lane ? lane - 1 : 0u) * b, da & mask);
+    or_field(buf, (63 + lane) * b, db & mask);
+    if (E) {
+        const uint32_t lw = (m * b + 31) >> 5, qw = (E + 3) >> 2;
+        const bool xa = da > mask, xb = db > mask;
+        const uint64_t ma = ballot(xa), mb = ballot(xb), lt = lanemask_lt();
+        if (xa) {
+            const uint32_t e = popc64(ma & lt);
+            or_field(buf, lw * 32 + e * 8, lane - 1);
+            or_field(buf, (lw + qw) * 32 + e * h, da >> b);
+        }
+        if (xb) {
+            const uint32_t e = popc64(ma) + popc64(mb & lt);
+            or_field(buf, lw * 32 + e * 8, 63 + lane);
+            or_field(buf, (lw + qw) * 32 + e * h, db >> b);
+        }
+    }
+}
+
+// What enc_full encodes a block as: the plain minimal width, the exhaustive
+// choice, or (a resolved learned choice) the bitmap or PFOR with its best b.
+enum FullSel : int { kSelPlain = 0, kSelExhaustive = 1, kSelBitmap = 2, kSelPfor = 3 };
+
+// Full block (128 IDs) whose class the encoder picks itself or is handed:
+// the same choice as choose(), computed with scalar selects, and bit-pack /
+// bitmap payloads packed without branches.  PFOR payloads are packed by the
+// general routine.  kSelBitmap requires span <= 4096.
+// wmin_known: the block's minimal width when the caller has it already, else
+// a negative value.
 __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t lo, uint32_t hi,
-                                             bool exhaustive, uint32_t *dir, uint32_t *dst,
-                                             uint32_t *buf, uint32_t lane, uint32_t *err) {
+                                             int sel, uint32_t *dir, uint32_t *dst,
+                                             uint32_t *buf, uint32_t lane, uint32_t *err,
+                                             int wmin_known = -1) {
     constexpr uint32_t m = kBlock - 1;
     const uint32_t a63 = readlane(va, 63);
     const uint32_t pa = lane_prev(va, 0u);
@@ -499,14 +554,19 @@ __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t 
     if ((bad != 0ull) | (v0 < lo) | (vlast >= hi)) {
         if (lane == 0) raise_err(err, kErrInval);
     }
-    const uint32_t wmin = bitlen32(wave_max(max(da, db)));
+    const uint32_t wmin = wmin_known >= 0 ? (uint32_t)wmin_known : bitlen32(wave_max(max(da, db)));
     const uint32_t span = vlast - v0;
     const uint32_t bpw = (m * wmin + 31) >> 5;
     uint32_t cls = 1 + wmin, param = wmin, aux = 0, words = bpw;
     uint32_t pfb = wmin, pfe = 0;
-    if (exhaustive) {
+    if (sel == kSelBitmap) {
+        cls = kClsBitmap;
+        param = 0;
+        aux = span;
+        words = (span + 31) >> 5;
+    } else if (sel >= kSelExhaustive) {
         const uint32_t bmw = (span + 31) >> 5;
-        if ((span <= kBitmapMaxSpan) & (bmw < words)) {
+        if ((sel == kSelExhaustive) & (span <= kBitmapMaxSpan) & (bmw < words)) {
             cls = kClsBitmap;
             param = 0;
             aux = span;
@@ -517,7 +577,7 @@ __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t 
         // words: widths whose bound reaches the best so far cannot be chosen
         // and are skipped (b <= (32 (words - 3)) / m is the largest candidate).
         uint32_t best = bpw;
-        const uint32_t bcap = words >= 3 ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
+        const uint32_t bcap = sel == kSelPfor ? wmin : words >= 3 ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
         uint32_t low = m * bcap, h = wmin - bcap;
         for (uint32_t b = bcap; b-- > 0;) {
             low -= m;
@@ -532,10 +592,10 @@ __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t 
                 pfe = e;
             }
         }
-        if (best < words) {
+        if ((best < words) | (sel == kSelPfor)) {
             cls = kClsPfor;
             param = pfb;
-            aux = pfe | ((wmin - pfb) << 8);
+            aux = pfe | (pfe ? (wmin - pfb) << 8 : 0u);
             words = best;
         }
     }
@@ -546,28 +606,7 @@ __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (cls == kClsPfor) {
-        BlockRegs R;
-        R.da = da;
-        R.db = db;
-        R.oa = va - v0;
-        R.ob = vb - v0;
-        R.hasa = lane >= 1;
-        R.hasb = true;
-        BlockStats S;
-        S.nk = kBlock;
-        S.m = m;
-        S.v0 = v0;
-        S.span = span;
-        S.dmin = 0;
-        S.dmax = 0;
-        S.wmin = wmin;
-        BlockInfo I;
-        I.cls = cls;
-        I.param = param;
-        I.aux = aux;
-        I.words = words;
-        I.first = 0;
-        pack_block(buf, I, R, S, lane);
+        pack_pfor_full(buf, da, db, param, aux & 0xFFu, aux >> 8, lane);
     } else if (cls == kClsBitmap) {
         // bit o-1 for offset o = v - v0 >= 1 (the first value is implied); the
         // word index is kept inside the buffer even for unsorted input,
@@ -602,7 +641,8 @@ __device__ __forceinline__ uint32_t enc_block(uint32_t va, uint32_t vb, uint32_t
                                               uint32_t lane, uint32_t *err) {
     if constexpr (FULL) {
         if (given < 0 && !SCANPACK)
-            return enc_full(va, vb, lo, hi, mode != BFSC_SEL_PLAIN_BP, dir, dst, buf, lane, err);
+            return enc_full(va, vb, lo, hi, mode == BFSC_SEL_PLAIN_BP ? kSelPlain : kSelExhaustive, dir, dst,
+                            buf, lane, err);
         nk = kBlock;
     } else {
         nk = readfirst(nk);
@@ -769,6 +809,122 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
     }
 }
 
+// Pack pass with the learned choice fused in, one wave per unit.  The wave
+// stages the unit's IDs in LDS, computes every block's eight fp16 features,
+// evaluates the network for the unit's blocks at once on the matrix cores
+// (block k is sample k, the other rows zero), resolves each prediction
+// (bitmap if it is valid, bit-pack at the minimal width, PFOR at its best b,
+// the exhaustive choice when the bitmap is invalid or a logit is NaN) and
+// packs the blocks from LDS.  The logits of a sample depend only on its own
+// features, so the classes equal those of the separate selection pass.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
+    constexpr uint32_t kIds = kHalf * kBlock;
+    constexpr uint32_t kPerLane = kIds / 64;
+    __shared__ MlpMfma s_w;
+    __shared__ uint32_t s_ids[WAVES][kIds];
+    __shared__ uint32_t s_buf[WAVES][132];
+    __shared__ uint16_t s_x[WAVES][kHalf][kIn];
+    __shared__ uint32_t s_span[WAVES][kHalf];
+    __shared__ uint32_t s_wmin[WAVES][kHalf];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    mlp_mfma_stage(&s_w, a.w, tid, WAVES * 64);
+    __syncthreads();
+    const uint32_t units = 2 * readfirst(a.p.tile_base[a.nseg]);
+    uint32_t *sid = s_ids[w];
+    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    SegCursor c;
+    int32_t level = 0;
+    for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
+        const uint32_t t = u >> 1, h = u & 1;
+        if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
+            c.bb = readfirst(a.p.blk_base[c.r]);
+            c.nb = readfirst(a.p.blk_base[c.r + 1]) - c.bb;
+            c.n = readfirst(a.p.seg_n[c.r]);
+            c.lo = readfirst(a.seg_lo[c.r]);
+            c.hi = readfirst(a.seg_hi[c.r]);
+            c.base = readfirst64(a.seg_off[c.r]);
+            level = a.seg_level ? (int32_t)readfirst((uint32_t)a.seg_level[c.r]) : 0;
+        }
+        const uint32_t g = t - c.t_first;
+        const uint32_t nb = c.nb;
+        const uint32_t k0 = g * kGroup + h * kHalf;
+        const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
+        uint32_t run = 0;
+        if (nblk) {
+            const uint32_t n = c.n, lo = c.lo, hi = c.hi;
+            const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
+            const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+            uint32_t v[kPerLane];
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) sid[lane + 64 * i] = v[i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // features of every block
+            for (uint32_t kk = 0; kk < nblk; ++kk) {
+                const uint32_t nk = readfirst(min(kBlock, cnt - kk * kBlock));
+                const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
+                BlockRegs R;
+                BlockStats S;
+                if (nk == kBlock)
+                    analyze_block(va, vb, kBlock, lo, hi, lane, true, R, S, a.err);
+                else
+                    analyze_block(va, vb, nk, lo, hi, lane, true, R, S, a.err);
+                if (lane == 0) s_wmin[w][kk] = S.wmin;
+                float f[8];
+                block_features(S, n, level, f);
+                float fv = f[0];
+#pragma unroll
+                for (int q = 1; q < 8; ++q) fv = lane == (uint32_t)q ? f[q] : fv;
+                if (lane < 8) s_x[w][kk][lane] = f16bits(fv);
+                if (lane == 0) s_span[w][kk] = S.span;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // the network on the unit's blocks
+            half4_t x = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+            const uint32_t smp = lane & 15;
+            if (lane < 32 && smp < nblk) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[j] = __builtin_bit_cast(_Float16, s_x[w][smp][(lane >> 4) * 4 + j]);
+            }
+            float4_t z[3];
+            // operand tiles are read from LDS here, not kept in registers
+            // across the unit loop (that would cost 64 VGPRs of occupancy)
+            __asm__ volatile("" ::: "memory");
+            mlp16(s_w, x, lane, z);
+            const uint32_t pred = mlp16_argmax(z, lane);
+            // resolve and pack
+            uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+            uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
+            for (uint32_t kk = 0; kk < nblk; ++kk) {
+                const uint32_t nk = min(kBlock, cnt - kk * kBlock);
+                const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
+                const uint32_t p = readlane(pred, kk);
+                const bool bitmap_ok = s_span[w][kk] <= kBitmapMaxSpan;
+                // resolved selection: -1 exhaustive, else the class to use
+                const int sel = p == 255u ? kSelExhaustive
+                                : p == kClsBitmap ? (bitmap_ok ? kSelBitmap : kSelExhaustive)
+                                : p <= 33u ? kSelPlain : kSelPfor;
+                uint32_t *dir = slot + 2 * (h * kHalf + kk), *dst = pay + run;
+                if (nk == kBlock) {
+                    run += enc_full(va, vb, lo, hi, sel, dir, dst, s_buf[w], lane, a.err, (int)s_wmin[w][kk]);
+                } else {
+                    // the last block of a segment: the general routine with the
+                    // resolved class (BP at the minimal width is what plain picks)
+                    const int given = sel == kSelBitmap ? (int)kClsBitmap : sel == kSelPfor ? (int)kClsPfor : -1;
+                    const int mode = sel == kSelPlain ? BFSC_SEL_PLAIN_BP : BFSC_SEL_EXHAUSTIVE;
+                    run += enc_block<false, false>(va, vb, nk, lo, hi, mode, given, dir, dst, s_buf[w], nullptr,
+                                                   nullptr, lane, a.err);
+                }
+            }
+        }
+        if (lane == 0) a.p.unit_words[u] = run;
+    }
+}
+
 // One workgroup: unit sizes -> offsets and the batch end.
 __global__ __launch_bounds__(1024) void k_enc_scan(EncArgs a) {
     finish_offsets(a, 2 * a.p.tile_base[a.nseg]);
@@ -837,25 +993,6 @@ struct SelArgs {
     Plan p;
     uint32_t *err;
 };
-
-__device__ __forceinline__ uint16_t f16bits(float x) {
-    _Float16 h = (_Float16)x;
-    return __builtin_bit_cast(uint16_t, h);
-}
-
-// Eight selector features of a block (identical arithmetic to the spec in bfsc.h).
-__device__ __forceinline__ void block_features(const BlockStats &S, uint32_t seg_n, int32_t level,
-                                               float f[8]) {
-    const int32_t L = level < 0 ? 0 : (level > 63 ? 63 : level);
-    f[0] = (float)S.nk / 128.0f;
-    f[1] = S.m ? (float)bitlen32(S.dmin) / 32.0f : 0.0f;
-    f[2] = S.m ? (float)S.wmin / 32.0f : 0.0f;
-    f[3] = S.m ? (float)bitlen32(S.span / S.m) / 32.0f : 0.0f;
-    f[4] = (float)bitlen32(S.span) / 32.0f;
-    f[5] = __fdiv_rn((float)S.nk, (float)((uint64_t)S.span + 1ull));
-    f[6] = (float)L / 64.0f;
-    f[7] = (float)bitlen32(seg_n) / 32.0f;
-}
 
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
@@ -1411,10 +1548,23 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     a.p = p;
     a.err = ctx->err;
     a.strided = (ctx->tune.enc_pack >> 2) & 1u;
+    a.seg_level = b->seg_level;
+    a.w = (const MlpMfma *)ctx->mlp_mfma;
     const uint32_t waves = ctx->tune.enc_waves;
     const uint64_t units = 2ull * p.max_tiles;
     const uint32_t per_cu = ctx->tune.enc_wg_per_cu;
     const int slot = timing_begin(ctx, BFSC_OP_ENCODE, s);
+    const bool fused_learned = !classes && mode == BFSC_SEL_LEARNED;
+    if (fused_learned) {
+        // staged units; at most 8 waves per workgroup (the network is staged
+        // once per workgroup)
+        switch (waves) {
+            case 1: hipLaunchKernelGGL((k_enc_pack_l<1>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<1>, 64, per_cu, units)), dim3(64), 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_enc_pack_l<2>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<2>, 128, per_cu, units)), dim3(128), 0, s, a); break;
+            case 8: case 16: hipLaunchKernelGGL((k_enc_pack_l<8>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<8>, 512, per_cu, units)), dim3(512), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_enc_pack_l<4>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<4>, 256, per_cu, units)), dim3(256), 0, s, a); break;
+        }
+    } else
     switch (waves) {
 #define BFSC_PACK_LAUNCH(K, W)                                                               \
     hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \

@@ -187,3 +187,53 @@ def test_trained_selector_on_gpu_gains_over_plain(ctx):
         exh += oracle.encode(b, mode=oracle.EXHAUSTIVE)[0].size
     assert learned <= 0.85 * plain, (learned, plain)
     assert learned <= 1.02 * exh, (learned, exh)
+
+
+def _codec_batches():
+    from test_gpu_codec import batches
+    return [b for name, b in batches()] + [b for b in _held_out()]
+
+
+def _held_out():
+    from test_selector_trained import held_out_batches
+    return held_out_batches()
+
+
+@pytest.mark.parametrize("weights", ["random", "trained"])
+@pytest.mark.parametrize("waves,strided", [(4, 1), (4, 0), (1, 1), (2, 1), (8, 1)])
+def test_fused_learned_encode_equals_two_pass(ctx, weights, waves, strided):
+    """bfsc_encode with the learned mode and no class vector (the network
+    inside the pack pass) writes the same bytes as bfsc_select + bfsc_encode,
+    and those are the oracle's encoding of the selected classes.  Random
+    weights reach every resolve branch, fallbacks included."""
+    import os
+    from test_selector_trained import WEIGHTS
+    if weights == "trained":
+        if not os.path.exists(WEIGHTS):
+            pytest.skip("selector not trained")
+        theta = np.load(WEIGHTS, allow_pickle=False)
+    else:
+        theta = inputs.mlp_init(11)
+        theta[::3] *= 4.0
+    ctx.mlp_set_weights(theta)
+    before = ctx.get_tune()
+    ctx.set_tune(enc_waves=waves, enc_pack=4 * strided)
+    try:
+        seen = set()
+        for b in _codec_batches():
+            print("fused learned n=%d nseg=%d" % (b.n_ids, b.nseg), flush=True)
+            st, cls, fb = gpu_select(ctx, b, 2)
+            assert st == 0
+            seen.update(np.unique(cls).tolist())
+            st, two, two_off = gpu_encode(ctx, b, classes=cls)
+            assert st == 0
+            st, fused, fused_off = gpu_encode(ctx, b, mode=2)
+            assert st == 0
+            np.testing.assert_array_equal(fused_off, two_off)
+            np.testing.assert_array_equal(fused, two)
+            want, want_off = oracle.encode(b, classes=cls)
+            np.testing.assert_array_equal(fused, want)
+        if weights == "random":
+            assert len(seen) >= 2
+    finally:
+        ctx.set_tune(**before)
