@@ -416,63 +416,6 @@ __device__ __forceinline__ EncTile enc_tile_meta(const Plan &p, const uint64_t *
     return m;
 }
 
-// Unit sizes to offsets (one workgroup, after the pack pass): unit_off =
-// exclusive prefix of unit_words; the batch end goes to seg_byte_off[nseg].
-__device__ void finish_offsets(const EncArgs &a, uint32_t units) {
-    __shared__ uint32_t s_wt[16];
-    __shared__ unsigned long long s_carry;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t nthr = blockDim.x, nw = nthr >> 6;
-    constexpr uint32_t kPer = 16;  // units per thread per pass
-    if (tid == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t base = 0; base < units; base += nthr * kPer) {
-        uint32_t v[kPer];
-        uint32_t sum = 0;
-        const uint32_t t0 = base + tid * kPer;
-        if (t0 + kPer <= units) {
-            const uint4 *src = (const uint4 *)(a.p.unit_words + t0);
-#pragma unroll
-            for (uint32_t k = 0; k < kPer / 4; ++k) {
-                const uint4 x = src[k];
-                v[4 * k] = x.x;
-                v[4 * k + 1] = x.y;
-                v[4 * k + 2] = x.z;
-                v[4 * k + 3] = x.w;
-            }
-        } else {
-#pragma unroll
-            for (uint32_t k = 0; k < kPer; ++k) v[k] = (t0 + k < units) ? a.p.unit_words[t0 + k] : 0u;
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) sum += v[k];
-        const uint32_t incl = wave_incl_scan(sum);
-        if (lane == 63) s_wt[w] = incl;
-        __syncthreads();
-        uint32_t wb = 0, tot = 0;
-        for (uint32_t q = 0; q < nw; ++q) {
-            wb += q < w ? s_wt[q] : 0u;
-            tot += s_wt[q];
-        }
-        uint64_t run = s_carry + wb + incl - sum;
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) {
-            if (t0 + k < units) a.p.unit_off[t0 + k] = run;
-            run += v[k];
-        }
-        __syncthreads();
-        if (tid == 0) s_carry += tot;
-        __syncthreads();
-    }
-    const uint64_t total_words = s_carry;
-    if (tid == 0) {
-        const uint64_t end = 16ull * a.nseg + 8ull * a.p.blk_base[a.nseg] + 4ull * a.p.grp_base[a.nseg] +
-                             4ull * total_words;
-        a.seg_byte_off[a.nseg] = end;
-        if (end > a.out_cap) raise_err(a.err, kErrCapacity);
-    }
-}
-
 __device__ __forceinline__ uint16_t f16bits(float x) {
     _Float16 h = (_Float16)x;
     return __builtin_bit_cast(uint16_t, h);
@@ -925,9 +868,41 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
     }
 }
 
-// One workgroup: unit sizes -> offsets and the batch end.
+// Unit sizes -> offsets, one workgroup per chunk of kScanChunk units (4 per
+// thread, coalesced 16-byte loads and stores): the offsets within the chunk
+// and the chunk's total.  The place pass adds the totals of the chunks before.
 __global__ __launch_bounds__(1024) void k_enc_scan(EncArgs a) {
-    finish_offsets(a, 2 * a.p.tile_base[a.nseg]);
+    __shared__ uint32_t s_tmp[17];
+    const uint32_t units = 2 * readfirst(a.p.tile_base[a.nseg]);
+    const uint32_t c0 = blockIdx.x * kScanChunk;
+    if (c0 >= units) return;
+    const uint32_t i0 = c0 + 4 * threadIdx.x;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (i0 + 4 <= units) {
+        v = *(const uint4 *)(a.p.unit_words + i0);
+    } else if (i0 < units) {
+        v.x = a.p.unit_words[i0];
+        v.y = i0 + 1 < units ? a.p.unit_words[i0 + 1] : 0u;
+        v.z = i0 + 2 < units ? a.p.unit_words[i0 + 2] : 0u;
+    }
+    uint32_t total;
+    const uint32_t ex = wg_excl_scan(v.x + v.y + v.z + v.w, s_tmp, &total);
+    const uint4 o = {ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z};
+    if (i0 + 4 <= units) {
+        *(uint4 *)(a.p.unit_off + i0) = o;
+    } else if (i0 < units) {
+        a.p.unit_off[i0] = o.x;
+        if (i0 + 1 < units) a.p.unit_off[i0 + 1] = o.y;
+        if (i0 + 2 < units) a.p.unit_off[i0 + 2] = o.z;
+    }
+    if (threadIdx.x == 0) a.p.chunk_words[blockIdx.x] = total;
+}
+
+// Payload words before the first `chunks` chunks (the whole wave).
+__device__ __forceinline__ uint64_t chunk_prefix(const uint32_t *chunk_words, uint32_t chunks, uint32_t lane) {
+    uint64_t s = 0;
+    for (uint32_t k = lane; k < chunks; k += 64) s += chunk_words[k];
+    return wave_sum64(s);
 }
 
 // Place pass, one wave per tile (tiles are independent, so every wave's
@@ -948,9 +923,24 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t nb = readfirst(a.p.blk_base[r + 1]) - bb;
     const uint32_t gb = readfirst(a.p.grp_base[r]);
     const uint32_t ng = readfirst(a.p.grp_base[r + 1]) - gb;
-    const uint64_t P = readfirst64(a.p.unit_off[2 * t_first]);
+    // payload words before the segment and before the tile (unit 2t)
+    const uint32_t cf = 2 * t_first / kScanChunk, ct = 2 * t / kScanChunk;
+    const uint64_t Pf = chunk_prefix(a.p.chunk_words, cf, lane);
+    const uint64_t P = Pf + readfirst(a.p.unit_off[2 * t_first]);
+    const uint64_t Pt = (ct == cf ? Pf : chunk_prefix(a.p.chunk_words, ct, lane)) + readfirst(a.p.unit_off[2 * t]);
     const uint64_t sw = (16ull * r + 8ull * bb + 4ull * gb + 4ull * P) >> 2;
     const uint32_t g = t - t_first;
+    if (t == 0) {
+        // the batch end, from the totals of all chunks
+        const uint32_t units = 2 * total;
+        const uint64_t words = chunk_prefix(a.p.chunk_words, (units + kScanChunk - 1) / kScanChunk, lane);
+        if (lane == 0) {
+            const uint64_t end = 16ull * a.nseg + 8ull * a.p.blk_base[a.nseg] + 4ull * a.p.grp_base[a.nseg] +
+                                 4ull * words;
+            a.seg_byte_off[a.nseg] = end;
+            if (end > a.out_cap) raise_err(a.err, kErrCapacity);
+        }
+    }
     if (g == 0 && lane < 4) {
         if (lane == 0) a.seg_byte_off[r] = sw << 2;
         if (sw + 4 <= capw) {
@@ -961,7 +951,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t k0 = g * kGroup;
     const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
     if (!nblk) return;
-    const uint64_t rel = readfirst64(a.p.unit_off[2 * t]) - P;
+    const uint64_t rel = Pt - P;
     const uint32_t A0 = readfirst(a.p.unit_words[2 * t]), A1 = readfirst(a.p.unit_words[2 * t + 1]);
     const uint64_t pwb = sw + 4 + 2ull * nb + ng + rel;
     const uint64_t dwb = sw + 4 + 2ull * k0;
@@ -1585,7 +1575,8 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
 #undef BFSC_PACK_CASE
     }
     timing_end(ctx, slot, s);
-    hipLaunchKernelGGL(k_enc_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_enc_scan, dim3((uint32_t)((2ull * p.max_tiles + kScanChunk - 1) / kScanChunk)), dim3(1024),
+                       0, s, a);
     const int slot2 = timing_begin(ctx, BFSC_OP_ENCODE_PLACE, s);
     hipLaunchKernelGGL(k_enc_place<4>, dim3((uint32_t)((p.max_tiles + 3) / 4)), dim3(256), 0, s, a);
     timing_end(ctx, slot2, s);

@@ -153,6 +153,10 @@ constexpr uint32_t kHalf = kGroup / 2;                 // blocks per pack unit
 constexpr uint32_t kSlotDirWords = 2 * kGroup;
 constexpr uint32_t kSlotHalfWords = kHalf * kBlock;    // payload words of a unit, at most
 constexpr uint32_t kSlotWords = kSlotDirWords + 2 * kSlotHalfWords;
+// Units per chunk of the offset scan (one workgroup of 1024 threads, 4 units
+// each); a chunk holds at most 4096 x 1024 payload words, so chunk-local
+// offsets and chunk totals fit 32 bits.
+constexpr uint32_t kScanChunk = 4096;
 
 struct Plan {
     uint32_t *blk_base;   // [nseg+1] first global block of each segment
@@ -161,7 +165,8 @@ struct Plan {
     uint32_t *seg_n;      // [nseg]   IDs per segment (0 for a rejected segment)
     uint32_t *counter;    // [4]      [0]: workgroups done with the pack pass
     uint32_t *unit_words; // [2 max_tiles] payload words per unit (unit 2t + h: half h of tile t)
-    uint64_t *unit_off;   // [2 max_tiles] exclusive prefix of unit_words
+    uint32_t *unit_off;   // [2 max_tiles] exclusive prefix of unit_words within the unit's chunk
+    uint32_t *chunk_words;  // [chunks] payload words of every chunk of kScanChunk units
     uint32_t *slots;      // [max_tiles][kSlotWords] (encode only)
     uint32_t max_tiles;
 };
@@ -192,8 +197,10 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     off = align256(off + 16);
     if (p) p->unit_words = (uint32_t *)(b + off);
     off = align256(off + 2 * mt * 4);
-    if (p) p->unit_off = (uint64_t *)(b + off);
-    off = align256(off + 2 * mt * 8);
+    if (p) p->unit_off = (uint32_t *)(b + off);
+    off = align256(off + 2 * mt * 4);
+    if (p) p->chunk_words = (uint32_t *)(b + off);
+    off = align256(off + ((2 * mt + kScanChunk - 1) / kScanChunk) * 4);
     if (p) p->slots = slots ? (uint32_t *)(b + off) : nullptr;
     if (slots) off = align256(off + mt * (size_t)kSlotWords * 4);
     if (p) p->max_tiles = (uint32_t)mt;
