@@ -118,8 +118,13 @@ struct BlockStats {
 
 __device__ __forceinline__ void fetch_block(const uint32_t *ids, uint32_t nk, uint32_t lane,
                                             uint32_t &va, uint32_t &vb) {
-    va = lane < nk ? ids[lane] : 0u;
-    vb = lane + 64 < nk ? ids[64 + lane] : 0u;
+    if (nk == kBlock) {  // uniform: no per-lane masks for a full block
+        va = ids[lane];
+        vb = ids[64 + lane];
+    } else {
+        va = lane < nk ? ids[lane] : 0u;
+        vb = lane + 64 < nk ? ids[64 + lane] : 0u;
+    }
 }
 
 __device__ __forceinline__ void analyze_block(uint32_t va, uint32_t vb, uint32_t nk, uint32_t lo,
@@ -481,8 +486,10 @@ enum FullSel : int { kSelPlain = 0, kSelExhaustive = 1, kSelBitmap = 2, kSelPfor
 // general routine.  kSelBitmap requires span <= 4096.
 // wmin_known: the block's minimal width when the caller has it already, else
 // a negative value.
+// The block's two directory words are returned in d0 / d1 (the caller
+// collects a unit's entries in a register and stores them once).
 __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t lo, uint32_t hi,
-                                             int sel, uint32_t *dir, uint32_t *dst,
+                                             int sel, uint32_t &d0, uint32_t &d1, uint32_t *dst,
                                              uint32_t *buf, uint32_t lane, uint32_t *err,
                                              int wmin_known = -1) {
     constexpr uint32_t m = kBlock - 1;
@@ -542,10 +549,10 @@ __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t 
             words = best;
         }
     }
-    if (lane < 2) dir[lane] = lane ? (cls | (param << 8) | (aux << 16)) : v0 - lo;
+    d0 = v0 - lo;
+    d1 = cls | (param << 8) | (aux << 16);
     buf[lane] = 0u;
     buf[lane + 64] = 0u;
-    if (lane < 4) buf[128 + lane] = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (cls == kClsPfor) {
@@ -579,12 +586,12 @@ __device__ __forceinline__ uint32_t enc_full(uint32_t va, uint32_t vb, uint32_t 
 // validity test folds away at compile time.
 template <bool FULL, bool SCANPACK>
 __device__ __forceinline__ uint32_t enc_block(uint32_t va, uint32_t vb, uint32_t nk, uint32_t lo,
-                                              uint32_t hi, int mode, int given, uint32_t *dir,
+                                              uint32_t hi, int mode, int given, uint32_t &d0, uint32_t &d1,
                                               uint32_t *dst, uint32_t *buf, uint32_t *pj, uint32_t *dj,
                                               uint32_t lane, uint32_t *err) {
     if constexpr (FULL) {
         if (given < 0 && !SCANPACK)
-            return enc_full(va, vb, lo, hi, mode == BFSC_SEL_PLAIN_BP ? kSelPlain : kSelExhaustive, dir, dst,
+            return enc_full(va, vb, lo, hi, mode == BFSC_SEL_PLAIN_BP ? kSelPlain : kSelExhaustive, d0, d1, dst,
                             buf, lane, err);
         nk = kBlock;
     } else {
@@ -594,7 +601,8 @@ __device__ __forceinline__ uint32_t enc_block(uint32_t va, uint32_t vb, uint32_t
     BlockStats S;
     analyze_block(va, vb, nk, lo, hi, lane, false, R, S, err);
     const BlockInfo I = choose(R, S, mode, given, err);
-    if (lane < 2) dir[lane] = lane ? (I.cls | (I.param << 8) | (I.aux << 16)) : S.v0 - lo;
+    d0 = S.v0 - lo;
+    d1 = I.cls | (I.param << 8) | (I.aux << 16);
     if (I.words) {
         if constexpr (SCANPACK)
             pack_block_scan(buf, pj, dj, I, R, S, lane);
@@ -726,6 +734,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
             }
             uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
             uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
+            uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
             for (uint32_t kk = 0; kk < nblk; ++kk) {
                 const uint32_t nk = min(kBlock, cnt - kk * kBlock);
                 uint32_t na = 0, nbv = 0;
@@ -736,17 +745,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
                     fetch_block(src + (kk + 1) * kBlock, min(kBlock, cnt - (kk + 1) * kBlock), lane, na, nbv);
                 }
                 const int given = a.classes ? (int)readlane(cl, kk) : -1;
-                uint32_t *dir = slot + 2 * (h * kHalf + kk), *dst = pay + run;
+                uint32_t *dst = pay + run, d0, d1;
                 run += nk == kBlock
-                           ? enc_block<true, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, dir, dst, s_buf[w],
+                           ? enc_block<true, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, d0, d1, dst, s_buf[w],
                                                        s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane, a.err)
-                           : enc_block<false, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, dir, dst, s_buf[w],
+                           : enc_block<false, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, d0, d1, dst, s_buf[w],
                                                         s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane, a.err);
+                dirv = lane == 2 * kk ? d0 : lane == 2 * kk + 1 ? d1 : dirv;
                 if constexpr (!STAGE) {
                     va = na;
                     vb = nbv;
                 }
             }
+            if (lane < 2 * nblk) slot[2 * h * kHalf + lane] = dirv;
         }
         if (lane == 0) a.p.unit_words[u] = run;
     }
@@ -842,6 +853,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             // resolve and pack
             uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
             uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
+            uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
             for (uint32_t kk = 0; kk < nblk; ++kk) {
                 const uint32_t nk = min(kBlock, cnt - kk * kBlock);
                 const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
@@ -851,18 +863,20 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
                 const int sel = p == 255u ? kSelExhaustive
                                 : p == kClsBitmap ? (bitmap_ok ? kSelBitmap : kSelExhaustive)
                                 : p <= 33u ? kSelPlain : kSelPfor;
-                uint32_t *dir = slot + 2 * (h * kHalf + kk), *dst = pay + run;
+                uint32_t *dst = pay + run, d0, d1;
                 if (nk == kBlock) {
-                    run += enc_full(va, vb, lo, hi, sel, dir, dst, s_buf[w], lane, a.err, (int)s_wmin[w][kk]);
+                    run += enc_full(va, vb, lo, hi, sel, d0, d1, dst, s_buf[w], lane, a.err, (int)s_wmin[w][kk]);
                 } else {
                     // the last block of a segment: the general routine with the
                     // resolved class (BP at the minimal width is what plain picks)
                     const int given = sel == kSelBitmap ? (int)kClsBitmap : sel == kSelPfor ? (int)kClsPfor : -1;
                     const int mode = sel == kSelPlain ? BFSC_SEL_PLAIN_BP : BFSC_SEL_EXHAUSTIVE;
-                    run += enc_block<false, false>(va, vb, nk, lo, hi, mode, given, dir, dst, s_buf[w], nullptr,
+                    run += enc_block<false, false>(va, vb, nk, lo, hi, mode, given, d0, d1, dst, s_buf[w], nullptr,
                                                    nullptr, lane, a.err);
                 }
+                dirv = lane == 2 * kk ? d0 : lane == 2 * kk + 1 ? d1 : dirv;
             }
+            if (lane < 2 * nblk) slot[2 * h * kHalf + lane] = dirv;
         }
         if (lane == 0) a.p.unit_words[u] = run;
     }
