@@ -1333,8 +1333,13 @@ __device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t b
     if (ballot(bad) != 0ull) {
         if (lane == 0) raise_err(err, kErrCorrupt);
     } else {
-        if (ina && ob + lane < out_cap) out[ob + lane] = xa;
-        if (inb && ob + 64 + lane < out_cap) out[ob + 64 + lane] = xb;
+        if (FULL && ob + kBlock <= out_cap) {  // uniform: unmasked stores
+            out[ob + lane] = xa;
+            out[ob + 64 + lane] = xb;
+        } else {
+            if (ina && ob + lane < out_cap) out[ob + lane] = xa;
+            if (inb && ob + 64 + lane < out_cap) out[ob + 64 + lane] = xb;
+        }
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -1349,6 +1354,21 @@ __device__ __forceinline__ void decode_block(const uint32_t *buf, uint32_t bw, u
     else
         decode_one_block<false>(buf, bw, val, cls, param, aux, v0, nk, hi, has_next, nxt, out, ob, out_cap,
                                 err, lane);
+}
+
+// A block's payload words (wc of them, at word o of the segment's payload
+// area, availw words long) into lane / 64+lane.  When 128 words from o lie
+// inside the area the loads go unmasked (the words past wc are never taken
+// as payload); near its end only the block's own words are read.
+__device__ __forceinline__ void load_payload(const uint32_t *pay, uint32_t o, uint32_t wc, uint64_t availw,
+                                             uint32_t lane, uint32_t &x, uint32_t &y) {
+    if ((uint64_t)o + kBlock <= availw) {
+        x = pay[o + lane];
+        y = pay[o + 64 + lane];
+    } else {
+        x = lane < wc ? pay[o + lane] : 0u;
+        y = lane + 64 < wc ? pay[o + 64 + lane] : 0u;
+    }
 }
 
 // Decode, one wave per unit (half a group: up to 8 blocks).  The wave reads
@@ -1447,9 +1467,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_u(DecArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
         } else {
-            const uint32_t wc = readlane(words, hb);
-            pa = lane < wc ? pay[ub + lane] : 0u;
-            pb = lane + 64 < wc ? pay[ub + lane + 64] : 0u;
+            load_payload(pay, ub, readlane(words, hb), availw, lane, pa, pb);
         }
         for (uint32_t kk = 0; kk < nblk; ++kk) {
             const uint32_t j = hb + kk, k = k0 + j;
@@ -1460,14 +1478,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_u(DecArgs a) {
                 buf = win + (readlane(off, j) - ub);
             } else {
                 uint32_t na = 0, nbw = 0;
-                if (kk + 1 < nblk) {
-                    const uint32_t wn = readlane(words, j + 1), on = readlane(off, j + 1);
-                    na = lane < wn ? pay[on + lane] : 0u;
-                    nbw = lane + 64 < wn ? pay[on + lane + 64] : 0u;
-                }
+                if (kk + 1 < nblk) load_payload(pay, readlane(off, j + 1), readlane(words, j + 1), availw, lane, na, nbw);
                 win[lane] = pa;
                 win[lane + 64] = pb;
-                if (lane < 4) win[128 + lane] = 0u;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 pa = na;
