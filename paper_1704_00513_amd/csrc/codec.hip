@@ -317,14 +317,13 @@ __device__ __forceinline__ void pack_block_scan(uint32_t *buf, uint32_t *pj, uin
             const bool xa = R.hasa && b < 32 && (R.da >> b) != 0u;
             const bool xb = R.hasb && b < 32 && (R.db >> b) != 0u;
             const uint64_t ma = ballot(xa), mb = ballot(xb);
-            const uint64_t lt = lanemask_lt();
             if (xa) {
-                const uint32_t e = popc64(ma & lt);
+                const uint32_t e = mbcnt64(ma);
                 put_bits(buf, lw * 32 + e * 8, 8, lane - 1);
                 put_bits(buf, (lw + qw) * 32 + e * h, h, R.da >> b);
             }
             if (xb) {
-                const uint32_t e = popc64(ma) + popc64(mb & lt);
+                const uint32_t e = popc64(ma) + mbcnt64(mb);
                 put_bits(buf, lw * 32 + e * 8, 8, 63 + lane);
                 put_bits(buf, (lw + qw) * 32 + e * h, h, R.db >> b);
             }
@@ -359,14 +358,13 @@ __device__ __forceinline__ void pack_block(uint32_t *buf, const BlockInfo &I, co
             const bool xa = R.hasa && b < 32 && (R.da >> b) != 0u;
             const bool xb = R.hasb && b < 32 && (R.db >> b) != 0u;
             const uint64_t ma = ballot(xa), mb = ballot(xb);
-            const uint64_t lt = lanemask_lt();
             if (xa) {
-                const uint32_t e = popc64(ma & lt);
+                const uint32_t e = mbcnt64(ma);
                 put_bits(buf, lw * 32 + e * 8, 8, ja - 1);
                 put_bits(buf, (lw + qw) * 32 + e * h, h, R.da >> b);
             }
             if (xb) {
-                const uint32_t e = popc64(ma) + popc64(mb & lt);
+                const uint32_t e = popc64(ma) + mbcnt64(mb);
                 put_bits(buf, lw * 32 + e * 8, 8, jb - 1);
                 put_bits(buf, (lw + qw) * 32 + e * h, h, R.db >> b);
             }
@@ -462,14 +460,14 @@ __device__ __forceinline__ void pack_pfor_full(uint32_t *buf, uint32_t da, uint3
     if (E) {
         const uint32_t lw = (m * b + 31) >> 5, qw = (E + 3) >> 2;
         const bool xa = da > mask, xb = db > mask;
-        const uint64_t ma = ballot(xa), mb = ballot(xb), lt = lanemask_lt();
+        const uint64_t ma = ballot(xa), mb = ballot(xb);
         if (xa) {
-            const uint32_t e = popc64(ma & lt);
+            const uint32_t e = mbcnt64(ma);
             or_field(buf, lw * 32 + e * 8, lane - 1);
             or_field(buf, (lw + qw) * 32 + e * h, da >> b);
         }
         if (xb) {
-            const uint32_t e = popc64(ma) + popc64(mb & lt);
+            const uint32_t e = popc64(ma) + mbcnt64(mb);
             or_field(buf, lw * 32 + e * 8, 63 + lane);
             or_field(buf, (lw + qw) * 32 + e * h, db >> b);
         }
@@ -1273,12 +1271,17 @@ __device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t b
         uint32_t cnt = 1;
         if (lane == 0) val[0] = v0;
         for (uint32_t c = 0; c < nch; ++c) {
+            // word 2c for lanes 0..31, 2c+1 for 32..63, read unconditionally:
+            // wi <= 2 nch - 1 <= bw, at most one word past the block, still
+            // inside the staging buffer; words past bw count as zero
             const uint32_t wi = lane < 32 ? 2 * c : 2 * c + 1;
-            const uint32_t word = wi < bw ? buf[wi] : 0u;
+            const uint32_t rw = buf[wi];
+            const uint32_t word = wi < bw ? rw : 0u;
             const bool set = (word >> (lane & 31)) & 1u;
             const uint64_t mk = ballot(set);
-            const uint32_t rank = popc64(mk & lanemask_lt());
-            if (set && cnt + rank < 128) val[cnt + rank] = v0 + 64 * c + lane + 1;
+            // a damaged block may set more than 127 bits: it is rejected below,
+            // and its writes stay inside val
+            if (set) val[min(cnt + mbcnt64(mk), 127u)] = v0 + 64 * c + lane + 1;
             cnt += popc64(mk);
         }
         const uint32_t tailw = aux >> 5, tailb = aux & 31;

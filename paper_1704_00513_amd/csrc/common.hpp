@@ -43,6 +43,10 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     uint32_t l = lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
+// Number of set bits of mk below this lane (v_mbcnt_lo / v_mbcnt_hi).
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mk) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+}
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
