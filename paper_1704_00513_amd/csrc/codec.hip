@@ -613,6 +613,261 @@ __device__ __forceinline__ uint32_t enc_block(uint32_t va, uint32_t vb, uint32_t
     return I.words;
 }
 
+// A DPP move whose result only some lanes select must still run with every
+// lane of the wave active: were the compiler to move it under the select's
+// exec mask, lanes would read disabled neighbours (and get `old`).  The
+// empty asm consumes the value where it is computed, which pins it.
+__device__ __forceinline__ uint32_t pin(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ void pin64(uint64_t &x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    x = ((uint64_t)hi << 32) | lo;
+}
+
+// ------------------------------------------------------------------ 16-lane rows
+
+// Lanes 16r .. 16r+15 of a wave form row r (ri = lane & 15), the unit of the
+// GFX9 DPP row operations: row_shr:n (0x110+n), row_mirror (0x140),
+// row_half_mirror (0x141), the quad permutations 0x4E / 0xB1, and
+// row_newbcast:n (0x150+n, lane n of the row to all of it).  The helpers
+// combine values inside every row at once; a row is either wholly active or
+// wholly inactive wherever they are used.
+__device__ __forceinline__ uint32_t row_max(uint32_t v) {
+    v = max(v, dpp<0x140>(v, v));
+    v = max(v, dpp<0x141>(v, v));
+    v = max(v, dpp<0x4E>(v, v));
+    v = max(v, dpp<0xB1>(v, v));
+    return v;
+}
+__device__ __forceinline__ uint32_t row_sum(uint32_t v) {
+    v += dpp<0x140>(v, v);
+    v += dpp<0x141>(v, v);
+    v += dpp<0x4E>(v, v);
+    v += dpp<0xB1>(v, v);
+    return v;
+}
+// Exclusive prefix sum inside the row (row shifts bring 0 in at its start).
+__device__ __forceinline__ uint32_t row_excl_scan(uint32_t v) {
+    uint32_t s = v;
+    s += dpp<0x111>(0u, s);
+    s += dpp<0x112>(0u, s);
+    s += dpp<0x114>(0u, s);
+    s += dpp<0x118>(0u, s);
+    return s - v;
+}
+
+// LDS words a wave needs to assemble a full unit's payloads: 8 blocks of at
+// most 128 words, one spill word, rounded to 16 bytes, then 2 x 64 words that
+// take the atomics of lanes with nothing to write (one word per lane: were
+// they aimed at the payload, up to 16 lanes would hit one address).
+constexpr uint32_t kUnitPay = kHalf * kBlock + 4;
+constexpr uint32_t kUnitStage = kUnitPay + 128;
+
+// A full unit (8 blocks of 128 IDs, src 4-byte aligned; al16: 16-byte
+// aligned) encoded by the wave in two passes of four blocks, one block per
+// 16-lane row: lane i of row r holds IDs 8i .. 8i+7 of block 4p + r in pass
+// p.  The per-block analysis is then a few row reductions shared by four
+// blocks and the class choice is ordinary vector code (the same choice as
+// enc_full: exhaustive, or the plain minimal width).  The payloads are
+// assembled back to back in the wave's LDS area st (kUnitStage words) and
+// copied to pay (16-byte aligned); the 16 directory words go to dir.
+// Returns the unit's payload words.
+__device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, uint32_t lo, uint32_t hi,
+                                               bool exhaustive, uint32_t *pay, uint32_t *dir, uint32_t *st,
+                                               uint32_t lane, uint32_t *err) {
+    constexpr uint32_t m = kBlock - 1;
+    const uint32_t ri = lane & 15, r = lane >> 4;
+    const uint64_t all = ballot(true);
+    uint32_t *const dmy0 = st + kUnitPay + lane, *const dmy1 = dmy0 + 64;
+    // the previous unit's copy-out has read st before it is cleared
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) ((uint4 *)st)[lane + 64 * q] = make_uint4(0u, 0u, 0u, 0u);
+    if (lane == 0) ((uint4 *)st)[256] = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t total = 0;
+#pragma unroll 1
+    for (uint32_t p = 0; p < 2; ++p) {
+        uint32_t v[8];
+        const uint32_t *ps = src + 512 * p + 8 * lane;
+        if (al16) {
+            const uint4 x = ((const uint4 *)ps)[0], y = ((const uint4 *)ps)[1];
+            v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+            v[4] = y.x, v[5] = y.y, v[6] = y.z, v[7] = y.w;
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) v[k] = ps[k];
+        }
+        // deltas: the row's first lane receives its own first ID (delta 0:
+        // the first ID of a block is stored in the directory)
+        const uint32_t pv = dpp<0x111>(v[0], v[7]);
+#define BFSC_D(k) ((k) ? v[k] - v[(k) ? (k) - 1 : 0] : v[0] - pv)
+        // strictly increasing inside the block, first >= lo, last < hi
+        uint64_t okm = ballot(ri == 0 || v[0] > pv);
+        uint32_t dm = BFSC_D(0);
+#pragma unroll
+        for (uint32_t k = 1; k < 8; ++k) {
+            okm &= ballot(v[k] > v[k - 1]);
+            dm = max(dm, BFSC_D(k));
+        }
+        const uint32_t v0 = dpp<0x150>(v[0], v[0]), vl = dpp<0x15F>(v[7], v[7]);
+        okm &= ballot((v0 >= lo) & (vl < hi));
+        if (okm != all) {
+            if (lane == 0) raise_err(err, kErrInval);
+        }
+        const uint32_t wmin = bitlen32(row_max(dm));
+        const uint32_t span = vl - v0;
+        // the deltas are not kept from here on (recomputed where used)
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) v[k] = pin(v[k]);
+
+        // choice, uniform inside each row
+        const uint32_t bpw = (m * wmin + 31) >> 5;
+        uint32_t cls = 1 + wmin, param = wmin, aux = 0, words = bpw;
+        if (exhaustive) {
+            const uint32_t bmw = (span + 31) >> 5;
+            if ((span <= kBitmapMaxSpan) & (bmw < words)) {
+                cls = kClsBitmap;
+                param = 0;
+                aux = span;
+                words = bmw;
+            }
+            // PFOR: fewest words with 10 E <= m, ties to the larger b; the
+            // same bound as enc_full prunes widths that cannot win
+            uint32_t best = bpw, pfb = 0, pfe = 0;
+            const uint32_t bcap = words >= 3 ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
+            uint32_t b = bcap;
+            bool live = b > 0;
+            while (ballot(live) != 0ull) {
+                if (live) {
+                    --b;
+                    const uint32_t thr = (1u << b) - 1u;
+                    uint32_t c = 0;
+#pragma unroll
+                    for (uint32_t k = 0; k < 8; ++k) c += BFSC_D(k) > thr;
+                    const uint32_t e = row_sum(c);
+                    if (e > m / 10) {
+                        live = false;
+                    } else {
+                        const uint32_t h = wmin - b;
+                        const uint32_t wd = ((m * b + 31) >> 5) + ((e + 3) >> 2) + ((e * h + 31) >> 5);
+                        if (wd < best) {
+                            best = wd;
+                            pfb = b;
+                            pfe = e;
+                        }
+                        live = b > 0;
+                    }
+                }
+            }
+            if (best < words) {
+                cls = kClsPfor;
+                param = pfb;
+                aux = pfe | (pfe ? (wmin - pfb) << 8 : 0u);
+                words = best;
+            }
+        }
+
+        // payload offsets: the pass's blocks back to back after the earlier
+        // ones
+        const uint32_t own = ri == 15 ? words : 0u;
+        const uint32_t incl = wave_incl_scan(own);
+        uint32_t *sg = st + total + (incl - own);
+        total += readlane(incl, 63);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        // main fields.  A bitmap sets bit o-1 for offset o = v - v0 >= 1; a
+        // bit-pack, or the low part of a PFOR, puts delta j at bit (j-1) w.
+        // A lane's fields are gathered into a 64-bit window that starts at
+        // the word of its first field and ORed into LDS with two atomics:
+        // this holds the whole run of a bit-pack of width <= 4 (8 w + 31 <
+        // 64 bits) and, mostly, of a bitmap; bitmap bits beyond the window
+        // (sparse blocks, or unsorted input, which is flagged and kept inside
+        // the block's words) and wider bit-packs are ORed field by field.
+        const bool isbm = cls == kClsBitmap;
+        const uint32_t pw = isbm ? 0u : param;
+        const uint32_t mask = pw >= 32 ? 0xFFFFFFFFu : (1u << pw) - 1u;
+        const bool narrow = isbm || pw <= 4;
+        const uint32_t qmax = 32 * max(words, 1u) - 1, vb1 = v0 + 1;
+        const uint32_t p0 = ri ? (8 * ri - 1) * pw : 0u;  // bit-pack: bit of the lane's first field
+        const uint32_t b0 = ri == 0 ? 0u : isbm ? min(v[0] - vb1, qmax) >> 5 : p0 >> 5;
+        // (selects written as bit operations: the compiler keeps them
+        // branch-free)
+        const uint32_t bmsel = isbm ? 0xFFFFFFFFu : 0u, one = bmsel & 1u, base32 = 32 * b0;
+        uint32_t relbp = p0 - base32 - (ri ? 0u : pw);  // bit-pack: window bit of field k
+        uint64_t win = 0;
+        bool ofl = false;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            const bool has = k != 0 || ri != 0;
+            const uint32_t relbm = min(v[k] - vb1, qmax) - base32;
+            const uint32_t rel = relbp ^ ((relbp ^ relbm) & bmsel);
+            const uint32_t val = (BFSC_D(k) & mask) | one;
+            const bool in = has & narrow & (rel < 64);
+            ofl |= has & isbm & (rel >= 64);
+            win |= (uint64_t)(in ? val : 0u) << (rel & 63);
+            pin64(win);  // one field at a time: keeps the live registers few
+            relbp += pw;
+        }
+        atomicOr(narrow ? &sg[b0] : dmy0, (uint32_t)win);
+        atomicOr(narrow ? &sg[b0 + 1] : dmy1, (uint32_t)(win >> 32));
+        if (ballot(ofl) != 0ull) {
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                const bool has = k != 0 || ri != 0;
+                const uint32_t q = min(v[k] - vb1, qmax);
+                const bool o = has & isbm & (q - 32 * b0 >= 64);
+                atomicOr(o ? &sg[q >> 5] : dmy0, 1u << (q & 31));
+            }
+        }
+        if (ballot(!narrow) != 0ull) {
+            uint32_t pos = p0;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                const bool go = !narrow & (k != 0 || ri != 0);
+                const uint64_t x = (uint64_t)(BFSC_D(k) & mask) << (pos & 31);
+                atomicOr(go ? sg + (pos >> 5) : dmy0, (uint32_t)x);
+                atomicOr(go ? sg + (pos >> 5) + 1 : dmy1, (uint32_t)(x >> 32));
+                pos += k != 0 || ri != 0 ? pw : 0u;
+            }
+        }
+        // PFOR exceptions: positions (bytes, j - 1) and high parts, in order
+        const bool ispf = cls == kClsPfor;
+        if (ballot(ispf) != 0ull) {
+            const uint32_t E = aux & 0xFFu, h = aux >> 8;
+            const uint32_t lw = (m * pw + 31) >> 5, qw = (E + 3) >> 2;
+            uint32_t xc = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) xc += ispf & (BFSC_D(k) > mask);
+            uint32_t e = row_excl_scan(xc);
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                const uint32_t dk = BFSC_D(k);
+                const bool x = ispf & (dk > mask);
+                const uint32_t j = 8 * ri + k;
+                // position byte (never crosses a word), then the high part
+                const uint32_t bp = lw * 32 + e * 8, hp = (lw + qw) * 32 + e * h;
+                atomicOr(x ? sg + (bp >> 5) : dmy0, (j - 1) << (bp & 31));
+                const uint64_t hx = (uint64_t)(dk >> (pw & 31)) << (hp & 31);
+                atomicOr(x ? sg + (hp >> 5) : dmy0, (uint32_t)hx);
+                atomicOr(x ? sg + (hp >> 5) + 1 : dmy1, (uint32_t)(hx >> 32));
+                e += x;
+            }
+        }
+#undef BFSC_D
+        // directory entries: lanes 0 / 1 of row r write block 4p + r's words
+        if (ri < 2) dir[8 * p + 2 * r + ri] = ri ? cls | (param << 8) | (aux << 16) : v0 - lo;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t q = 4 * lane; q < total; q += 256) *(uint4 *)(pay + q) = *(const uint4 *)(st + q);
+    return total;
+}
+
 // Last r < n with base[r] <= t (base non-decreasing, base[0] <= t), found by
 // the whole wave: 64 probes per round, so 2 dependent loads for up to 4096
 // entries and 3 for up to 262144.
@@ -688,13 +943,19 @@ template <int WAVES, bool SCANPACK, bool STAGE>
 __global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
     constexpr uint32_t kIds = kHalf * kBlock;
     constexpr uint32_t kPerLane = kIds / 64;
-    __shared__ uint32_t s_ids[STAGE ? WAVES : 1][STAGE ? kIds : 1];
+    // full units take the 16-lane-row encoder in the per-block packing
+    // variants; it assembles payloads in the same per-wave LDS area that the
+    // staged variant loads IDs into
+    constexpr bool kGrp = !SCANPACK;
+    __shared__ __align__(16) uint32_t s_ids[STAGE || kGrp ? WAVES : 1][STAGE || kGrp ? kUnitStage : 4];
     __shared__ uint32_t s_buf[WAVES][132];
     __shared__ uint32_t s_pj[SCANPACK ? WAVES : 1][128];
     __shared__ uint32_t s_dj[SCANPACK ? WAVES : 1][128];
-    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // wave index made scalar: the unit loop and the segment fields stay in
+    // scalar registers
+    const uint32_t lane = threadIdx.x & 63, w = readfirst(threadIdx.x >> 6);
     const uint32_t units = 2 * readfirst(a.p.tile_base[a.nseg]);
-    uint32_t *sid = s_ids[STAGE ? w : 0];
+    uint32_t *sid = s_ids[STAGE || kGrp ? w : 0];
     UnitRange ur = unit_range(units, WAVES, w, a.strided);
     SegCursor c;
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
@@ -717,6 +978,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
             const uint32_t lo = c.lo, hi = c.hi;
             const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
             const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+            uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+            if (kGrp && !a.classes && cnt == kIds) {
+                run = enc_unit_r(src, ((uintptr_t)src & 15) == 0, lo, hi, a.mode != BFSC_SEL_PLAIN_BP,
+                                 slot + kSlotDirWords + h * kSlotHalfWords, slot + 2 * h * kHalf, sid, lane, a.err);
+                if (lane == 0) a.p.unit_words[u] = run;
+                continue;
+            }
             const uint32_t cl = a.classes && lane < nblk ? (uint32_t)a.classes[bb + k0 + lane] : 0u;
             uint32_t va = 0, vb = 0;
             if constexpr (STAGE) {
@@ -730,7 +998,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
             } else {
                 fetch_block(src, min(kBlock, cnt), lane, va, vb);
             }
-            uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
             uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
             uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
             for (uint32_t kk = 0; kk < nblk; ++kk) {
