@@ -940,7 +940,7 @@ struct SegCursor {
 // way it analyses, chooses and packs the blocks in order into the unit's half
 // of the tile's slot.
 template <int WAVES, bool SCANPACK, bool STAGE>
-__global__ __launch_bounds__(WAVES * 64) void k_enc_pack_u(EncArgs a) {
+__global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
     constexpr uint32_t kIds = kHalf * kBlock;
     constexpr uint32_t kPerLane = kIds / 64;
     // full units take the 16-lane-row encoder in the per-block packing
