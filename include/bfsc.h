@@ -132,7 +132,10 @@ typedef struct {
     uint32_t dec_mode;       /* bit 0: payload loaded block by block instead of a whole
                                 unit staged in LDS at once;
                                 bit 1: units taken every NW-th instead of in one contiguous
-                                run per wave */
+                                run per wave;
+                                bit 2: full units decoded one block per 16-lane row, the
+                                next unit's payload loaded straight into LDS while the
+                                current one decodes (bit 0 is then ignored) */
 } bfsc_tune;
 
 /* Creates a context on HIP device `device`: queries the device, allocates

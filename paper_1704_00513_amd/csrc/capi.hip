@@ -292,7 +292,7 @@ int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t) {
     if (!ctx || !t) return BFSC_E_INVAL;
     if (!waves_ok(t->enc_waves) || !waves_ok(t->dec_waves) || t->enc_wg_per_cu < 1 ||
         t->enc_wg_per_cu > 64 || t->dec_wg_per_cu < 1 || t->dec_wg_per_cu > 64 || t->enc_pack > 7 ||
-        t->dec_mode > 3)
+        t->dec_mode > 7)
         return BFSC_E_INVAL;
     ctx->tune = *t;
     return BFSC_OK;

@@ -1641,6 +1641,172 @@ __device__ __forceinline__ void load_payload(const uint32_t *pay, uint32_t o, ui
     }
 }
 
+// A full unit (8 blocks of 128 IDs) decoded in two passes of four blocks,
+// one block per 16-lane row: lane i of row r produces IDs 8i .. 8i+7 of
+// group block jr = hb + 4p + r in pass p.  The group's checked directory is
+// held one block per lane (e1: class | param << 8 | aux << 16; first; off:
+// payload word offset; lane gblk holds the next block's first value).  win:
+// the unit's staged payload words, from payload word ub; val: 512 words of
+// the wave's LDS.  Bit-pack fields (and PFOR low parts) are taken from a
+// 64-bit window per lane for widths <= 4, else field by field; PFOR
+// exceptions are patched through val; a bitmap is expanded one word per
+// lane per step (popcount, row scan for the ranks, then the lane writes its
+// set bits' IDs into val).  The prefix sums run inside the lane and then as
+// a row scan.  A block that fails a check is reported and not written.
+__device__ __forceinline__ void dec_unit_r(const uint32_t *win, uint32_t *val, uint32_t ub, uint32_t hb,
+                                           uint32_t k0, uint32_t nb, uint32_t e1, uint32_t first, uint32_t off,
+                                           uint32_t lo, uint32_t hi, uint32_t *out, uint64_t oo,
+                                           uint64_t out_cap, uint32_t *err, uint32_t lane) {
+    constexpr uint32_t m = kBlock - 1;
+    const uint32_t ri = lane & 15, r = lane >> 4;
+    uint32_t *const vr = val + 128 * r;
+    // whole unit inside the output and 16-byte aligned: two vector stores
+    // per lane
+    const bool vec = (oo & 3) == 0 && ((uintptr_t)out & 15) == 0 &&
+                     oo + (uint64_t)(k0 + hb + kHalf) * kBlock <= out_cap;
+#pragma unroll 1
+    for (uint32_t p = 0; p < 2; ++p) {
+        const uint32_t jr = hb + 4 * p + r;
+        const uint32_t me = shfl(e1, (int)jr), mo = shfl(off, (int)jr);
+        const uint32_t mf = shfl(first, (int)jr), mn = shfl(first, (int)jr + 1);
+        const uint32_t cls = me & 0xFFu, param = (me >> 8) & 0xFFu, aux = me >> 16;
+        const uint32_t *buf = win + (mo - ub);
+        const uint32_t v0 = lo + mf, nxt = lo + mn;
+        const bool hasnx = k0 + jr + 1 < nb;
+        const bool isbm = cls == kClsBitmap, ispf = cls == kClsPfor;
+        const uint32_t b = isbm ? 0u : cls <= 33 ? cls - 1 : param;
+        const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : (1u << b) - 1u;
+        const bool has0 = ri != 0;  // the lane's first slot carries a delta
+        bool bad = false;
+        uint32_t x[8];
+        // deltas of a bit-pack / PFOR low part: delta j is field j-1 at bit
+        // (j-1) b; delta 0 of the block is 0 (its first ID is v0)
+        const uint32_t p0 = has0 ? (8 * ri - 1) * b : 0u;
+        {
+            const uint32_t wi = p0 >> 5;
+            const uint64_t wv = ((uint64_t)buf[wi + 1] << 32) | buf[wi];
+            uint32_t rel = (p0 & 31) - (has0 ? 0u : b);
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                x[k] = (k != 0 || has0) ? (uint32_t)(wv >> (rel & 63)) & mask : 0u;
+                rel += b;
+            }
+        }
+        if (ballot(b > 4) != 0ull) {
+            uint32_t pos = p0;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                if (k != 0 || has0) {
+                    const uint32_t wi = pos >> 5;
+                    const uint32_t f = __builtin_amdgcn_alignbit(buf[wi + 1], buf[wi], pos & 31) & mask;
+                    x[k] = b > 4 ? f : x[k];
+                    pos += b;
+                }
+            }
+        }
+        if (ballot(ispf) != 0ull) {
+            // exception e < E (one lane each): position byte p_e, high part;
+            // delta p_e + 1 gets hv << b
+            const uint32_t E = ispf ? aux & 0xFFu : 0u, h = aux >> 8;
+            const uint32_t lw = cdiv32(m * b, 32), qw = cdiv32(E, 4);
+            *(uint4 *)&vr[8 * ri] = make_uint4(x[0], x[1], x[2], x[3]);
+            *(uint4 *)&vr[8 * ri + 4] = make_uint4(x[4], x[5], x[6], x[7]);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const bool ex = ri < E;
+            const uint32_t pe = ex ? (buf[lw + (ri >> 2)] >> (8 * (ri & 3))) & 0xFFu : 0u;
+            const uint32_t pp = pin(dpp<0x111>(0u, pe));
+            bad |= ex && (pe >= m || (ri > 0 && pe <= pp));
+            if (ex && pe < m) {
+                const uint32_t hv = h ? get_field(buf + lw + qw, ri * h, h) : 0u;
+                atomicOr(&vr[pe + 1], b >= 32 ? 0u : hv << b);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const uint4 y0 = *(const uint4 *)&vr[8 * ri], y1 = *(const uint4 *)&vr[8 * ri + 4];
+            x[0] = y0.x, x[1] = y0.y, x[2] = y0.z, x[3] = y0.w;
+            x[4] = y1.x, x[5] = y1.y, x[6] = y1.z, x[7] = y1.w;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // prefix sums: inside the lane, then across the row
+        {
+            uint32_t s = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) {
+                bad |= !isbm & (k != 0 || has0) & (x[k] == 0u);
+                s += x[k];
+                x[k] = s;
+            }
+            const uint32_t base = v0 + row_excl_scan(s);
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) x[k] += base;
+        }
+        if (ballot(isbm) != 0ull) {
+            // bitmap: bit q set means ID v0 + q + 1; exactly m bits, none at or
+            // past bit aux (the span), read only inside the block's words
+            const uint32_t bw = isbm ? cdiv32(aux, 32) : 0u;
+            if (ri == 0) vr[0] = v0;
+            uint32_t cnt = 1;  // IDs placed so far in the row's block
+            const uint32_t nsteps = readfirst(max(wave_max(bw), 1u) + 15) >> 4;
+            for (uint32_t st = 0; st < nsteps; ++st) {
+                const uint32_t wi = 16 * st + ri;
+                uint32_t word = wi < bw ? buf[wi] : 0u;
+                if (wi + 1 == bw && (aux & 31)) {
+                    bad |= (word >> (aux & 31)) != 0u;
+                    word &= (1u << (aux & 31)) - 1u;
+                }
+                const uint32_t c = __builtin_popcount(word);
+                uint32_t rank = cnt + row_excl_scan(c);
+                cnt += row_sum(c);
+                const uint32_t idb = v0 + 32 * wi + 1;
+                while (word) {
+                    const uint32_t bit = __builtin_ctz(word);
+                    vr[min(rank, 127u)] = idb + bit;
+                    ++rank;
+                    word &= word - 1u;
+                }
+            }
+            bad |= isbm & (cnt != kBlock);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const uint4 y0 = *(const uint4 *)&vr[8 * ri], y1 = *(const uint4 *)&vr[8 * ri + 4];
+            if (isbm) {
+                x[0] = y0.x, x[1] = y0.y, x[2] = y0.z, x[3] = y0.w;
+                x[4] = y1.x, x[5] = y1.y, x[6] = y1.z, x[7] = y1.w;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // strictly increasing (this also catches a wrapped sum), the last ID
+        // below hi and below the next block's first
+        const uint32_t px = pin(dpp<0x111>(0u, x[7]));
+        bad |= has0 & (x[0] <= px);
+#pragma unroll
+        for (uint32_t k = 1; k < 8; ++k) bad |= x[k] <= x[k - 1];
+        const uint32_t last = dpp<0x15F>(x[7], x[7]);
+        const uint64_t last64 = (uint64_t)v0 + (last - v0);
+        bad |= (last64 >= hi) | (hasnx & (last64 >= nxt));
+        // a row is bad when any of its lanes is
+        const uint64_t bm = ballot(bad);
+        const bool rowbad = ((bm >> (16 * r)) & 0xFFFFull) != 0ull;
+        if (bm != 0ull) {
+            if (lane == 0) raise_err(err, kErrCorrupt);
+        }
+        const uint64_t ob = oo + (uint64_t)(k0 + jr) * kBlock + 8 * ri;
+        if (!rowbad) {
+            if (vec) {
+                *(uint4 *)(out + ob) = make_uint4(x[0], x[1], x[2], x[3]);
+                *(uint4 *)(out + ob + 4) = make_uint4(x[4], x[5], x[6], x[7]);
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < 8; ++k)
+                    if (ob + k < out_cap) out[ob + k] = x[k];
+            }
+        }
+    }
+}
+
 // Decode, one wave per unit (half a group: up to 8 blocks).  The wave reads
 // and checks the group's directory entries (one lane per block) and table
 // words, then decodes the unit's blocks in order.  STAGE: the unit's payload
@@ -1760,6 +1926,196 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_u(DecArgs a) {
                          lo + readlane(first, j), min(kBlock, n - k * kBlock), hi, has_next, nxt, a.out,
                          oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
         }
+    }
+}
+
+// The directory side of a decode unit, as read and checked by the wave.
+struct DecUnit {
+    uint32_t kind;  // 0: nothing to decode (empty half, or a damaged group, reported)
+                    // 1: full unit (8 blocks of 128 IDs); 2: any other unit
+    uint32_t hb, k0, nb, n, gblk, nblk, lo, hi, ub, ue;
+    uint64_t oo, availw;
+    const uint32_t *pay;
+    // lane j < gblk: block j of the group (lane gblk: first of the next block)
+    uint32_t e1, first, off, words;
+};
+
+// Reads and checks unit u's group directory entries (one lane per block)
+// and group-table words, as k_decode_u does.
+__device__ __forceinline__ DecUnit dec_dir(const DecArgs &a, SegCursor &c, uint32_t u, uint32_t lane) {
+    DecUnit U;
+    U.kind = 0;
+    const uint32_t t = u >> 1, h = u & 1;
+    if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
+        c.n = readfirst(a.seg_n[c.r]);
+        c.S = readfirst64(a.seg_byte_off[c.r]);
+        c.bytes = readfirst64(a.seg_byte_off[c.r + 1]) - c.S;
+        c.base = readfirst64(a.out_off[c.r]);
+        const uint32_t *sg = (const uint32_t *)(a.in + c.S);
+        c.lo = readfirst(sg[1]);
+        c.hi = readfirst(sg[2]);
+    }
+    const uint32_t g = t - c.t_first;
+    const uint32_t n = c.n;
+    const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
+    const uint32_t k0 = g * kGroup;
+    const uint32_t gblk = min(kGroup, nb - k0);
+    const uint32_t hb = h * kHalf;
+    if (hb >= gblk) return U;
+    const uint32_t *seg = (const uint32_t *)(a.in + c.S);
+    const uint32_t lo = c.lo, hi = c.hi;
+    const uint32_t metaw = 4 + 2 * nb + ng;
+    const uint64_t availw = c.bytes / 4 - metaw;
+    bool bad = false;
+    uint32_t words = 0, e1 = 0, first = 0;
+    if (lane <= gblk && k0 + lane < nb) {
+        first = seg[4 + 2 * (k0 + lane)];
+        if (lane < gblk) {
+            e1 = seg[4 + 2 * (k0 + lane) + 1];
+            const uint32_t cls = e1 & 0xFFu, param = (e1 >> 8) & 0xFFu, aux = e1 >> 16;
+            const uint32_t nk = min(kBlock, n - (k0 + lane) * kBlock), m = nk - 1;
+            if (cls == kClsBitmap) {
+                bad = param != 0 || aux > kBitmapMaxSpan;
+            } else if (cls <= 33) {
+                bad = param != cls - 1 || aux != 0;
+            } else if (cls == kClsPfor) {
+                const uint32_t E = aux & 0xFFu, hh = aux >> 8;
+                bad = param > 32 || param + hh > 32 || 10 * E > m;
+            } else {
+                bad = true;
+            }
+            words = bad ? 0u : block_words(cls, param, aux, m);
+            bad |= words > kBlock;
+            bad |= (uint64_t)lo + first >= (uint64_t)hi;
+        }
+    }
+    const uint32_t incl = wave_incl_scan(lane < gblk ? words : 0u);
+    const uint32_t A = readlane(incl, 63);
+    const uint32_t gt = readfirst(seg[4 + 2 * nb + g]);
+    bool ok = ballot(bad) == 0ull;
+    ok = ok && (uint64_t)gt + A <= availw;
+    if (g + 1 < ng) ok = ok && seg[4 + 2 * nb + g + 1] == gt + A;
+    else ok = ok && (uint64_t)gt + A == availw;
+    if (!ok) {
+        if (lane == 0) raise_err(a.err, kErrCorrupt);
+        return U;
+    }
+    const uint32_t nblk = min(kHalf, gblk - hb);
+    U.off = gt + incl - words;
+    U.hb = hb, U.k0 = k0, U.nb = nb, U.n = n, U.gblk = gblk, U.nblk = nblk, U.lo = lo, U.hi = hi;
+    U.ub = readlane(U.off, hb);
+    U.ue = hb + nblk < gblk ? readlane(U.off, hb + nblk) : gt + A;
+    U.oo = c.base, U.availw = availw, U.pay = seg + metaw;
+    U.e1 = e1, U.first = first, U.words = words;
+    U.kind = nblk == kHalf && (uint64_t)(k0 + hb + kHalf) * kBlock <= n ? 1u : 2u;
+    return U;
+}
+
+// Decode with one block per 16-lane row for full units (dec_unit_r),
+// software pipelined: while one full unit is decoded from one half of the
+// wave's LDS buffer, the payload of the next one is already on its way into
+// the other half by direct global-to-LDS loads (two 16-byte loads per lane
+// cover 512 words, from the 16-byte boundary at or below its first word, so
+// no load crosses a page that the payload does not touch).  Full units whose
+// payload does not fit a half are staged and decoded synchronously, the
+// others block by block as in k_decode_u.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 6) void k_decode_r(DecArgs a) {
+    constexpr uint32_t kHB = 512;  // words per buffer half
+    constexpr uint32_t kWin = kHalf * kBlock;
+    constexpr uint32_t kPerLane = kWin / 64;
+    __shared__ __align__(16) uint32_t s_buf[WAVES][2 * kHB + 4];
+    __shared__ __align__(16) uint32_t s_val[WAVES][4 * 128];
+    const uint32_t lane = threadIdx.x & 63, w = readfirst(threadIdx.x >> 6);
+    const uint32_t units = 2 * readfirst(a.tile_base[a.nseg]);
+    uint32_t *const buf = s_buf[w];
+    uint32_t *const val = s_val[w];
+    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    SegCursor c;
+    bool pv = false;  // a full unit is pending: its payload requested into half ps
+    uint32_t ps = 0, pdelta = 0;
+    DecUnit P;
+    P.kind = 0;
+    for (uint32_t u = ur.begin;; u += ur.step) {
+        const bool more = u < ur.end;
+        DecUnit U;
+        U.kind = 0;
+        if (more) U = dec_dir(a, c, u, lane);
+        bool upipe = false;
+        uint32_t us = 0, udelta = 0;
+        if (U.kind == 1) {
+            const uint32_t *src = U.pay + U.ub;
+            udelta = (uint32_t)(((uintptr_t)src & 15) >> 2);
+            const uint32_t need = udelta + (U.ue - U.ub);
+            // (a damaged directory can describe a unit with no payload words:
+            // then nothing is loaded ahead, so no load starts past the data)
+            if (U.ue > U.ub && need <= kHB) {
+                upipe = true;
+                us = pv ? ps ^ 1u : 0u;
+                const uint32_t *base = src - udelta;
+                const uint32_t last = need ? (need - 1) >> 2 : 0u;  // last 16-byte chunk holding payload
+                uint32_t *dst = buf + us * kHB;
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (uint32_t i = 0; i < 2; ++i)
+                    __builtin_amdgcn_global_load_lds((const void *)(base + 4 * min(lane + 64 * i, last)),
+                                                     (__attribute__((address_space(3))) void *)(dst + 256 * i),
+                                                     16, 0, 0);
+            }
+        }
+        if (pv) {
+            // the pending unit's two loads were issued before this unit's two
+            if (upipe) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+            else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            dec_unit_r(buf + ps * kHB + pdelta, val, P.ub, P.hb, P.k0, P.nb, P.e1, P.first, P.off, P.lo, P.hi,
+                       a.out, P.oo, a.out_cap, a.err, lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            pv = false;
+        }
+        if (U.kind == 1 && !upipe) {
+            const uint32_t Au = U.ue - U.ub;
+            uint32_t v[kPerLane];
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < Au ? U.pay[U.ub + lane + 64 * i] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) buf[lane + 64 * i] = v[i];
+            if (lane < 4) buf[kWin + lane] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            dec_unit_r(buf, val, U.ub, U.hb, U.k0, U.nb, U.e1, U.first, U.off, U.lo, U.hi, a.out, U.oo,
+                       a.out_cap, a.err, lane);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else if (U.kind == 2) {
+            uint32_t pa = 0, pb = 0;
+            load_payload(U.pay, U.ub, readlane(U.words, U.hb), U.availw, lane, pa, pb);
+            for (uint32_t kk = 0; kk < U.nblk; ++kk) {
+                const uint32_t j = U.hb + kk, k = U.k0 + j;
+                const bool has_next = k + 1 < U.nb;
+                const uint32_t nxt = has_next ? U.lo + readlane(U.first, j + 1) : 0u;
+                uint32_t na = 0, nbw = 0;
+                if (kk + 1 < U.nblk)
+                    load_payload(U.pay, readlane(U.off, j + 1), readlane(U.words, j + 1), U.availw, lane, na, nbw);
+                buf[lane] = pa;
+                buf[lane + 64] = pb;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                pa = na;
+                pb = nbw;
+                const uint32_t e1 = readlane(U.e1, j);
+                decode_block(buf, readlane(U.words, j), val, e1 & 0xFFu, (e1 >> 8) & 0xFFu, e1 >> 16,
+                             U.lo + readlane(U.first, j), min(kBlock, U.n - k * kBlock), U.hi, has_next, nxt,
+                             a.out, U.oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
+            }
+        }
+        if (upipe) {
+            pv = true;
+            ps = us;
+            pdelta = udelta;
+            P = U;
+        }
+        if (!more) break;
     }
 }
 
@@ -1943,7 +2299,9 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \
                        dim3(W * 64), 0, s, a)
 #define BFSC_DEC_CASE(W)                                                                   \
-    if (ctx->tune.dec_mode & 1u)                                                           \
+    if (ctx->tune.dec_mode & 4u)                                                           \
+        BFSC_DEC_LAUNCH((k_decode_r<W>), W);                                               \
+    else if (ctx->tune.dec_mode & 1u)                                                      \
         BFSC_DEC_LAUNCH((k_decode_u<W, false>), W);                                        \
     else                                                                                   \
         BFSC_DEC_LAUNCH((k_decode_u<W, true>), W);

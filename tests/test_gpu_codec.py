@@ -85,7 +85,7 @@ def test_encode_is_byte_exact(ctx, mode, waves, pack):
         ctx.set_tune(**before)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 6])
 @pytest.mark.parametrize("waves", [2, 4, 8, 16])
 def test_decode_shapes(ctx, waves, mode):
     before = ctx.get_tune()
@@ -162,17 +162,22 @@ def test_invalid_input_is_reported(ctx):
     assert st == 0
 
 
-def test_capacity_is_reported(ctx):
+@pytest.mark.parametrize("dec_mode", [3, 6])
+def test_capacity_is_reported(ctx, dec_mode):
     name, b = batches()[3]
-    log("capacity case=%s" % name)
+    log("capacity case=%s dec_mode=%d" % (name, dec_mode))
     st, _, _ = gpu_encode(ctx, b, out_cap=256)
     assert st == 2
     stream, sbo = oracle.encode(b)
-    st, _, _ = gpu_decode(ctx, stream, sbo, max_ids=b.n_ids, out_cap=b.n_ids // 2)
+    ctx.set_tune(dec_mode=dec_mode)
+    try:
+        st, _, _ = gpu_decode(ctx, stream, sbo, max_ids=b.n_ids, out_cap=b.n_ids // 2)
+    finally:
+        ctx.set_tune(dec_mode=3)
     assert st == 2
 
 
-@pytest.mark.parametrize("dec_mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("dec_mode", [0, 1, 2, 3, 4, 6])
 def test_damaged_streams_agree_with_oracle(ctx, dec_mode):
     ctx.set_tune(dec_mode=dec_mode)
     rng = np.random.default_rng(9)
