@@ -313,7 +313,7 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
                                        {8, 4, 6}, {4, 8, 0}};
     // {waves per workgroup, workgroups per CU, decoder variant}
     static const uint32_t kDec[][3] = {{4, 8, 3}, {4, 8, 2}, {4, 8, 1}, {2, 16, 3}, {8, 4, 3},
-                                       {4, 8, 0}};
+                                       {4, 8, 0}, {4, 8, 6}};
     bfsc_tune best = keep;
     float best_e = 1e30f, best_d = 1e30f;
     for (const auto &c : kEnc) {
