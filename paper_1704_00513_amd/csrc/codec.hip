@@ -968,6 +968,8 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
             c.hi = readfirst(a.seg_hi[c.r]);
             c.base = readfirst64(a.seg_off[c.r]);
         }
+        // the tile's segment, for the place pass
+        if (h == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
         const uint32_t g = t - c.t_first;
         const uint32_t bb = c.bb, nb = c.nb;
         const uint32_t k0 = g * kGroup + h * kHalf;
@@ -1065,6 +1067,8 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             c.base = readfirst64(a.seg_off[c.r]);
             level = a.seg_level ? (int32_t)readfirst((uint32_t)a.seg_level[c.r]) : 0;
         }
+        // the tile's segment, for the place pass
+        if (h == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
         const uint32_t g = t - c.t_first;
         const uint32_t nb = c.nb;
         const uint32_t k0 = g * kGroup + h * kHalf;
@@ -1196,8 +1200,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t t = blockIdx.x * WAVES + w;
     if (t >= total) return;
     const uint64_t capw = a.out_cap >> 2;
-    const uint32_t r = wave_find(a.p.tile_base, a.nseg, t, lane);
-    const uint32_t t_first = readfirst(a.p.tile_base[r]);
+    // segment and its first tile as recorded by the pack pass (no search)
+    const uint2 ts = a.p.tile_seg[t];
+    const uint32_t r = readfirst(ts.x);
+    const uint32_t t_first = readfirst(ts.y);
     const uint32_t bb = readfirst(a.p.blk_base[r]);
     const uint32_t nb = readfirst(a.p.blk_base[r + 1]) - bb;
     const uint32_t gb = readfirst(a.p.grp_base[r]);
@@ -1241,8 +1247,27 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
     if (lane < 2 * nblk) a.out[dwb + lane] = slot[lane];
     if (lane == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)rel;
-    for (uint32_t q = lane; q < A0; q += 64) a.out[pwb + q] = slot[kSlotDirWords + q];
-    for (uint32_t q = lane; q < A1; q += 64) a.out[pwb + A0 + q] = slot[kSlotDirWords + kSlotHalfWords + q];
+    // payload words q < A0 + A1 of the tile (half 0, then half 1): up to 512
+    // are loaded before any is stored (the stores may alias the slot as far
+    // as the compiler knows, which would otherwise put one load latency on
+    // every 64 words), the rest in a loop
+    constexpr uint32_t kC = 8;
+    const uint32_t nw = A0 + A1;
+    auto src = [&](uint32_t q) {
+        return q < A0 ? kSlotDirWords + q : kSlotDirWords + kSlotHalfWords + (q - A0);
+    };
+    uint32_t x[kC];
+#pragma unroll
+    for (uint32_t i = 0; i < kC; ++i) {
+        const uint32_t q = lane + 64 * i;
+        x[i] = q < nw ? slot[src(q)] : 0u;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kC; ++i) {
+        const uint32_t q = lane + 64 * i;
+        if (q < nw) a.out[pwb + q] = x[i];
+    }
+    for (uint32_t q = lane + 64 * kC; q < nw; q += 64) a.out[pwb + q] = slot[src(q)];
 }
 
 // ------------------------------------------------------------------ select / features

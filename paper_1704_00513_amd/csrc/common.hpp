@@ -171,6 +171,8 @@ struct Plan {
     uint32_t *unit_words; // [2 max_tiles] payload words per unit (unit 2t + h: half h of tile t)
     uint32_t *unit_off;   // [2 max_tiles] exclusive prefix of unit_words within the unit's chunk
     uint32_t *chunk_words;  // [chunks] payload words of every chunk of kScanChunk units
+    uint2 *tile_seg;      // [max_tiles] segment of each tile and the segment's first tile,
+                          // written by the pack pass (encode only)
     uint32_t *slots;      // [max_tiles][kSlotWords] (encode only)
     uint32_t max_tiles;
 };
@@ -205,6 +207,8 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     off = align256(off + 2 * mt * 4);
     if (p) p->chunk_words = (uint32_t *)(b + off);
     off = align256(off + ((2 * mt + kScanChunk - 1) / kScanChunk) * 4);
+    if (p) p->tile_seg = slots ? (uint2 *)(b + off) : nullptr;
+    if (slots) off = align256(off + mt * 8);
     if (p) p->slots = slots ? (uint32_t *)(b + off) : nullptr;
     if (slots) off = align256(off + mt * (size_t)kSlotWords * 4);
     if (p) p->max_tiles = (uint32_t)mt;
