@@ -642,6 +642,13 @@ __device__ __forceinline__ uint32_t row_max(uint32_t v) {
     v = max(v, dpp<0xB1>(v, v));
     return v;
 }
+__device__ __forceinline__ uint32_t row_min(uint32_t v) {
+    v = min(v, dpp<0x140>(v, v));
+    v = min(v, dpp<0x141>(v, v));
+    v = min(v, dpp<0x4E>(v, v));
+    v = min(v, dpp<0xB1>(v, v));
+    return v;
+}
 __device__ __forceinline__ uint32_t row_sum(uint32_t v) {
     v += dpp<0x140>(v, v);
     v += dpp<0x141>(v, v);
@@ -670,14 +677,15 @@ constexpr uint32_t kUnitStage = kUnitPay + 128;
 // aligned) encoded by the wave in two passes of four blocks, one block per
 // 16-lane row: lane i of row r holds IDs 8i .. 8i+7 of block 4p + r in pass
 // p.  The per-block analysis is then a few row reductions shared by four
-// blocks and the class choice is ordinary vector code (the same choice as
-// enc_full: exhaustive, or the plain minimal width).  The payloads are
+// blocks and the class choice is ordinary vector code, the same choice as
+// enc_full for the selection kind (FullSel) of the block: selu for every
+// block, or sel8[k] for block k when sel8 (LDS) is given.  The payloads are
 // assembled back to back in the wave's LDS area st (kUnitStage words) and
 // copied to pay (16-byte aligned); the 16 directory words go to dir.
 // Returns the unit's payload words.
 __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, uint32_t lo, uint32_t hi,
-                                               bool exhaustive, uint32_t *pay, uint32_t *dir, uint32_t *st,
-                                               uint32_t lane, uint32_t *err) {
+                                               uint32_t selu, const uint8_t *sel8, uint32_t *pay, uint32_t *dir,
+                                               uint32_t *st, uint32_t lane, uint32_t *err) {
     constexpr uint32_t m = kBlock - 1;
     const uint32_t ri = lane & 15, r = lane >> 4;
     const uint64_t all = ballot(true);
@@ -725,20 +733,24 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
         for (uint32_t k = 0; k < 8; ++k) v[k] = pin(v[k]);
 
         // choice, uniform inside each row
+        const uint32_t sel = sel8 ? sel8[4 * p + r] : selu;
+        const bool exh = sel == kSelExhaustive, pf = sel == kSelPfor;
         const uint32_t bpw = (m * wmin + 31) >> 5;
         uint32_t cls = 1 + wmin, param = wmin, aux = 0, words = bpw;
-        if (exhaustive) {
-            const uint32_t bmw = (span + 31) >> 5;
-            if ((span <= kBitmapMaxSpan) & (bmw < words)) {
-                cls = kClsBitmap;
-                param = 0;
-                aux = span;
-                words = bmw;
-            }
-            // PFOR: fewest words with 10 E <= m, ties to the larger b; the
-            // same bound as enc_full prunes widths that cannot win
-            uint32_t best = bpw, pfb = 0, pfe = 0;
-            const uint32_t bcap = words >= 3 ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
+        const uint32_t bmw = (span + 31) >> 5;
+        if ((sel == kSelBitmap) | (exh & (span <= kBitmapMaxSpan) & (bmw < words))) {
+            cls = kClsBitmap;
+            param = 0;
+            aux = span;
+            words = bmw;
+        }
+        if (ballot(exh | pf) != 0ull) {
+            // PFOR: fewest words with 10 E <= m, ties to the larger b.  For
+            // the exhaustive choice the same bound as enc_full prunes widths
+            // that cannot win; a block resolved to PFOR tries every b < wmin
+            // (and keeps b = wmin, no exceptions, if none is smaller)
+            uint32_t best = bpw, pfb = wmin, pfe = 0;
+            const uint32_t bcap = pf ? wmin : exh & (words >= 3) ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
             uint32_t b = bcap;
             bool live = b > 0;
             while (ballot(live) != 0ull) {
@@ -763,7 +775,7 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
                     }
                 }
             }
-            if (best < words) {
+            if ((exh & (best < words)) | pf) {
                 cls = kClsPfor;
                 param = pfb;
                 aux = pfe | (pfe ? (wmin - pfb) << 8 : 0u);
@@ -982,7 +994,8 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
             const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
             uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
             if (kGrp && !a.classes && cnt == kIds) {
-                run = enc_unit_r(src, ((uintptr_t)src & 15) == 0, lo, hi, a.mode != BFSC_SEL_PLAIN_BP,
+                run = enc_unit_r(src, ((uintptr_t)src & 15) == 0, lo, hi,
+                                 a.mode == BFSC_SEL_PLAIN_BP ? kSelPlain : kSelExhaustive, nullptr,
                                  slot + kSlotDirWords + h * kSlotHalfWords, slot + 2 * h * kHalf, sid, lane, a.err);
                 if (lane == 0) a.p.unit_words[u] = run;
                 continue;
@@ -1030,6 +1043,79 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
     }
 }
 
+// The eight fp16 features (block_features) of a full unit's 8 blocks, one
+// block per 16-lane row in two passes as in enc_unit_r: x[k][0..7] and the
+// span of block k in span[k] (LDS).  The statistics are the ones
+// analyze_block computes for a block of 128 IDs.
+__device__ __forceinline__ void unit_features_r(const uint32_t *src, bool al16, uint32_t lo, uint32_t hi,
+                                                uint32_t seg_n, int32_t level, uint16_t (*x)[kIn],
+                                                uint32_t *span_out, uint32_t lane, uint32_t *err) {
+    constexpr uint32_t m = kBlock - 1;
+    const uint32_t ri = lane & 15, r = lane >> 4;
+    const uint64_t all = ballot(true);
+    const int32_t L = level < 0 ? 0 : (level > 63 ? 63 : level);
+#pragma unroll 1
+    for (uint32_t p = 0; p < 2; ++p) {
+        uint32_t v[8];
+        const uint32_t *ps = src + 512 * p + 8 * lane;
+        if (al16) {
+            const uint4 x0 = ((const uint4 *)ps)[0], x1 = ((const uint4 *)ps)[1];
+            v[0] = x0.x, v[1] = x0.y, v[2] = x0.z, v[3] = x0.w;
+            v[4] = x1.x, v[5] = x1.y, v[6] = x1.z, v[7] = x1.w;
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < 8; ++k) v[k] = ps[k];
+        }
+        const uint32_t pv = dpp<0x111>(v[0], v[7]);  // the row's first lane: its own first ID
+        uint64_t okm = ballot(ri == 0 || v[0] > pv);
+        uint32_t dmax = v[0] - pv, dmin = ri ? v[0] - pv : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t k = 1; k < 8; ++k) {
+            okm &= ballot(v[k] > v[k - 1]);
+            dmax = max(dmax, v[k] - v[k - 1]);
+            dmin = min(dmin, v[k] - v[k - 1]);
+        }
+        const uint32_t v0 = dpp<0x150>(v[0], v[0]), vl = dpp<0x15F>(v[7], v[7]);
+        okm &= ballot((v0 >= lo) & (vl < hi));
+        if (okm != all) {
+            if (lane == 0) raise_err(err, kErrInval);
+        }
+        const uint32_t wmin = bitlen32(row_max(dmax)), mn = row_min(dmin), span = vl - v0;
+        float f[8];
+        f[0] = 1.0f;
+        f[1] = (float)bitlen32(mn) / 32.0f;
+        f[2] = (float)wmin / 32.0f;
+        f[3] = (float)bitlen32(span / m) / 32.0f;
+        f[4] = (float)bitlen32(span) / 32.0f;
+        f[5] = __fdiv_rn((float)kBlock, (float)((uint64_t)span + 1ull));
+        f[6] = (float)L / 64.0f;
+        f[7] = (float)bitlen32(seg_n) / 32.0f;
+        float fv = f[0];
+#pragma unroll
+        for (uint32_t q = 1; q < 8; ++q) fv = ri == q ? f[q] : fv;
+        if (ri < 8) x[4 * p + r][ri] = f16bits(fv);
+        if (ri == 0) span_out[4 * p + r] = span;
+    }
+}
+
+// The network on a unit's blocks (sample k: block k < nblk, features
+// x[k], the other samples zero): the predicted class of sample lane & 15.
+__device__ __forceinline__ uint32_t unit_predict(const MlpMfma &W, const uint16_t (*x)[kIn], uint32_t nblk,
+                                                 uint32_t lane) {
+    half4_t xv = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+    const uint32_t smp = lane & 15;
+    if (lane < 32 && smp < nblk) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = __builtin_bit_cast(_Float16, x[smp][(lane >> 4) * 4 + j]);
+    }
+    float4_t z[3];
+    // operand tiles are read from LDS here, not kept in registers across the
+    // unit loop (that would cost 64 VGPRs of occupancy)
+    __asm__ volatile("" ::: "memory");
+    mlp16(W, xv, lane, z);
+    return mlp16_argmax(z, lane);
+}
+
 // Pack pass with the learned choice fused in, one wave per unit.  The wave
 // stages the unit's IDs in LDS, computes every block's eight fp16 features,
 // evaluates the network for the unit's blocks at once on the matrix cores
@@ -1043,11 +1129,13 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
     constexpr uint32_t kIds = kHalf * kBlock;
     constexpr uint32_t kPerLane = kIds / 64;
     __shared__ MlpMfma s_w;
-    __shared__ uint32_t s_ids[WAVES][kIds];
+    // staged IDs (partial units) or the row encoder's payload area (full units)
+    __shared__ __align__(16) uint32_t s_ids[WAVES][kUnitStage];
     __shared__ uint32_t s_buf[WAVES][132];
     __shared__ uint16_t s_x[WAVES][kHalf][kIn];
     __shared__ uint32_t s_span[WAVES][kHalf];
     __shared__ uint32_t s_wmin[WAVES][kHalf];
+    __shared__ uint8_t s_sel[WAVES][kHalf];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     mlp_mfma_stage(&s_w, a.w, tid, WAVES * 64);
     __syncthreads();
@@ -1078,6 +1166,30 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             const uint32_t n = c.n, lo = c.lo, hi = c.hi;
             const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
             const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+            if (cnt == kIds) {
+                // full unit: features and packing one block per 16-lane row
+                const bool al16 = ((uintptr_t)src & 15) == 0;
+                unit_features_r(src, al16, lo, hi, n, level, s_x[w], s_span[w], lane, a.err);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t pred = unit_predict(s_w, s_x[w], kHalf, lane);
+                // resolved selection of block lane (bitmap only when valid; NaN
+                // or an invalid bitmap: the exhaustive choice)
+                if (lane < kHalf) {
+                    const uint32_t sel = pred == 255u ? kSelExhaustive
+                                         : pred == kClsBitmap ? (s_span[w][lane] <= kBitmapMaxSpan ? kSelBitmap
+                                                                                                  : kSelExhaustive)
+                                         : pred <= 33u ? kSelPlain : kSelPfor;
+                    s_sel[w][lane] = (uint8_t)sel;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+                run = enc_unit_r(src, al16, lo, hi, kSelExhaustive, s_sel[w], slot + kSlotDirWords + h * kSlotHalfWords,
+                                 slot + 2 * h * kHalf, sid, lane, a.err);
+                if (lane == 0) a.p.unit_words[u] = run;
+                continue;
+            }
             uint32_t v[kPerLane];
 #pragma unroll
             for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
@@ -1107,18 +1219,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
             // the network on the unit's blocks
-            half4_t x = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
-            const uint32_t smp = lane & 15;
-            if (lane < 32 && smp < nblk) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) x[j] = __builtin_bit_cast(_Float16, s_x[w][smp][(lane >> 4) * 4 + j]);
-            }
-            float4_t z[3];
-            // operand tiles are read from LDS here, not kept in registers
-            // across the unit loop (that would cost 64 VGPRs of occupancy)
-            __asm__ volatile("" ::: "memory");
-            mlp16(s_w, x, lane, z);
-            const uint32_t pred = mlp16_argmax(z, lane);
+            const uint32_t pred = unit_predict(s_w, s_x[w], nblk, lane);
             // resolve and pack
             uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
             uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
