@@ -72,3 +72,18 @@ def gpu_features(ctx, b):
     ctx.features(db, feat)
     st = ctx.sync_status()
     return st, feat[:b.n_blocks].cpu().numpy().view(np.uint16)
+
+
+def shifted_batch(b, shift):
+    """The batch with its IDs in a device buffer that starts `shift`
+    elements into an allocation: 4-byte aligned, not 16-byte aligned.
+    Returns the DeviceBatch and the allocation (keep it alive)."""
+    from paper_1704_00513_amd import DeviceBatch
+    t = torch()
+    dev = device_batch(b)
+    ids = np.ascontiguousarray(b.ids, np.uint32)
+    buf = t.zeros(ids.size + shift + 4, dtype=t.int32, device="cuda")
+    if ids.size:
+        buf[shift:shift + ids.size] = t.from_numpy(ids.view(np.int32)).to("cuda")
+    view = buf[shift:shift + max(ids.size, 1)]
+    return DeviceBatch(view, dev.seg_off, dev.seg_lo, dev.seg_hi, dev.seg_level, max_ids=dev.max_ids), buf

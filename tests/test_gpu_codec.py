@@ -7,7 +7,7 @@ import inputs
 import oracle
 from oracle import Batch
 
-from gpu_util import gpu_decode, gpu_encode, gpu_features, gpu_select
+from gpu_util import gpu_decode, gpu_encode, gpu_features, gpu_select, shifted_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -196,3 +196,45 @@ def test_damaged_streams_agree_with_oracle(ctx, dec_mode):
                 np.testing.assert_array_equal(ids, want_ids)
                 np.testing.assert_array_equal(off, want_off)
     ctx.set_tune(dec_mode=3)
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_unaligned_ids_and_output(ctx, shift):
+    """IDs and decoded output at addresses that are not 16-byte aligned take
+    the word-by-word paths of the row encoder and of the row decoder: the
+    stream and the IDs are the same as from aligned buffers."""
+    import paper_1704_00513_amd as P
+    from gpu_util import torch
+    t = torch()
+    before = ctx.get_tune()
+    try:
+        for name, b in batches():
+            if b.n_ids < 1024:
+                continue
+            db, keep = shifted_batch(b, shift)
+            for mode in (oracle.PLAIN_BP, oracle.EXHAUSTIVE):
+                log("unaligned encode shift=%d mode=%d case=%s" % (shift, mode, name))
+                cap = P.Context.encode_bound(b.n_ids, b.nseg)
+                out = t.zeros(cap, dtype=t.uint8, device="cuda")
+                sbo = t.zeros(b.nseg + 1, dtype=t.int64, device="cuda")
+                ctx.encode(db, out, sbo, mode=mode, out_cap=cap)
+                assert ctx.sync_status() == 0
+                sbo_h = sbo.cpu().numpy().view(np.uint64)
+                want, want_off = oracle.encode(b, mode=mode)
+                np.testing.assert_array_equal(sbo_h, want_off, err_msg=name)
+                np.testing.assert_array_equal(out[:int(sbo_h[-1])].cpu().numpy(), want, err_msg=name)
+            stream, sbo = oracle.encode(b)
+            data = t.from_numpy(np.concatenate([stream, np.zeros(4, np.uint8)])).to("cuda")
+            sbo_d = t.from_numpy(np.ascontiguousarray(sbo, np.uint64).view(np.int64)).to("cuda")
+            for dec_mode in (3, 6):
+                log("unaligned decode shift=%d dec_mode=%d case=%s" % (shift, dec_mode, name))
+                ctx.set_tune(dec_mode=dec_mode)
+                obuf = t.zeros(b.n_ids + shift + 4, dtype=t.int32, device="cuda")
+                off = t.zeros(b.nseg + 1, dtype=t.int64, device="cuda")
+                ctx.decode(data, sbo_d, b.nseg, b.n_ids, obuf[shift:shift + b.n_ids], off, out_cap=b.n_ids)
+                assert ctx.sync_status() == 0
+                got = obuf[shift:shift + b.n_ids].cpu().numpy().view(np.uint32)
+                np.testing.assert_array_equal(got, b.ids, err_msg=name)
+            del keep
+    finally:
+        ctx.set_tune(**before)

@@ -8,7 +8,7 @@ import inputs
 import oracle
 from oracle import mlp
 
-from gpu_util import gpu_encode, gpu_select, to_dev, torch
+from gpu_util import gpu_encode, gpu_select, shifted_batch, to_dev, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -237,3 +237,32 @@ def test_fused_learned_encode_equals_two_pass(ctx, weights, waves, strided):
             assert len(seen) >= 2
     finally:
         ctx.set_tune(**before)
+
+
+def test_fused_learned_unaligned_ids(ctx):
+    """The fused learned pack pass reading IDs that are not 16-byte aligned
+    (its row path loads them word by word) writes the oracle's encoding of
+    the selected classes."""
+    import paper_1704_00513_amd as P
+    theta = inputs.mlp_init(11)
+    theta[::3] *= 4.0
+    ctx.mlp_set_weights(theta)
+    t = torch()
+    for b in _codec_batches():
+        if b.n_ids < 1024:
+            continue
+        st, cls, _ = gpu_select(ctx, b, 2)
+        assert st == 0
+        want, want_off = oracle.encode(b, classes=cls)
+        for shift in (1, 3):
+            print("fused learned unaligned shift=%d n=%d" % (shift, b.n_ids), flush=True)
+            db, keep = shifted_batch(b, shift)
+            cap = P.Context.encode_bound(b.n_ids, b.nseg)
+            out = t.zeros(cap, dtype=t.uint8, device="cuda")
+            sbo = t.zeros(b.nseg + 1, dtype=t.int64, device="cuda")
+            ctx.encode(db, out, sbo, mode=2, out_cap=cap)
+            assert ctx.sync_status() == 0
+            sbo_h = sbo.cpu().numpy().view(np.uint64)
+            np.testing.assert_array_equal(sbo_h, want_off)
+            np.testing.assert_array_equal(out[:int(sbo_h[-1])].cpu().numpy(), want)
+            del keep
