@@ -1618,7 +1618,8 @@ __device__ __forceinline__ uint32_t block_words(uint32_t cls, uint32_t param, ui
 
 // Decodes and validates one block whose bw payload words start at buf (LDS;
 // words past bw may hold anything and are never taken as payload); writes
-// its IDs to out[ob ..] unless it is damaged.
+// its IDs to out[ob ..] unless it is damaged.  val: 192 words of LDS (the
+// block's IDs, then a spare slot per lane).
 // FULL: a block of exactly 128 IDs, where every per-lane validity test folds
 // away at compile time.
 template <bool FULL>
@@ -1663,18 +1664,23 @@ __device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t b
         const uint32_t nch = (aux + 63) >> 6;
         uint32_t cnt = 1;
         if (lane == 0) val[0] = v0;
-        for (uint32_t c = 0; c < nch; ++c) {
-            // word 2c for lanes 0..31, 2c+1 for 32..63, read unconditionally:
-            // wi <= 2 nch - 1 <= bw, at most one word past the block, still
-            // inside the staging buffer; words past bw count as zero
-            const uint32_t wi = lane < 32 ? 2 * c : 2 * c + 1;
-            const uint32_t rw = buf[wi];
+        // word 2c for lanes 0..31, 2c+1 for 32..63, read one step ahead and
+        // unconditionally: wi + 2 <= 2 nch + 1 <= bw + 2, at most two words
+        // past the block, still inside the staging buffer (132 words, or the
+        // unit's words + 4); words past bw count as zero
+        uint32_t wi = lane < 32 ? 0u : 1u;
+        uint32_t rw = buf[wi];
+        for (uint32_t c = 0; c < nch; ++c, wi += 2) {
+            const uint32_t rn = buf[wi + 2];
             const uint32_t word = wi < bw ? rw : 0u;
+            rw = rn;
             const bool set = (word >> (lane & 31)) & 1u;
             const uint64_t mk = ballot(set);
-            // a damaged block may set more than 127 bits: it is rejected below,
-            // and its writes stay inside val
-            if (set) val[min(cnt + mbcnt64(mk), 127u)] = v0 + 64 * c + lane + 1;
+            // every lane stores (no exec-mask branch): a lane without a bit
+            // writes its spare slot 128 + lane.  A damaged block may set more
+            // than 127 bits: it is rejected below, and its writes stay inside val
+            const uint32_t rk = pin(min(cnt + mbcnt64(mk), 127u));
+            val[set ? rk : 128u + lane] = v0 + 64 * c + lane + 1;
             cnt += popc64(mk);
         }
         const uint32_t tailw = aux >> 5, tailb = aux & 31;
@@ -1944,7 +1950,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_decode_u(DecArgs a) {
     constexpr uint32_t kWin = kHalf * kBlock;
     constexpr uint32_t kPerLane = kWin / 64;
     __shared__ uint32_t s_win[WAVES][STAGE ? kWin + 4 : 132];
-    __shared__ uint32_t s_val[WAVES][128];
+    __shared__ uint32_t s_val[WAVES][192];  // 128 IDs, 64 spare slots
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t units = 2 * readfirst(a.tile_base[a.nseg]);
     uint32_t *win = s_win[w];
