@@ -807,21 +807,21 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
         const uint32_t qmax = 32 * max(words, 1u) - 1, vb1 = v0 + 1;
         const uint32_t p0 = ri ? (8 * ri - 1) * pw : 0u;  // bit-pack: bit of the lane's first field
         const uint32_t b0 = ri == 0 ? 0u : isbm ? min(v[0] - vb1, qmax) >> 5 : p0 >> 5;
-        // (selects written as bit operations: the compiler keeps them
-        // branch-free)
-        const uint32_t bmsel = isbm ? 0xFFFFFFFFu : 0u, one = bmsel & 1u, base32 = 32 * b0;
-        uint32_t relbp = p0 - base32 - (ri ? 0u : pw);  // bit-pack: window bit of field k
+        // The window bit of a field, rel, is at or past 64 exactly when the
+        // field is not in the window: a bitmap's first ID (v - vb1b wraps),
+        // and every field of a bit-pack too wide for it (its run starts at
+        // 2^31).  Bitmap bits past the window: a lane's IDs increase, so its
+        // last one tells (unsorted input, already flagged, may lose bits but
+        // writes nothing outside the block's words).
+        const uint32_t one = isbm ? 1u : 0u, base32 = 32 * b0, vb1b = vb1 + base32;
+        uint32_t relbp = narrow ? p0 - base32 - (ri ? 0u : pw) : 0x80000000u;  // bit-pack: field k
         uint64_t win = 0;
-        bool ofl = false;
+        const bool ofl = isbm & (v[7] - vb1b >= 64);
 #pragma unroll
         for (uint32_t k = 0; k < 8; ++k) {
-            const bool has = k != 0 || ri != 0;
-            const uint32_t relbm = min(v[k] - vb1, qmax) - base32;
-            const uint32_t rel = relbp ^ ((relbp ^ relbm) & bmsel);
+            const uint32_t rel = isbm ? v[k] - vb1b : relbp;
             const uint32_t val = (BFSC_D(k) & mask) | one;
-            const bool in = has & narrow & (rel < 64);
-            ofl |= has & isbm & (rel >= 64);
-            win |= (uint64_t)(in ? val : 0u) << (rel & 63);
+            win |= (uint64_t)(rel < 64 ? val : 0u) << (rel & 63);
             pin64(win);  // one field at a time: keeps the live registers few
             relbp += pw;
         }
@@ -1946,7 +1946,7 @@ __device__ __forceinline__ void dec_unit_r(const uint32_t *win, uint32_t *val, u
 // in LDS with every load in flight at once; otherwise they are loaded block
 // by block, the next block's words in flight while the current one decodes.
 template <int WAVES, bool STAGE>
-__global__ __launch_bounds__(WAVES * 64) void k_decode_u(DecArgs a) {
+__global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
     constexpr uint32_t kWin = kHalf * kBlock;
     constexpr uint32_t kPerLane = kWin / 64;
     __shared__ uint32_t s_win[WAVES][STAGE ? kWin + 4 : 132];
