@@ -847,27 +847,45 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
                 pos += k != 0 || ri != 0 ? pw : 0u;
             }
         }
-        // PFOR exceptions: positions (bytes, j - 1) and high parts, in order
+        // PFOR exceptions: positions (bytes, j - 1) and high parts, in order.
+        // A block has at most 12 over its 16 lanes, so the counting pass
+        // keeps the first two of each lane (field, delta) and only those are
+        // written; a lane with more (rare) takes the field-by-field loop.
         const bool ispf = cls == kClsPfor;
         if (ballot(ispf) != 0ull) {
             const uint32_t E = aux & 0xFFu, h = aux >> 8;
             const uint32_t lw = (m * pw + 31) >> 5, qw = (E + 3) >> 2;
-            uint32_t xc = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < 8; ++k) xc += ispf & (BFSC_D(k) > mask);
-            uint32_t e = row_excl_scan(xc);
+            uint32_t xc = 0, k0x = 0, d0x = 0, k1x = 0, d1x = 0;
 #pragma unroll
             for (uint32_t k = 0; k < 8; ++k) {
                 const uint32_t dk = BFSC_D(k);
                 const bool x = ispf & (dk > mask);
-                const uint32_t j = 8 * ri + k;
-                // position byte (never crosses a word), then the high part
+                k1x = x & (xc == 1) ? k : k1x;
+                d1x = x & (xc == 1) ? dk : d1x;
+                k0x = x & (xc == 0) ? k : k0x;
+                d0x = x & (xc == 0) ? dk : d0x;
+                xc += x;
+            }
+            const uint32_t e0 = row_excl_scan(xc);
+            // exception number e of this lane at field k with delta dk
+            auto put = [&](uint32_t e, uint32_t k, uint32_t dk) {
                 const uint32_t bp = lw * 32 + e * 8, hp = (lw + qw) * 32 + e * h;
-                atomicOr(x ? sg + (bp >> 5) : dmy0, (j - 1) << (bp & 31));
+                atomicOr(sg + (bp >> 5), (8 * ri + k - 1) << (bp & 31));  // position byte: one word
                 const uint64_t hx = (uint64_t)(dk >> (pw & 31)) << (hp & 31);
-                atomicOr(x ? sg + (hp >> 5) : dmy0, (uint32_t)hx);
-                atomicOr(x ? sg + (hp >> 5) + 1 : dmy1, (uint32_t)(hx >> 32));
-                e += x;
+                atomicOr(sg + (hp >> 5), (uint32_t)hx);
+                atomicOr(sg + (hp >> 5) + 1, (uint32_t)(hx >> 32));
+            };
+            if (xc > 0) put(e0, k0x, d0x);
+            if (xc > 1) put(e0 + 1, k1x, d1x);
+            if (ballot(xc > 2) != 0ull) {
+                uint32_t e = e0;
+#pragma unroll
+                for (uint32_t k = 0; k < 8; ++k) {
+                    const uint32_t dk = BFSC_D(k);
+                    const bool x = ispf & (dk > mask);
+                    if (x & (e >= e0 + 2)) put(e, k, dk);
+                    e += x;
+                }
             }
         }
 #undef BFSC_D
