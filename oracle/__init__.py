@@ -4,7 +4,9 @@ Plain, slow reference implementations of every step of the frontier-codec
 path: a textbook FIFO BFS and its invariant checker, the frontier
 partitioner, the scalar block codec (writer and validating reader), the
 codec selectors, the selector features, the resolve rules (``oracle.c``,
-plain C built with gcc) and the MLP in fp64 numpy (``mlp.py``).
+plain C built with gcc), the MLP in fp64 numpy (``mlp.py``), and the
+candidate exchange of the compressed 2D BFS (unfiltered candidates per owner,
+the receiver's merge and visited filter; numpy below).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
 leg may import this package.  It shares no code with the HIP library.
@@ -289,3 +291,48 @@ def ratio(raw_bytes: int, compressed_bytes: int) -> float:
 def ratio_percent(raw_bytes: int, compressed_bytes: int) -> float:
     """Compression ratio in percent, eq. (10): 100 / ratio."""
     return 100.0 / ratio(raw_bytes, compressed_bytes)
+
+
+# ---------------------------------------------------------------- candidate exchange
+
+def candidates(g, frontier_ids, bounds, level: int = 0) -> Batch:
+    """The row exchange of the compressed 2D BFS (the candidate vector t = A x f
+    compressed and sent to its owners before the visited filter), on one
+    address space.  Owner p holds the frontier vertices in [bounds[p],
+    bounds[p+1]); its candidate set T_p is every neighbour of those vertices,
+    visited or not, sorted and without repeats; segment p*R + d of the batch
+    is T_p restricted to owner d's range [bounds[d], bounds[d+1]).  A vertex
+    that several owners reach appears in each of their sets."""
+    bounds = _u32(bounds)
+    fr = _u32(frontier_ids)
+    R = bounds.size - 1
+    rp = np.asarray(g.row_ptr, np.int64)
+    ids, offs, lo, hi = [], [np.zeros(1, np.uint64)], [], []
+    base = 0
+    for p in range(R):
+        fp = fr[(fr >= bounds[p]) & (fr < bounds[p + 1])]
+        if fp.size:
+            nb = np.concatenate([g.col_idx[rp[u]:rp[u + 1]] for u in fp.tolist()])
+        else:
+            nb = np.zeros(0, np.uint32)
+        tp = np.unique(nb.astype(np.uint32))
+        off = partition(tp, bounds)
+        ids.append(tp)
+        offs.append(off[1:].astype(np.uint64) + np.uint64(base))
+        base += tp.size
+        lo.append(bounds[:-1])
+        hi.append(bounds[1:])
+    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+    return Batch(cat(ids, np.uint32), np.concatenate(offs), cat(lo, np.uint32), cat(hi, np.uint32),
+                 np.full(R * R, level, np.int32))
+
+
+def merge_filter(ids, level: np.ndarray, cur_level: int):
+    """The receiving side: the union of every received candidate, less the
+    visited vertices (level >= 0), is the next frontier (sorted); those get
+    level cur_level + 1.  Returns (frontier u32, new level array)."""
+    u = np.unique(_u32(ids))
+    lv = np.ascontiguousarray(level, np.int32).copy()
+    new = u[lv[u] < 0]
+    lv[new] = cur_level + 1
+    return new.astype(np.uint32), lv
