@@ -182,6 +182,50 @@ int bfsc_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const ui
 int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds,
                    uint32_t nseg, uint64_t *seg_off, void *stream);
 
+/* ---- Candidate exchange (the paper's algorithm "Integration of
+ * compression": the candidate vector t = A x f is compressed, sent to its
+ * owners by ALLTOALLV and decompressed there, and only then multiplied
+ * element-wise by the complement of the visited list), on one GPU.
+ *
+ * The vertex range [0, n_vertices) is split by bounds u32[nseg+1] (device;
+ * bounds[0] = 0, bounds[nseg] = n_vertices, non-decreasing, else the call
+ * reports BFSC_E_INVAL through the error word) into nseg owners.  Owner p
+ * holds the frontier vertices in [bounds[p], bounds[p+1]); its candidate set
+ * T_p is every neighbour of them, visited or not.  T_p restricted to owner
+ * d's range is segment p*nseg + d of a batch (sorted, without repeats), so a
+ * vertex that several owners reach is sent once by each: the exchanged
+ * volume.  Requires nseg * 32 * ceil(n_vertices / 32) < 2^32.
+ *
+ * Workspace: bfsc_exchange_workspace_size bytes (nseg + 1 bitmaps of
+ * n_vertices bits and counters), caller-owned, cleared once by
+ * bfsc_exchange_init before the first bfsc_candidates / bfsc_merge_filter
+ * of a traversal; the calls leave it clear again. */
+int bfsc_exchange_workspace_size(const bfsc_csr *g, uint32_t nseg, size_t *bytes);
+int bfsc_exchange_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t nseg, void *ws, void *stream);
+
+/* The senders' side.  frontier u32[*frontier_len_dev] (device, sorted, as
+ * bfsc_bfs_level writes it).  Writes the nseg*nseg segments back to back:
+ * ids u32[cap] (the candidates; more than cap sets BFSC_E_CAPACITY and the
+ * batch keeps the first cap), seg_off u64[nseg*nseg + 1], seg_lo / seg_hi
+ * u32[nseg*nseg] (bounds[d], bounds[d+1] of segment p*nseg + d): a batch
+ * for bfsc_encode.  All pointers device; asynchronous. */
+int bfsc_candidates(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *frontier,
+                    const uint32_t *frontier_len_dev, const uint32_t *bounds, uint32_t nseg,
+                    uint32_t *ids, uint64_t cap, uint64_t *seg_off, uint32_t *seg_lo,
+                    uint32_t *seg_hi, void *ws, void *stream);
+
+/* The receivers' side.  ids u32[*n_dev] (device; every owner's decoded
+ * segments, as bfsc_decode writes them, in any order, repeats allowed) are
+ * merged into one set; the vertices in it that are not yet visited (the
+ * visited list of the BFS workspace bfs_ws, as bfsc_bfs_init /
+ * bfsc_bfs_level keep it) become visited, get level[w] = cur_level + 1, and
+ * form the next frontier next[0 .. *next_len_dev), sorted ascending
+ * (capacity n_vertices).  parent[] is not written: the exchanged candidates
+ * carry no predecessor.  IDs >= n_vertices are ignored. */
+int bfsc_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *ids,
+                      const uint64_t *n_dev, int32_t *level, uint32_t *next, uint32_t *next_len_dev,
+                      void *bfs_ws, void *ws, void *stream);
+
 /* Chooses a class per block (0 bitmap, 1..33 bit-pack width 0..32, 34 PFOR)
  * for every 128-ID block of every segment, in segment order: classes u8,
  * capacity ceil(max_ids/128) + nseg.  BFSC_SEL_LEARNED resolves the MLP's

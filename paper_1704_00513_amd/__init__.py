@@ -214,6 +214,31 @@ class Context:
         check(_lib.load().bfsc_partition(ptr(ids), ptr(n_dev), ptr(bounds), int(bounds.numel()) - 1,
                                          ptr(seg_off), _stream(stream)), "bfsc_partition")
 
+    # ---------------------------------------------------------- candidate exchange
+
+    def exchange_workspace(self, g: DeviceGraph, nseg: int, key="exchange"):
+        n = ctypes.c_size_t()
+        check(_lib.load().bfsc_exchange_workspace_size(ctypes.byref(g.desc), int(nseg), ctypes.byref(n)),
+              "bfsc_exchange_workspace_size")
+        return self._grow(key, n.value)
+
+    def exchange_init(self, g, nseg, ws, stream=None):
+        check(_lib.load().bfsc_exchange_init(self.h, ctypes.byref(g.desc), int(nseg), ptr(ws), _stream(stream)),
+              "bfsc_exchange_init")
+
+    def candidates(self, g, frontier, frontier_len, bounds, ids, seg_off, seg_lo, seg_hi, ws, cap=None,
+                   stream=None):
+        nseg = int(bounds.numel()) - 1
+        cap = ids.numel() if cap is None else cap
+        check(_lib.load().bfsc_candidates(self.h, ctypes.byref(g.desc), ptr(frontier), ptr(frontier_len),
+                                          ptr(bounds), nseg, ptr(ids), int(cap), ptr(seg_off), ptr(seg_lo),
+                                          ptr(seg_hi), ptr(ws), _stream(stream)), "bfsc_candidates")
+
+    def merge_filter(self, g, cur_level, ids, n_dev, level, nxt, next_len, bfs_ws, ws, stream=None):
+        check(_lib.load().bfsc_merge_filter(self.h, ctypes.byref(g.desc), int(cur_level), ptr(ids), ptr(n_dev),
+                                            ptr(level), ptr(nxt), ptr(next_len), ptr(bfs_ws), ptr(ws),
+                                            _stream(stream)), "bfsc_merge_filter")
+
     # ---------------------------------------------------------- codec
 
     def select(self, b: DeviceBatch, mode, classes, fallbacks=None, ws=None, stream=None):

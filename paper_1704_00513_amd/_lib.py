@@ -66,6 +66,10 @@ _SIGS = {
     "bfsc_bfs_init": [vp, P(CSR), u32, vp, vp, vp, vp, vp, vp],
     "bfsc_bfs_level": [vp, P(CSR), i32, vp, vp, vp, vp, vp, vp, vp, vp],
     "bfsc_partition": [vp, vp, vp, u32, vp, vp],
+    "bfsc_exchange_workspace_size": [P(CSR), u32, P(sz)],
+    "bfsc_exchange_init": [vp, P(CSR), u32, vp, vp],
+    "bfsc_candidates": [vp, P(CSR), vp, vp, vp, u32, vp, u64, vp, vp, vp, vp, vp],
+    "bfsc_merge_filter": [vp, P(CSR), i32, vp, vp, vp, vp, vp, vp, vp, vp],
     "bfsc_select": [vp, P(BatchDesc), ctypes.c_int, vp, vp, vp, vp],
     "bfsc_encode_bound": [u64, u32, P(sz)],
     "bfsc_encode": [vp, P(BatchDesc), vp, ctypes.c_int, vp, sz, vp, vp, vp],

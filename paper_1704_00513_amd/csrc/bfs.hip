@@ -11,6 +11,7 @@
 // concatenated small adjacency lists; vertices of degree >= 16384 are cut
 // into 8192-edge chunks and queued for a second, grid-wide kernel.
 #include "common.hpp"
+#include "exchange.hpp"
 
 namespace bfsc {
 
@@ -313,6 +314,257 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws, next_len);
     hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next);
     timing_end(ctx, slot, s);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+// ------------------------------------------------------------------ candidate exchange
+
+// The row exchange of the compressed 2D BFS (the candidate vector t = A x f,
+// compressed and sent to the owners before the element-wise filter with the
+// complement of the visited list, in the paper's algorithm with compression
+// integrated), on one GPU.  The vertex range is split by bounds[0..R] into R
+// owners.  Owner p's frontier vertices (those in [bounds[p], bounds[p+1]))
+// expand into owner p's candidate bitmap, visited or not; the R bitmaps are
+// compacted as one, in key order p*V + w, which is the order of the
+// segments (p, d) of the batch; the receiver ORs every decoded candidate
+// into one bitmap and keeps what is not yet visited.
+
+// Workspace: the merge bitmap (first, so that its place does not depend on
+// R), R candidate bitmaps of S = 32 * ceil(V/32) bits (compacted through a BfsWs view), the
+// segment bounds in key space, the candidate count.
+struct ExWs {
+    uint32_t *merged;
+    BfsWs cb;        // next_bm: the R bitmaps back to back (words = R * V/32)
+    uint32_t *keyb;  // [R*R + 1] first key of segment p*R + d
+    uint32_t *count; // [4] [0]: candidates found, [1]: kept (capacity)
+    uint32_t words;  // V/32 (rounded up)
+};
+
+static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint32_t nseg, size_t *bytes) {
+    ExWs w;
+    char *b = (char *)ws;
+    size_t off = 0;
+    w.words = (V + 31) / 32;
+    w.merged = (uint32_t *)(b + off);
+    off = align256(off + (size_t)w.words * 4);
+    const uint64_t cw = (uint64_t)w.words * nseg;
+    w.cb.visited = nullptr;
+    w.cb.next_bm = (uint32_t *)(b + off);
+    off = align256(off + cw * 4);
+    w.cb.words = (uint32_t)cw;
+    w.cb.nchunks = (uint32_t)((cw + kCompactWords - 1) / kCompactWords);
+    w.cb.chunk = (uint32_t *)(b + off);
+    off = align256(off + ((size_t)w.cb.nchunks + 1) * 4);
+    w.cb.qcount = (uint32_t *)(b + off);  // written by the compaction scan, unused here
+    off = align256(off + 16);
+    w.cb.queue = nullptr;
+    w.cb.qcap = 0;
+    w.keyb = (uint32_t *)(b + off);
+    off = align256(off + ((size_t)nseg * nseg + 1) * 4);
+    w.count = (uint32_t *)(b + off);
+    off = align256(off + 16);
+    if (bytes) *bytes = off;
+    return w;
+}
+
+size_t ex_ws_bytes(uint32_t V, uint32_t nseg) {
+    size_t bytes;
+    ex_ws_layout(nullptr, V, nseg, &bytes);
+    return bytes;
+}
+
+__global__ void k_ex_zero(uint32_t *a, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0u;
+}
+
+// Keys: owner p's bitmap starts at bit p*S, S = 32 * ceil(V/32), so vertex w
+// of owner p has key p*S + w.  Segment p*R + d holds the keys
+// [p*S + bounds[d], p*S + bounds[d+1]); the owners must cover [0, V) in order
+// (else the batch is flagged invalid).
+__global__ void k_ex_keyb(const uint32_t *bounds, uint32_t R, uint32_t V, uint32_t S, uint32_t *keyb,
+                          uint32_t *err) {
+    const uint32_t RR = R * R;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < RR; i += gridDim.x * blockDim.x)
+        keyb[i] = (i / R) * S + bounds[i % R];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        keyb[RR] = (uint32_t)((uint64_t)R * S);
+        bool ok = bounds[0] == 0 && bounds[R] == V;
+        for (uint32_t r = 0; r < R; ++r) ok = ok && bounds[r] <= bounds[r + 1];
+        if (!ok) raise_err(err, kErrInval);
+    }
+}
+
+// Every arc (u, w) of a frontier vertex u of owner p sets bit w of owner p's
+// bitmap.  A wave takes 64 consecutive frontier vertices and walks their
+// concatenated adjacency lists 64 arcs at a time (lane k: arc k, its vertex
+// found by a binary search over the degree prefix sums in LDS).
+__global__ __launch_bounds__(256) void k_ex_expand(const uint64_t *row_ptr, const uint32_t *col_idx,
+                                                   const uint32_t *frontier, const uint32_t *flen,
+                                                   const uint32_t *bounds, uint32_t R, uint32_t words,
+                                                   uint32_t *cand) {
+    __shared__ uint64_t s_beg[4][64];
+    __shared__ uint32_t s_cum[4][64];
+    __shared__ uint32_t s_own[4][64];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t n = *flen;
+    for (uint64_t base = ((uint64_t)blockIdx.x * 4 + w) * 64; base < n; base += (uint64_t)gridDim.x * 256) {
+        const uint64_t i = base + lane;
+        uint32_t deg = 0, own = 0;
+        uint64_t beg = 0;
+        if (i < n) {
+            const uint32_t u = frontier[i];
+            beg = row_ptr[u];
+            deg = (uint32_t)(row_ptr[u + 1] - beg);
+            own = upper_bound_m1(bounds, R, u);
+        }
+        const uint32_t incl = wave_incl_scan(deg);
+        const uint32_t total = readlane(incl, 63);
+        s_beg[w][lane] = beg;
+        s_cum[w][lane] = incl - deg;
+        s_own[w][lane] = own;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t k = lane; k < total; k += 64) {
+            // the last vertex whose arcs start at or before arc k (vertices
+            // without arcs share their start with the next one)
+            uint32_t lo = 0, hi = 64;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_cum[w][mid] <= k) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t x = col_idx[s_beg[w][lo] + (k - s_cum[w][lo])];
+            atomicOr(&cand[(uint64_t)s_own[w][lo] * words + (x >> 5)], 1u << (x & 31));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The candidates' keys in order (k_bfs_emit with a capacity: keys past cap
+// are dropped), the bitmap cleared for the next call.
+__global__ __launch_bounds__(256) void k_ex_emit(BfsWs ws, uint32_t *keys, uint64_t cap) {
+    __shared__ uint32_t s_wt[4];
+    const uint32_t c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const uint32_t w0 = c * kCompactWords + tid * 4;
+    uint32_t x[4], cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        x[k] = (w0 + k < ws.words) ? ws.next_bm[w0 + k] : 0u;
+        cnt += __popc(x[k]);
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    if (lane == 63) s_wt[tid >> 6] = incl;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (uint32_t q = 0; q < (tid >> 6); ++q) wb += s_wt[q];
+    uint64_t pos = (uint64_t)ws.chunk[c] + wb + incl - cnt;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t v = x[k];
+        while (v) {
+            const uint32_t b = __builtin_ctz(v);
+            v &= v - 1;
+            if (pos < cap) keys[pos] = (w0 + k) * 32 + b;
+            ++pos;
+        }
+        if (x[k]) ws.next_bm[w0 + k] = 0u;
+    }
+}
+
+__global__ void k_ex_clamp(uint32_t *count, uint64_t cap, uint32_t *err) {
+    const uint32_t n = count[0];
+    count[1] = (uint64_t)n > cap ? (uint32_t)cap : n;
+    if ((uint64_t)n > cap) raise_err(err, kErrCapacity);
+}
+
+// Keys back to vertex IDs; each segment's range.
+__global__ void k_ex_finish(uint32_t *ids, const uint32_t *count, uint32_t S, const uint32_t *bounds, uint32_t R,
+                            uint32_t *seg_lo, uint32_t *seg_hi) {
+    const uint32_t n = count[1];
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) ids[i] = ids[i] % S;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R * R; i += stride) {
+        seg_lo[i] = bounds[i % R];
+        seg_hi[i] = bounds[i % R + 1];
+    }
+}
+
+// Receiver: every decoded candidate into one bitmap (IDs outside [0, V) are
+// ignored: a damaged stream is reported by the decoder).
+__global__ void k_ex_merge(const uint32_t *ids, const uint64_t *n_dev, uint32_t V, uint32_t *merged) {
+    const uint64_t n = *n_dev, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t w = ids[i];
+        if (w < V) atomicOr(&merged[w >> 5], 1u << (w & 31));
+    }
+}
+
+// ... less the visited vertices: the rest are marked visited, get level nl,
+// and go to the next-level bitmap (compacted as in a BFS level).  One thread
+// per word, so the visited word is updated without atomics.
+__global__ void k_ex_filter(uint32_t *merged, BfsWs ws, int32_t *level, int32_t nl) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ws.words; i += stride) {
+        const uint32_t m = merged[i];
+        if (!m) continue;
+        merged[i] = 0u;
+        const uint32_t nb = m & ~ws.visited[i];
+        if (!nb) continue;
+        ws.visited[i] |= nb;
+        ws.next_bm[i] |= nb;
+        uint32_t v = nb;
+        while (v) {
+            const uint32_t b = __builtin_ctz(v);
+            v &= v - 1;
+            level[i * 32 + b] = nl;
+        }
+    }
+}
+
+int launch_ex_init(bfsc_ctx *ctx, uint32_t V, uint32_t nseg, void *wsp, hipStream_t s) {
+    ExWs ws = ex_ws_layout(wsp, V, nseg, nullptr);
+    const uint32_t grid = (uint32_t)ctx->n_cu * 8;
+    hipLaunchKernelGGL(k_ex_zero, dim3(grid), dim3(256), 0, s, ws.cb.next_bm, (uint64_t)ws.cb.words);
+    hipLaunchKernelGGL(k_ex_zero, dim3(grid), dim3(256), 0, s, ws.merged, (uint64_t)ws.words);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+int launch_candidates(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *frontier, const uint32_t *frontier_len,
+                      const uint32_t *bounds, uint32_t nseg, uint32_t *ids, uint64_t cap, uint64_t *seg_off,
+                      uint32_t *seg_lo, uint32_t *seg_hi, void *wsp, hipStream_t s) {
+    const uint32_t V = g->n_vertices;
+    ExWs ws = ex_ws_layout(wsp, V, nseg, nullptr);
+    const uint32_t grid = (uint32_t)ctx->n_cu * 8;
+    const uint32_t S = ws.words * 32;
+    hipLaunchKernelGGL(k_ex_keyb, dim3((nseg * nseg + 255) / 256), dim3(256), 0, s, bounds, nseg, V, S, ws.keyb,
+                       ctx->err);
+    hipLaunchKernelGGL(k_ex_expand, dim3(grid), dim3(256), 0, s, g->row_ptr, g->col_idx, frontier, frontier_len,
+                       bounds, nseg, ws.words, ws.cb.next_bm);
+    hipLaunchKernelGGL(k_bfs_count, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb);
+    hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws.cb, ws.count);
+    hipLaunchKernelGGL(k_ex_emit, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb, ids, cap);
+    hipLaunchKernelGGL(k_ex_clamp, dim3(1), dim3(1), 0, s, ws.count, cap, ctx->err);
+    if (hipGetLastError() != hipSuccess) return BFSC_E_HIP;
+    const int st = launch_partition(ids, ws.count + 1, ws.keyb, nseg * nseg, seg_off, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_ex_finish, dim3(grid), dim3(256), 0, s, ids, ws.count, S, bounds, nseg, seg_lo, seg_hi);
+    return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
+}
+
+int launch_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *ids,
+                        const uint64_t *n_dev, int32_t *level, uint32_t *next, uint32_t *next_len, void *bfs_wsp,
+                        void *wsp, hipStream_t s) {
+    const uint32_t V = g->n_vertices;
+    BfsWs bws = bfs_ws_layout(bfs_wsp, V, g->n_arcs, nullptr);
+    ExWs ws = ex_ws_layout(wsp, V, 1, nullptr);  // the merge bitmap's place does not depend on R
+    const uint32_t grid = (uint32_t)ctx->n_cu * 8;
+    hipLaunchKernelGGL(k_ex_merge, dim3(grid), dim3(256), 0, s, ids, n_dev, V, ws.merged);
+    hipLaunchKernelGGL(k_ex_filter, dim3(grid), dim3(256), 0, s, ws.merged, bws, level, cur_level + 1);
+    hipLaunchKernelGGL(k_bfs_count, dim3(bws.nchunks), dim3(256), 0, s, bws);
+    hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, bws, next_len);
+    hipLaunchKernelGGL(k_bfs_emit, dim3(bws.nchunks), dim3(256), 0, s, bws, next);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 

@@ -7,6 +7,7 @@
 #include <new>
 
 #include "common.hpp"
+#include "exchange.hpp"
 #include "mlp_mfma.hpp"
 
 using namespace bfsc;
@@ -164,6 +165,45 @@ int bfsc_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const ui
     if (set_device(ctx)) return BFSC_E_HIP;
     return launch_bfs_level(ctx, g, cur_level, frontier, frontier_len_dev, level, parent, next,
                             next_len_dev, ws, S(stream));
+}
+
+// keys p*V + w of the candidate exchange must fit 32 bits
+static bool ex_ok(const bfsc_csr *g, uint32_t nseg) {
+    return g && g->n_vertices > 0 && g->n_vertices <= 0x7FFFFFFFu && nseg > 0 &&
+           (uint64_t)nseg * ((g->n_vertices + 31ull) & ~31ull) <= 0xFFFFFFFFull;
+}
+
+int bfsc_exchange_workspace_size(const bfsc_csr *g, uint32_t nseg, size_t *bytes) {
+    if (!bytes || !ex_ok(g, nseg)) return BFSC_E_INVAL;
+    *bytes = ex_ws_bytes(g->n_vertices, nseg);
+    return BFSC_OK;
+}
+
+int bfsc_exchange_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t nseg, void *ws, void *stream) {
+    if (!ctx || !ws || !ex_ok(g, nseg)) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_ex_init(ctx, g->n_vertices, nseg, ws, S(stream));
+}
+
+int bfsc_candidates(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *frontier, const uint32_t *frontier_len_dev,
+                    const uint32_t *bounds, uint32_t nseg, uint32_t *ids, uint64_t cap, uint64_t *seg_off,
+                    uint32_t *seg_lo, uint32_t *seg_hi, void *ws, void *stream) {
+    if (!ctx || !ex_ok(g, nseg) || !g->row_ptr || !g->col_idx || !frontier || !frontier_len_dev || !bounds ||
+        !ids || !seg_off || !seg_lo || !seg_hi || !ws)
+        return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_candidates(ctx, g, frontier, frontier_len_dev, bounds, nseg, ids, cap, seg_off, seg_lo, seg_hi,
+                             ws, S(stream));
+}
+
+int bfsc_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *ids,
+                      const uint64_t *n_dev, int32_t *level, uint32_t *next, uint32_t *next_len_dev, void *bfs_ws,
+                      void *ws, void *stream) {
+    if (!ctx || !ex_ok(g, 1) || !ids || !n_dev || !level || !next || !next_len_dev || !bfs_ws || !ws ||
+        cur_level < 0)
+        return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_merge_filter(ctx, g, cur_level, ids, n_dev, level, next, next_len_dev, bfs_ws, ws, S(stream));
 }
 
 int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds, uint32_t nseg,
