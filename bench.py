@@ -419,6 +419,7 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
                                    "batched_speedup": round(4.0 * N / (ms_step * 1e-3) / 1e9 / pg, 2)}
 
     out["per_level_root0"] = per_level(ctx, P, torch, b, host, mode)
+    out["exchange_root0"] = exchange_leg(ctx, P, torch, g, int(roots[0]), host, args.nseg, mode)
     out["mall_cold"] = mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps)
 
     # per-level pipeline for the first root: graph replay vs eager launches
@@ -487,6 +488,114 @@ def per_level(ctx, P, torch, b, host, mode, reps=10):
                     "GBps": round(4.0 * n / (us * 1e-6) / 1e9, 2),
                     "classes": {"bitmap": int(c[0]), "bitpack": int(c[1:34].sum()), "pfor": int(c[34])}})
     return res
+
+
+def exchange_leg(ctx, P, torch, g, root, host, nseg, mode, reps=3):
+    """The first root's traversal through the candidate exchange of the 2D
+    BFS: per level, every owner's unfiltered candidates (nseg*nseg segments)
+    are compressed, decompressed, merged and filtered by the receivers.  The
+    exchanged volume, its compression and the time of each phase (stream
+    events), the best of `reps` traversals; the levels are checked against a
+    plain GPU BFS."""
+    V = g.n_vertices
+    S = (V + 31) // 32 * 32
+    bounds_h = np.concatenate([[host["seg_lo"][0]], host["seg_hi"][:nseg]]).astype(np.uint32)
+    if nseg * S >= 1 << 32:  # candidate keys are u32: fall back to 16 equal owners
+        import inputs
+        nseg = 16
+        bounds_h = inputs.bounds_equal(V, nseg)
+    RR = nseg * nseg
+    dg = P.DeviceGraph.from_host(g)
+    i32 = dict(dtype=torch.int32, device="cuda")
+    level, parent = torch.empty(V, **i32), torch.empty(V, **i32)
+    fa, fb = torch.empty(V, **i32), torch.empty(V, **i32)
+    la, lb = torch.zeros(1, **i32), torch.zeros(1, **i32)
+    bws = ctx.bfs_workspace(dg)
+    xws = ctx.exchange_workspace(dg, nseg)
+    ctx.exchange_init(dg, nseg, xws)
+    bounds = torch.from_numpy(bounds_h.view(np.int32)).cuda()
+    cap = max(1, g.n_arcs)
+    ids = torch.zeros(cap, **i32)
+    seg_off = torch.zeros(RR + 1, dtype=torch.int64, device="cuda")
+    seg_lo, seg_hi = torch.zeros(RR, **i32), torch.zeros(RR, **i32)
+    seg_level = torch.zeros(RR, **i32)
+    db = P.DeviceBatch(ids, seg_off, seg_lo, seg_hi, seg_level, max_ids=cap)
+    bcap = P.Context.encode_bound(cap, RR)
+    stream = torch.zeros(bcap, dtype=torch.uint8, device="cuda")
+    sbo = torch.zeros(RR + 1, dtype=torch.int64, device="cuda")
+    out = torch.zeros(cap, **i32)
+    out_off = torch.zeros(RR + 1, dtype=torch.int64, device="cuda")
+
+    def traversal():
+        ctx.bfs_init(dg, root, level, parent, fa, la, bws)
+        f, fn, nxt, nn = fa, la, fb, lb
+        rows, L = [], 0
+        while True:
+            n = int(fn.item())
+            if n == 0:
+                break
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            seg_level.fill_(L)  # a feature of the learned selector
+            ev[0].record()
+            ctx.candidates(dg, f, fn, bounds, ids, seg_off, seg_lo, seg_hi, xws)
+            ev[1].record()
+            ctx.encode(db, stream, sbo, mode=mode, out_cap=bcap)
+            ctx.decode(stream, sbo, RR, cap, out, out_off)
+            ev[2].record()
+            ctx.merge_filter(dg, L, out, out_off[RR:], level, nxt, nn, bws, xws)
+            ev[3].record()
+            torch.cuda.synchronize()
+            rows.append(dict(level=L, frontier=n, candidates=int(seg_off[-1].item()),
+                             bytes=int(sbo[-1].item()), us_candidates=ev[0].elapsed_time(ev[1]) * 1e3,
+                             us_codec=ev[1].elapsed_time(ev[2]) * 1e3, us_merge=ev[2].elapsed_time(ev[3]) * 1e3))
+            f, fn, nxt, nn = nxt, nn, f, fn
+            L += 1
+        return rows
+
+    traversal()
+    assert ctx.sync_status() == 0, "candidate exchange reported an error"
+    got = level.clone()
+    # the same levels from the plain BFS (filtered frontier, no exchange),
+    # each level timed for comparison
+    bfs_us = []
+    for rep in range(reps):
+        ctx.bfs_init(dg, root, level, parent, fa, la, bws)
+        L, us = 0, []
+        while int(la.item()):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.bfs_level(dg, L, fa, la, level, parent, fb, lb, bws)
+            e1.record()
+            torch.cuda.synchronize()
+            us.append(e0.elapsed_time(e1) * 1e3)
+            fa, fb, la, lb = fb, fa, lb, la
+            L += 1
+        if not bfs_us or sum(us) < sum(bfs_us):
+            bfs_us = us
+    assert torch.equal(got, level), "exchange traversal levels differ from the BFS"
+    best = None
+    for _ in range(reps):
+        rows = traversal()
+        t = sum(r["us_candidates"] + r["us_codec"] + r["us_merge"] for r in rows)
+        if best is None or t < best[0]:
+            best = (t, rows)
+    rows = best[1]
+    cand = sum(r["candidates"] for r in rows)
+    comp = sum(r["bytes"] for r in rows)
+    codec_us = sum(r["us_codec"] for r in rows)
+    return {"owners": nseg, "segments": RR, "levels": len(rows),
+            "frontier_ids": sum(r["frontier"] for r in rows), "candidate_ids": cand, "compressed_bytes": comp,
+            "ratio": round(4.0 * cand / max(1, comp), 3),
+            "ms_candidates": round(sum(r["us_candidates"] for r in rows) / 1e3, 4),
+            "ms_codec": round(codec_us / 1e3, 4),
+            "ms_merge_filter": round(sum(r["us_merge"] for r in rows) / 1e3, 4),
+            "codec_GBps": round(4.0 * cand / max(1e-9, codec_us * 1e-6) / 1e9, 2),
+            "ms_bfs_levels": round(sum(bfs_us) / 1e3, 4),
+            "per_level": [{"level": r["level"], "frontier": r["frontier"], "candidates": r["candidates"],
+                           "ratio": round(4.0 * r["candidates"] / max(1, r["bytes"]), 3),
+                           "us_candidates": round(r["us_candidates"], 1), "us_codec": round(r["us_codec"], 1),
+                           "us_merge": round(r["us_merge"], 1), "us_bfs_level": round(u, 1)}
+                          for r, u in zip(rows, bfs_us)]}
 
 
 def mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps):

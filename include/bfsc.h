@@ -197,7 +197,7 @@ int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *b
  * volume.  Requires nseg * 32 * ceil(n_vertices / 32) < 2^32.
  *
  * Workspace: bfsc_exchange_workspace_size bytes (nseg + 1 bitmaps of
- * n_vertices bits and counters), caller-owned, cleared once by
+ * n_vertices bits, a queue of high-degree vertices, counters), caller-owned, cleared once by
  * bfsc_exchange_init before the first bfsc_candidates / bfsc_merge_filter
  * of a traversal; the calls leave it clear again. */
 int bfsc_exchange_workspace_size(const bfsc_csr *g, uint32_t nseg, size_t *bytes);

@@ -69,11 +69,40 @@ __device__ __forceinline__ void visit(uint32_t w, uint32_t u, int32_t nl, const 
     atomicOr(&ws.next_bm[word], bit);
 }
 
+// What an arc (u, w) of the frontier does, for the expansion kernels below:
+// tag(u) is computed once per frontier vertex and handed to every one of its
+// arcs, visit(w, tag) handles one arc.
+struct BfsVisit {  // a BFS level: the visited filter, level and parent
+    BfsWs ws;
+    int32_t *level, *parent;
+    int32_t nl;                // the new level, from the host ...
+    const int32_t *level_dev;  // ... or one past the level kept on the device
+    __device__ void begin() {
+        if (level_dev) nl = *level_dev + 1;
+    }
+    __device__ uint32_t tag(uint32_t u) const { return u; }
+    __device__ void operator()(uint32_t w, uint32_t u) const { visit(w, u, nl, ws, level, parent); }
+};
+
+struct CandVisit {  // the candidate exchange: bit w of the owner's bitmap, visited or not
+    const uint32_t *bounds;
+    uint32_t R, words;
+    uint32_t *cand;  // R bitmaps of `words` words each
+    __device__ void begin() {}
+    __device__ uint32_t tag(uint32_t u) const { return upper_bound_m1(bounds, R, u) * words; }
+    __device__ void operator()(uint32_t w, uint32_t base) const {
+        uint32_t *p = cand + base + (w >> 5);
+        const uint32_t bit = 1u << (w & 31);
+        if (*p & bit) return;  // bits only get set: skip most atomics
+        atomicOr(p, bit);
+    }
+};
+
+template <class Visit>
 __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
     const uint64_t *row_ptr, const uint32_t *col_idx, const uint32_t *frontier,
-    const uint32_t *frontier_len, int32_t *level, int32_t *parent, int32_t nl_host, const int32_t *level_dev, BfsWs ws) {
-    // the new level: from the host, or one past the level kept on the device
-    const int32_t nl = level_dev ? *level_dev + 1 : nl_host;
+    const uint32_t *frontier_len, Visit vis, BfsWs ws) {
+    vis.begin();
     __shared__ uint32_t s_deg_scan[kExpandThreads];
     __shared__ uint32_t s_u[kExpandThreads];
     __shared__ uint64_t s_start[kExpandThreads];
@@ -89,9 +118,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
         uint32_t u = 0, deg = 0;
         uint64_t start = 0;
         if (i < n) {
-            u = frontier[i];
-            start = row_ptr[u];
-            deg = (uint32_t)(row_ptr[u + 1] - start);
+            const uint32_t f = frontier[i];
+            start = row_ptr[f];
+            deg = (uint32_t)(row_ptr[f + 1] - start);
+            u = vis.tag(f);
         }
         // huge: queue 8192-edge chunks for the grid-wide pass
         if (deg >= kHuge) {
@@ -123,7 +153,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
             __syncthreads();
             const uint32_t bu = s_big_u, blen = s_big_len;
             const uint64_t bs = s_big_start;
-            for (uint32_t e = tid; e < blen; e += kExpandThreads) visit(col_idx[bs + e], bu, nl, ws, level, parent);
+            for (uint32_t e = tid; e < blen; e += kExpandThreads) vis(col_idx[bs + e], bu);
             __syncthreads();
         }
         // medium: whole wave, one vertex at a time
@@ -135,7 +165,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
             const uint64_t ms = ((uint64_t)readlane((uint32_t)(start >> 32), src) << 32) |
                                 readlane((uint32_t)start, src);
             if (lane == src) deg = 0;
-            for (uint32_t e = lane; e < mlen; e += 64) visit(col_idx[ms + e], mu, nl, ws, level, parent);
+            for (uint32_t e = lane; e < mlen; e += 64) vis(col_idx[ms + e], mu);
         }
         // small: gather over the concatenated lists
         uint32_t tot;
@@ -162,21 +192,20 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
                 const uint32_t mid = (lo + hi) >> 1;
                 if (s_deg_scan[mid] <= e) lo = mid; else hi = mid;
             }
-            visit(col_idx[s_start[lo] + (e - s_deg_scan[lo])], s_u[lo], nl, ws, level, parent);
+            vis(col_idx[s_start[lo] + (e - s_deg_scan[lo])], s_u[lo]);
         }
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_bfs_huge(const uint32_t *col_idx, int32_t *level,
-                                                  int32_t *parent, int32_t nl_host,
-                                                  const int32_t *level_dev, BfsWs ws) {
-    const int32_t nl = level_dev ? *level_dev + 1 : nl_host;
+template <class Visit>
+__global__ __launch_bounds__(256) void k_bfs_huge(const uint32_t *col_idx, Visit vis, BfsWs ws) {
+    vis.begin();
     const uint32_t nq = min(*ws.qcount, ws.qcap);
     for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const uint4 c = ws.queue[q];
         const uint64_t s = ((uint64_t)c.z << 32) | c.y;
-        for (uint32_t e = threadIdx.x; e < c.w; e += blockDim.x) visit(col_idx[s + e], c.x, nl, ws, level, parent);
+        for (uint32_t e = threadIdx.x; e < c.w; e += blockDim.x) vis(col_idx[s + e], c.x);
     }
 }
 
@@ -306,10 +335,10 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
     const int32_t nl = cur_level + 1;
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     const int slot = timing_begin(ctx, BFSC_OP_BFS, s);
-    hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
-                       frontier, frontier_len, level, parent, nl, cur_level_dev, ws);
-    hipLaunchKernelGGL(k_bfs_huge, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, level,
-                       parent, nl, cur_level_dev, ws);
+    const BfsVisit vis{ws, level, parent, nl, cur_level_dev};
+    hipLaunchKernelGGL(k_bfs_expand<BfsVisit>, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
+                       frontier, frontier_len, vis, ws);
+    hipLaunchKernelGGL(k_bfs_huge<BfsVisit>, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, vis, ws);
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.nchunks), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws, next_len);
     hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next);
@@ -324,7 +353,8 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
 // complement of the visited list, in the paper's algorithm with compression
 // integrated), on one GPU.  The vertex range is split by bounds[0..R] into R
 // owners.  Owner p's frontier vertices (those in [bounds[p], bounds[p+1]))
-// expand into owner p's candidate bitmap, visited or not; the R bitmaps are
+// expand into owner p's candidate bitmap, visited or not (the expansion
+// kernels of a BFS level, with the candidate visitor); the R bitmaps are
 // compacted as one, in key order p*V + w, which is the order of the
 // segments (p, d) of the batch; the receiver ORs every decoded candidate
 // into one bitmap and keeps what is not yet visited.
@@ -340,7 +370,7 @@ struct ExWs {
     uint32_t words;  // V/32 (rounded up)
 };
 
-static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint32_t nseg, size_t *bytes) {
+static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, uint32_t nseg, size_t *bytes) {
     ExWs w;
     char *b = (char *)ws;
     size_t off = 0;
@@ -355,10 +385,11 @@ static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint32_t nseg, size_t *byt
     w.cb.nchunks = (uint32_t)((cw + kCompactWords - 1) / kCompactWords);
     w.cb.chunk = (uint32_t *)(b + off);
     off = align256(off + ((size_t)w.cb.nchunks + 1) * 4);
-    w.cb.qcount = (uint32_t *)(b + off);  // written by the compaction scan, unused here
+    w.cb.qcap = (uint32_t)(n_arcs / kHugeChunk + n_arcs / kHuge + 16);
+    w.cb.qcount = (uint32_t *)(b + off);  // the expansion's queue of huge vertices
     off = align256(off + 16);
-    w.cb.queue = nullptr;
-    w.cb.qcap = 0;
+    w.cb.queue = (uint4 *)(b + off);
+    off = align256(off + (size_t)w.cb.qcap * 16);
     w.keyb = (uint32_t *)(b + off);
     off = align256(off + ((size_t)nseg * nseg + 1) * 4);
     w.count = (uint32_t *)(b + off);
@@ -367,9 +398,9 @@ static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint32_t nseg, size_t *byt
     return w;
 }
 
-size_t ex_ws_bytes(uint32_t V, uint32_t nseg) {
+size_t ex_ws_bytes(uint32_t V, uint64_t n_arcs, uint32_t nseg) {
     size_t bytes;
-    ex_ws_layout(nullptr, V, nseg, &bytes);
+    ex_ws_layout(nullptr, V, n_arcs, nseg, &bytes);
     return bytes;
 }
 
@@ -392,53 +423,6 @@ __global__ void k_ex_keyb(const uint32_t *bounds, uint32_t R, uint32_t V, uint32
         bool ok = bounds[0] == 0 && bounds[R] == V;
         for (uint32_t r = 0; r < R; ++r) ok = ok && bounds[r] <= bounds[r + 1];
         if (!ok) raise_err(err, kErrInval);
-    }
-}
-
-// Every arc (u, w) of a frontier vertex u of owner p sets bit w of owner p's
-// bitmap.  A wave takes 64 consecutive frontier vertices and walks their
-// concatenated adjacency lists 64 arcs at a time (lane k: arc k, its vertex
-// found by a binary search over the degree prefix sums in LDS).
-__global__ __launch_bounds__(256) void k_ex_expand(const uint64_t *row_ptr, const uint32_t *col_idx,
-                                                   const uint32_t *frontier, const uint32_t *flen,
-                                                   const uint32_t *bounds, uint32_t R, uint32_t words,
-                                                   uint32_t *cand) {
-    __shared__ uint64_t s_beg[4][64];
-    __shared__ uint32_t s_cum[4][64];
-    __shared__ uint32_t s_own[4][64];
-    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint64_t n = *flen;
-    for (uint64_t base = ((uint64_t)blockIdx.x * 4 + w) * 64; base < n; base += (uint64_t)gridDim.x * 256) {
-        const uint64_t i = base + lane;
-        uint32_t deg = 0, own = 0;
-        uint64_t beg = 0;
-        if (i < n) {
-            const uint32_t u = frontier[i];
-            beg = row_ptr[u];
-            deg = (uint32_t)(row_ptr[u + 1] - beg);
-            own = upper_bound_m1(bounds, R, u);
-        }
-        const uint32_t incl = wave_incl_scan(deg);
-        const uint32_t total = readlane(incl, 63);
-        s_beg[w][lane] = beg;
-        s_cum[w][lane] = incl - deg;
-        s_own[w][lane] = own;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (uint32_t k = lane; k < total; k += 64) {
-            // the last vertex whose arcs start at or before arc k (vertices
-            // without arcs share their start with the next one)
-            uint32_t lo = 0, hi = 64;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_cum[w][mid] <= k) lo = mid;
-                else hi = mid;
-            }
-            const uint32_t x = col_idx[s_beg[w][lo] + (k - s_cum[w][lo])];
-            atomicOr(&cand[(uint64_t)s_own[w][lo] * words + (x >> 5)], 1u << (x & 31));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -492,12 +476,32 @@ __global__ void k_ex_finish(uint32_t *ids, const uint32_t *count, uint32_t S, co
 }
 
 // Receiver: every decoded candidate into one bitmap (IDs outside [0, V) are
-// ignored: a damaged stream is reported by the decoder).
-__global__ void k_ex_merge(const uint32_t *ids, const uint64_t *n_dev, uint32_t V, uint32_t *merged) {
+// ignored: a damaged stream is reported by the decoder).  The segments are
+// sorted, so neighbouring lanes mostly hit the same word: lanes first OR
+// their bits over runs of equal words (a segmented scan across the wave) and
+// only the last lane of a run issues the atomic.  Lanes combine only bits of
+// their own word, and every lane's bits reach the last lane of its run.
+__global__ __launch_bounds__(256) void k_ex_merge(const uint32_t *ids, const uint64_t *n_dev, uint32_t V,
+                                                  uint32_t *merged) {
     const uint64_t n = *n_dev, stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t w = ids[i];
-        if (w < V) atomicOr(&merged[w >> 5], 1u << (w & 31));
+    const int lane = (int)(threadIdx.x & 63);
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {  // wave-uniform
+        const uint64_t i = base + threadIdx.x;
+        uint32_t wd = 0xFFFFFFFFu, bits = 0u;  // no valid word is all ones (V < 2^31)
+        if (i < n) {
+            const uint32_t w = ids[i];
+            if (w < V) {
+                wd = w >> 5;
+                bits = 1u << (w & 31);
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ow = (uint32_t)__shfl_up((int)wd, d, 64), ob = (uint32_t)__shfl_up((int)bits, d, 64);
+            if (lane >= d && ow == wd) bits |= ob;
+        }
+        const uint32_t nw = (uint32_t)__shfl_down((int)wd, 1, 64);
+        if (bits && (lane == 63 || nw != wd)) atomicOr(&merged[wd], bits);
     }
 }
 
@@ -523,11 +527,12 @@ __global__ void k_ex_filter(uint32_t *merged, BfsWs ws, int32_t *level, int32_t 
     }
 }
 
-int launch_ex_init(bfsc_ctx *ctx, uint32_t V, uint32_t nseg, void *wsp, hipStream_t s) {
-    ExWs ws = ex_ws_layout(wsp, V, nseg, nullptr);
+int launch_ex_init(bfsc_ctx *ctx, uint32_t V, uint64_t n_arcs, uint32_t nseg, void *wsp, hipStream_t s) {
+    ExWs ws = ex_ws_layout(wsp, V, n_arcs, nseg, nullptr);
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     hipLaunchKernelGGL(k_ex_zero, dim3(grid), dim3(256), 0, s, ws.cb.next_bm, (uint64_t)ws.cb.words);
     hipLaunchKernelGGL(k_ex_zero, dim3(grid), dim3(256), 0, s, ws.merged, (uint64_t)ws.words);
+    hipLaunchKernelGGL(k_ex_zero, dim3(1), dim3(64), 0, s, ws.cb.qcount, (uint64_t)4);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -535,13 +540,15 @@ int launch_candidates(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *frontier
                       const uint32_t *bounds, uint32_t nseg, uint32_t *ids, uint64_t cap, uint64_t *seg_off,
                       uint32_t *seg_lo, uint32_t *seg_hi, void *wsp, hipStream_t s) {
     const uint32_t V = g->n_vertices;
-    ExWs ws = ex_ws_layout(wsp, V, nseg, nullptr);
+    ExWs ws = ex_ws_layout(wsp, V, g->n_arcs, nseg, nullptr);
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     const uint32_t S = ws.words * 32;
     hipLaunchKernelGGL(k_ex_keyb, dim3((nseg * nseg + 255) / 256), dim3(256), 0, s, bounds, nseg, V, S, ws.keyb,
                        ctx->err);
-    hipLaunchKernelGGL(k_ex_expand, dim3(grid), dim3(256), 0, s, g->row_ptr, g->col_idx, frontier, frontier_len,
-                       bounds, nseg, ws.words, ws.cb.next_bm);
+    const CandVisit vis{bounds, nseg, ws.words, ws.cb.next_bm};
+    hipLaunchKernelGGL(k_bfs_expand<CandVisit>, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
+                       frontier, frontier_len, vis, ws.cb);
+    hipLaunchKernelGGL(k_bfs_huge<CandVisit>, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, vis, ws.cb);
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws.cb, ws.count);
     hipLaunchKernelGGL(k_ex_emit, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb, ids, cap);
@@ -558,7 +565,7 @@ int launch_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, con
                         void *wsp, hipStream_t s) {
     const uint32_t V = g->n_vertices;
     BfsWs bws = bfs_ws_layout(bfs_wsp, V, g->n_arcs, nullptr);
-    ExWs ws = ex_ws_layout(wsp, V, 1, nullptr);  // the merge bitmap's place does not depend on R
+    ExWs ws = ex_ws_layout(wsp, V, g->n_arcs, 1, nullptr);  // the merge bitmap's place does not depend on R
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     hipLaunchKernelGGL(k_ex_merge, dim3(grid), dim3(256), 0, s, ids, n_dev, V, ws.merged);
     hipLaunchKernelGGL(k_ex_filter, dim3(grid), dim3(256), 0, s, ws.merged, bws, level, cur_level + 1);

@@ -175,14 +175,14 @@ static bool ex_ok(const bfsc_csr *g, uint32_t nseg) {
 
 int bfsc_exchange_workspace_size(const bfsc_csr *g, uint32_t nseg, size_t *bytes) {
     if (!bytes || !ex_ok(g, nseg)) return BFSC_E_INVAL;
-    *bytes = ex_ws_bytes(g->n_vertices, nseg);
+    *bytes = ex_ws_bytes(g->n_vertices, g->n_arcs, nseg);
     return BFSC_OK;
 }
 
 int bfsc_exchange_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t nseg, void *ws, void *stream) {
     if (!ctx || !ws || !ex_ok(g, nseg)) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
-    return launch_ex_init(ctx, g->n_vertices, nseg, ws, S(stream));
+    return launch_ex_init(ctx, g->n_vertices, g->n_arcs, nseg, ws, S(stream));
 }
 
 int bfsc_candidates(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *frontier, const uint32_t *frontier_len_dev,
