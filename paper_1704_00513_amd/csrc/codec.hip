@@ -1777,18 +1777,13 @@ __device__ __forceinline__ void decode_block(const uint32_t *buf, uint32_t bw, u
 }
 
 // A block's payload words (wc of them, at word o of the segment's payload
-// area, availw words long) into lane / 64+lane.  When 128 words from o lie
-// inside the area the loads go unmasked (the words past wc are never taken
-// as payload); near its end only the block's own words are read.
-__device__ __forceinline__ void load_payload(const uint32_t *pay, uint32_t o, uint32_t wc, uint64_t availw,
-                                             uint32_t lane, uint32_t &x, uint32_t &y) {
-    if ((uint64_t)o + kBlock <= availw) {
-        x = pay[o + lane];
-        y = pay[o + 64 + lane];
-    } else {
-        x = lane < wc ? pay[o + lane] : 0u;
-        y = lane + 64 < wc ? pay[o + 64 + lane] : 0u;
-    }
+// area) into lane / 64+lane.  Only the block's own words are read: reading
+// whole 512-byte windows pulled the next units' lines into this XCD's L2 as
+// well: over twice the stream's bytes in fetches.
+__device__ __forceinline__ void load_payload(const uint32_t *pay, uint32_t o, uint32_t wc, uint32_t lane,
+                                             uint32_t &x, uint32_t &y) {
+    x = lane < wc ? pay[o + lane] : 0u;
+    y = lane + 64 < wc ? pay[o + 64 + lane] : 0u;
 }
 
 // A full unit (8 blocks of 128 IDs) decoded in two passes of four blocks,
@@ -2053,7 +2048,7 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
         } else {
-            load_payload(pay, ub, readlane(words, hb), availw, lane, pa, pb);
+            load_payload(pay, ub, readlane(words, hb), lane, pa, pb);
         }
         for (uint32_t kk = 0; kk < nblk; ++kk) {
             const uint32_t j = hb + kk, k = k0 + j;
@@ -2064,7 +2059,7 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
                 buf = win + (readlane(off, j) - ub);
             } else {
                 uint32_t na = 0, nbw = 0;
-                if (kk + 1 < nblk) load_payload(pay, readlane(off, j + 1), readlane(words, j + 1), availw, lane, na, nbw);
+                if (kk + 1 < nblk) load_payload(pay, readlane(off, j + 1), readlane(words, j + 1), lane, na, nbw);
                 win[lane] = pa;
                 win[lane + 64] = pb;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2239,14 +2234,14 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_decode_r(DecArgs a) {
             __builtin_amdgcn_wave_barrier();
         } else if (U.kind == 2) {
             uint32_t pa = 0, pb = 0;
-            load_payload(U.pay, U.ub, readlane(U.words, U.hb), U.availw, lane, pa, pb);
+            load_payload(U.pay, U.ub, readlane(U.words, U.hb), lane, pa, pb);
             for (uint32_t kk = 0; kk < U.nblk; ++kk) {
                 const uint32_t j = U.hb + kk, k = U.k0 + j;
                 const bool has_next = k + 1 < U.nb;
                 const uint32_t nxt = has_next ? U.lo + readlane(U.first, j + 1) : 0u;
                 uint32_t na = 0, nbw = 0;
                 if (kk + 1 < U.nblk)
-                    load_payload(U.pay, readlane(U.off, j + 1), readlane(U.words, j + 1), U.availw, lane, na, nbw);
+                    load_payload(U.pay, readlane(U.off, j + 1), readlane(U.words, j + 1), lane, na, nbw);
                 buf[lane] = pa;
                 buf[lane + 64] = pb;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
