@@ -134,6 +134,8 @@ def main():
                     help="codec choice: exhaustive search, plain minimal width, or the trained "
                          "selector (exhaustive fallback where its choice is invalid)")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--bfs", choices=["do", "td"], default="do",
+                    help="BFS producing the frontiers: direction-optimizing (alpha 14, beta 24) or top-down only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -160,6 +162,8 @@ def main():
                                                     time.time() - t0))
     roots = inputs.roots(g, args.roots, args.seed)
     ctx = P.Context(0)
+    if args.bfs == "do":
+        ctx.bfs_set_direction(14.0, 24.0)
     b, host, bfs = build_batch(ctx, P, torch, g, roots, args.nseg, args.bounds, args.seed)
     N = bfs["n_ids"]
     log("batch: %d IDs in %d segments, %d levels; BFS %.2f ms total" % (N, b.nseg, bfs["bfs_levels"],
@@ -269,7 +273,7 @@ def main():
                      "traffic": traffic,
                      "alg_bytes_per_launch": int(alg_bytes)},
         "enc_dec_alg_frac": round((2 * alg_bytes) / ((enc_avg + dec_avg) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "bfs": {"ms_total": round(bfs["bfs_ms"], 3), "levels": bfs["bfs_levels"],
+        "bfs": {"direction": args.bfs, "ms_total": round(bfs["bfs_ms"], 3), "levels": bfs["bfs_levels"],
                 "GTEPS": round(bfs["edges"] / 2 / (bfs["bfs_ms"] * 1e-3) / 1e9, 3)},
     }
     if args.calib:
@@ -419,6 +423,8 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
                                    "batched_speedup": round(4.0 * N / (ms_step * 1e-3) / 1e9 / pg, 2)}
 
     out["per_level_root0"] = per_level(ctx, P, torch, b, host, mode)
+    if args.bfs == "do":
+        out["bfs_top_down_only"] = bfs_top_down(ctx, P, torch, g, roots, host)
     out["exchange_root0"] = exchange_leg(ctx, P, torch, g, int(roots[0]), host, args.nseg, mode)
     out["mall_cold"] = mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps)
 
@@ -444,6 +450,42 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
         out[key] = {"levels": L, "ms_traversal": round(min(times), 3),
                     "us_per_level": round(1e3 * min(times) / L, 1)}
     return out
+
+
+def bfs_top_down(ctx, P, torch, g, roots, host):
+    """The same traversals with top-down levels only (the frontiers, and so
+    the batch, are the same; checked by level count and frontier sizes)."""
+    V = g.n_vertices
+    dg = P.DeviceGraph.from_host(g)
+    i32 = dict(dtype=torch.int32, device="cuda")
+    level, parent = torch.empty(V, **i32), torch.empty(V, **i32)
+    fa, fb = torch.empty(V, **i32), torch.empty(V, **i32)
+    la, lb = torch.zeros(1, **i32), torch.zeros(1, **i32)
+    ws = ctx.bfs_workspace(dg, key="bfs_td")
+    ctx.bfs_set_direction(0.0, 0.0)
+    sizes, ms, edges = [], 0.0, 0
+    deg = np.diff(g.row_ptr)
+    ctx.timing(True)
+    for root in roots:
+        ctx.bfs_init(dg, int(root), level, parent, fa, la, ws)
+        L = 0
+        while True:
+            n = int(la.item())
+            if n == 0:
+                break
+            sizes.append(n)
+            ctx.bfs_level(dg, L, fa, la, level, parent, fb, lb, ws)
+            fa, fb, la, lb = fb, fa, lb, la
+            L += 1
+        edges += int(deg[level.cpu().numpy() >= 0].sum())
+        ms += ctx.timing_read(P._lib.OP_BFS)[0]
+    ctx.timing(False)
+    ctx.bfs_set_direction(14.0, 24.0)
+    so = host["seg_off"].astype(np.int64)
+    nseg = host["seg_lo"].size // max(1, len(sizes))
+    want = [int(so[(i + 1) * nseg] - so[i * nseg]) for i in range(len(sizes))] if nseg else []
+    assert sizes == want, "top-down frontiers differ from the direction-optimizing ones"
+    return {"ms_total": round(ms, 3), "levels": len(sizes), "GTEPS": round(edges / 2 / (ms * 1e-3) / 1e9, 3)}
 
 
 def per_level(ctx, P, torch, b, host, mode, reps=10):

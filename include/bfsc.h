@@ -151,8 +151,9 @@ int bfsc_destroy(bfsc_ctx *ctx);
 int bfsc_workspace_size(const bfsc_ctx *ctx, int op, uint64_t max_ids, uint32_t nseg,
                         size_t *bytes);
 
-/* Bytes of BFS workspace for graph g (visited and next-level bitmaps, the
- * compaction counters and the queue of high-degree adjacency chunks). */
+/* Bytes of BFS workspace for graph g (visited, next-level and frontier
+ * bitmaps, the compaction counters, the queue of high-degree adjacency
+ * chunks and the direction state). */
 int bfsc_bfs_workspace_size(const bfsc_csr *g, size_t *bytes);
 
 /* Initialises a traversal from `root`: level[] = -1 and parent[] = -1 except
@@ -174,6 +175,20 @@ int bfsc_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *leve
 int bfsc_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const uint32_t *frontier,
                    const uint32_t *frontier_len_dev, int32_t *level, int32_t *parent,
                    uint32_t *next, uint32_t *next_len_dev, void *ws, void *stream);
+
+/* Direction-optimizing levels (the paper's related work, "Direction
+ * optimization": a level may run bottom-up, each unvisited vertex searching
+ * its own neighbours for one on the frontier; Beamer, Asanovic & Patterson,
+ * SC 2012, for the switching rule).  With m_f the frontier's arcs and m_u the
+ * arcs of the unvisited vertices, bfsc_bfs_level runs bottom-up from the
+ * first level where m_f > m_u / alpha while the frontier grows, and top-down
+ * again once the frontier holds fewer than n_vertices / beta vertices while
+ * it shrinks; the choice is made on the device (levels stay capturable).
+ * Levels and frontiers are the same as top-down; parents are any frontier
+ * neighbour.  alpha = 0 (the default): top-down only.  Set it before
+ * bfsc_bfs_init of a traversal.  Returns BFSC_E_INVAL for alpha < 0, or for
+ * alpha > 0 with beta <= 0 (Beamer's values: alpha 14, beta 24). */
+int bfsc_bfs_set_direction(bfsc_ctx *ctx, float alpha, float beta);
 
 /* Splits a sorted frontier ids[0 .. *n_dev) by destination vertex range:
  * seg_off[r] = number of IDs below bounds[r] for r < nseg, seg_off[nseg] =

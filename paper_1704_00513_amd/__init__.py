@@ -210,6 +210,10 @@ class Context:
                                          ptr(nxt), ptr(next_len), ptr(ws), _stream(stream)),
               "bfsc_bfs_level")
 
+    def bfs_set_direction(self, alpha: float = 14.0, beta: float = 24.0):
+        """Direction-optimizing BFS levels (alpha = 0: top-down only)."""
+        check(_lib.load().bfsc_bfs_set_direction(self.h, float(alpha), float(beta)), "bfsc_bfs_set_direction")
+
     def partition(self, ids, n_dev, bounds, seg_off, stream=None):
         check(_lib.load().bfsc_partition(ptr(ids), ptr(n_dev), ptr(bounds), int(bounds.numel()) - 1,
                                          ptr(seg_off), _stream(stream)), "bfsc_partition")

@@ -65,6 +65,7 @@ _SIGS = {
     "bfsc_bfs_workspace_size": [P(CSR), P(sz)],
     "bfsc_bfs_init": [vp, P(CSR), u32, vp, vp, vp, vp, vp, vp],
     "bfsc_bfs_level": [vp, P(CSR), i32, vp, vp, vp, vp, vp, vp, vp, vp],
+    "bfsc_bfs_set_direction": [vp, ctypes.c_float, ctypes.c_float],
     "bfsc_partition": [vp, vp, vp, u32, vp, vp],
     "bfsc_exchange_workspace_size": [P(CSR), u32, P(sz)],
     "bfsc_exchange_init": [vp, P(CSR), u32, vp, vp],

@@ -25,8 +25,15 @@ struct BfsWs {
     uint32_t *chunk;     // [nchunks + 1] counts then offsets
     uint32_t *qcount;    // [4] huge queue count
     uint4 *queue;        // huge chunks {u, start_lo, start_hi, len}
+    uint32_t *front_bm;  // V/32 words: the current frontier as a bitmap (bottom-up levels read it)
+    unsigned long long *stat;  // direction state, see k_bfs_decide
     uint32_t words, nchunks, qcap;
 };
+
+// Direction state (stat[]): [0] arcs of the unvisited vertices, [1] the
+// previous frontier's size, [2] this level's direction (0 top-down, 1
+// bottom-up), [3] arcs of the frontier being emitted.
+enum { kStatMu = 0, kStatPrevN = 1, kStatDir = 2, kStatMf = 3 };
 
 static inline BfsWs bfs_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, size_t *bytes) {
     BfsWs w;
@@ -45,6 +52,10 @@ static inline BfsWs bfs_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, size_t 
     off = align256(off + 16);
     w.queue = (uint4 *)(b + off);
     off = align256(off + (size_t)w.qcap * 16);
+    w.front_bm = (uint32_t *)(b + off);
+    off = align256(off + (size_t)w.words * 4);
+    w.stat = (unsigned long long *)(b + off);
+    off = align256(off + 32);
     if (bytes) *bytes = off;
     return w;
 }
@@ -77,9 +88,12 @@ struct BfsVisit {  // a BFS level: the visited filter, level and parent
     int32_t *level, *parent;
     int32_t nl;                // the new level, from the host ...
     const int32_t *level_dev;  // ... or one past the level kept on the device
+    const unsigned long long *dir;  // the level's direction (null: always top-down)
     __device__ void begin() {
         if (level_dev) nl = *level_dev + 1;
     }
+    // false on a bottom-up level: the expansion kernels then do nothing
+    __device__ bool active() const { return !dir || *dir == 0ull; }
     __device__ uint32_t tag(uint32_t u) const { return u; }
     __device__ void operator()(uint32_t w, uint32_t u) const { visit(w, u, nl, ws, level, parent); }
 };
@@ -89,6 +103,7 @@ struct CandVisit {  // the candidate exchange: bit w of the owner's bitmap, visi
     uint32_t R, words;
     uint32_t *cand;  // R bitmaps of `words` words each
     __device__ void begin() {}
+    __device__ bool active() const { return true; }
     __device__ uint32_t tag(uint32_t u) const { return upper_bound_m1(bounds, R, u) * words; }
     __device__ void operator()(uint32_t w, uint32_t base) const {
         uint32_t *p = cand + base + (w >> 5);
@@ -102,6 +117,7 @@ template <class Visit>
 __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
     const uint64_t *row_ptr, const uint32_t *col_idx, const uint32_t *frontier,
     const uint32_t *frontier_len, Visit vis, BfsWs ws) {
+    if (!vis.active()) return;  // uniform over the grid
     vis.begin();
     __shared__ uint32_t s_deg_scan[kExpandThreads];
     __shared__ uint32_t s_u[kExpandThreads];
@@ -200,6 +216,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
 
 template <class Visit>
 __global__ __launch_bounds__(256) void k_bfs_huge(const uint32_t *col_idx, Visit vis, BfsWs ws) {
+    if (!vis.active()) return;
     vis.begin();
     const uint32_t nq = min(*ws.qcount, ws.qcap);
     for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
@@ -256,8 +273,10 @@ __global__ __launch_bounds__(1024) void k_bfs_scan(BfsWs ws, uint32_t *next_len)
     }
 }
 
-// Pass 3: write the set bits' vertex IDs in order and clear the bitmap.
-__global__ __launch_bounds__(256) void k_bfs_emit(BfsWs ws, uint32_t *next) {
+// Pass 3: write the set bits' vertex IDs in order and clear the bitmap; the
+// bitmap becomes the frontier bitmap of the next level.  With row_ptr, the
+// new frontier's arcs are summed for the direction choice.
+__global__ __launch_bounds__(256) void k_bfs_emit(BfsWs ws, uint32_t *next, const uint64_t *row_ptr) {
     __shared__ uint32_t s_wt[4];
     const uint32_t c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const uint32_t w0 = c * kCompactWords + tid * 4;  // 4 consecutive words per thread
@@ -273,15 +292,24 @@ __global__ __launch_bounds__(256) void k_bfs_emit(BfsWs ws, uint32_t *next) {
     uint32_t wb = 0;
     for (uint32_t q = 0; q < (tid >> 6); ++q) wb += s_wt[q];
     uint32_t pos = ws.chunk[c] + wb + incl - cnt;
+    unsigned long long arcs = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         uint32_t v = x[k];
         while (v) {
             const uint32_t b = __builtin_ctz(v);
             v &= v - 1;
-            next[pos++] = (w0 + k) * 32 + b;
+            const uint32_t id = (w0 + k) * 32 + b;
+            next[pos++] = id;
+            if (row_ptr) arcs += row_ptr[id + 1] - row_ptr[id];
         }
         if (x[k]) ws.next_bm[w0 + k] = 0u;
+        if (w0 + k < ws.words) ws.front_bm[w0 + k] = x[k];
+    }
+    if (row_ptr) {  // uniform
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) arcs += __shfl_xor(arcs, o, 64);
+        if (lane == 0 && arcs) atomicAdd(&ws.stat[kStatMf], arcs);
     }
 }
 
@@ -294,17 +322,84 @@ __global__ void k_bfs_fill(int32_t *level, int32_t *parent, uint32_t V, BfsWs ws
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ws.words; i += stride) {
         ws.visited[i] = 0u;
         ws.next_bm[i] = 0u;
+        ws.front_bm[i] = 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *ws.qcount = 0;
 }
 
 __global__ void k_bfs_root(uint32_t root, int32_t *level, int32_t *parent, uint32_t *frontier,
-                           uint32_t *frontier_len, BfsWs ws) {
+                           uint32_t *frontier_len, BfsWs ws, const uint64_t *row_ptr, uint64_t n_arcs) {
     level[root] = 0;
     parent[root] = (int32_t)root;
     ws.visited[root >> 5] |= 1u << (root & 31);
+    ws.front_bm[root >> 5] |= 1u << (root & 31);
     frontier[0] = root;
     *frontier_len = 1;
+    ws.stat[kStatMu] = n_arcs;
+    ws.stat[kStatPrevN] = 0ull;
+    ws.stat[kStatDir] = 0ull;
+    ws.stat[kStatMf] = row_ptr[root + 1] - row_ptr[root];
+}
+
+// Direction of the coming level (direction-optimizing BFS, Beamer, Asanovic
+// and Patterson, SC 2012): with m_f the frontier's arcs and m_u the arcs of
+// the unvisited vertices, a top-down traversal turns bottom-up when
+// m_f > m_u / alpha while the frontier grows, and a bottom-up one turns back
+// when the frontier holds fewer than V / beta vertices while it shrinks.
+__global__ void k_bfs_decide(BfsWs ws, const uint32_t *frontier_len, uint32_t V, float alpha, float beta) {
+    unsigned long long *st = ws.stat;
+    const unsigned long long mf = st[kStatMf];
+    const unsigned long long mu = st[kStatMu] - min(mf, st[kStatMu]);  // the frontier is visited now
+    const unsigned long long nf = *frontier_len, prev = st[kStatPrevN];
+    unsigned long long dir = st[kStatDir];
+    if (dir == 0ull) {
+        if ((double)mf * alpha > (double)mu && nf > prev) dir = 1ull;
+    } else if ((double)nf * beta < (double)V && nf < prev) {
+        dir = 0ull;
+    }
+    st[kStatMu] = mu;
+    st[kStatMf] = 0ull;  // the emit pass sums the next frontier's arcs here
+    st[kStatPrevN] = nf;
+    st[kStatDir] = dir;
+}
+
+// A bottom-up level: every unvisited vertex looks through its own
+// neighbours for one on the frontier (the frontier bitmap) and stops at the
+// first.  A wave owns 64 consecutive vertices, i.e. two bitmap words, so the
+// visited and next-level words are written by one lane without atomics.
+__global__ __launch_bounds__(256) void k_bfs_bu(const uint64_t *row_ptr, const uint32_t *col_idx, int32_t *level,
+                                                int32_t *parent, int32_t nl_host, const int32_t *level_dev,
+                                                BfsWs ws, uint32_t V) {
+    if (ws.stat[kStatDir] == 0ull) return;  // uniform over the grid
+    const int32_t nl = level_dev ? *level_dev + 1 : nl_host;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wv * 64 < V; wv += nwaves) {
+        const uint32_t v = (uint32_t)(wv * 64) + lane;
+        bool found = false;
+        uint32_t par = 0;
+        if (v < V && !((ws.visited[v >> 5] >> (v & 31)) & 1u)) {
+            const uint64_t e1 = row_ptr[v + 1];
+            for (uint64_t e = row_ptr[v]; e < e1; ++e) {
+                const uint32_t u = col_idx[e];
+                if ((ws.front_bm[u >> 5] >> (u & 31)) & 1u) {
+                    found = true;
+                    par = u;
+                    break;
+                }
+            }
+        }
+        if (found) {
+            level[v] = nl;
+            parent[v] = (int32_t)par;
+        }
+        const uint64_t m = ballot(found);
+        const uint32_t wi = (uint32_t)(wv * 2) + (lane >> 5), bits = lane < 32 ? (uint32_t)m : (uint32_t)(m >> 32);
+        if ((lane & 31) == 0 && bits) {
+            ws.visited[wi] |= bits;
+            ws.next_bm[wi] = bits;  // cleared by the previous emit pass
+        }
+    }
 }
 
 int launch_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *level,
@@ -314,7 +409,7 @@ int launch_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *le
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     hipLaunchKernelGGL(k_bfs_fill, dim3(grid), dim3(256), 0, s, level, parent, g->n_vertices, ws);
     hipLaunchKernelGGL(k_bfs_root, dim3(1), dim3(1), 0, s, root, level, parent, frontier,
-                       frontier_len, ws);
+                       frontier_len, ws, g->row_ptr, g->n_arcs);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -335,13 +430,20 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
     const int32_t nl = cur_level + 1;
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     const int slot = timing_begin(ctx, BFSC_OP_BFS, s);
-    const BfsVisit vis{ws, level, parent, nl, cur_level_dev};
+    const bool dopt = ctx->bfs_alpha > 0.f;
+    if (dopt)
+        hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(1), 0, s, ws, frontier_len, g->n_vertices, ctx->bfs_alpha,
+                           ctx->bfs_beta);
+    const BfsVisit vis{ws, level, parent, nl, cur_level_dev, dopt ? ws.stat + kStatDir : nullptr};
     hipLaunchKernelGGL(k_bfs_expand<BfsVisit>, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
                        frontier, frontier_len, vis, ws);
     hipLaunchKernelGGL(k_bfs_huge<BfsVisit>, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, vis, ws);
+    if (dopt)
+        hipLaunchKernelGGL(k_bfs_bu, dim3(grid), dim3(256), 0, s, g->row_ptr, g->col_idx, level, parent, nl,
+                           cur_level_dev, ws, g->n_vertices);
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.nchunks), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws, next_len);
-    hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next);
+    hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next, dopt ? g->row_ptr : nullptr);
     timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
@@ -390,6 +492,8 @@ static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, uint32_t 
     off = align256(off + 16);
     w.cb.queue = (uint4 *)(b + off);
     off = align256(off + (size_t)w.cb.qcap * 16);
+    w.cb.front_bm = nullptr;  // the candidate compaction uses k_ex_emit, which has no frontier bitmap
+    w.cb.stat = nullptr;
     w.keyb = (uint32_t *)(b + off);
     off = align256(off + ((size_t)nseg * nseg + 1) * 4);
     w.count = (uint32_t *)(b + off);
@@ -571,7 +675,7 @@ int launch_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, con
     hipLaunchKernelGGL(k_ex_filter, dim3(grid), dim3(256), 0, s, ws.merged, bws, level, cur_level + 1);
     hipLaunchKernelGGL(k_bfs_count, dim3(bws.nchunks), dim3(256), 0, s, bws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, bws, next_len);
-    hipLaunchKernelGGL(k_bfs_emit, dim3(bws.nchunks), dim3(256), 0, s, bws, next);
+    hipLaunchKernelGGL(k_bfs_emit, dim3(bws.nchunks), dim3(256), 0, s, bws, next, (const uint64_t *)nullptr);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 

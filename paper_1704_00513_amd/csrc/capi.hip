@@ -167,6 +167,13 @@ int bfsc_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const ui
                             next_len_dev, ws, S(stream));
 }
 
+int bfsc_bfs_set_direction(bfsc_ctx *ctx, float alpha, float beta) {
+    if (!ctx || !(alpha >= 0.f) || (alpha > 0.f && !(beta > 0.f))) return BFSC_E_INVAL;
+    ctx->bfs_alpha = alpha;
+    ctx->bfs_beta = beta;
+    return BFSC_OK;
+}
+
 // keys p*V + w of the candidate exchange must fit 32 bits
 static bool ex_ok(const bfsc_csr *g, uint32_t nseg) {
     return g && g->n_vertices > 0 && g->n_vertices <= 0x7FFFFFFFu && nseg > 0 &&

@@ -236,6 +236,8 @@ struct bfsc_ctx {
     int timed_op[4096];
     hipEvent_t ev_a[4096], ev_b[4096];
     uint32_t ev_created;
+    // direction-optimizing BFS (bfsc_bfs_set_direction); alpha 0: top-down only
+    float bfs_alpha, bfs_beta;
 };
 
 namespace bfsc {
