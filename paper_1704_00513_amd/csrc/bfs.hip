@@ -5,18 +5,19 @@
 // vertex list without sorting: winners mark a next-level bitmap, which is
 // compacted in vertex order.
 //
-// Load balance: each workgroup takes 256 frontier vertices; high-degree
-// vertices are expanded by the whole wave (64 <= deg < 2048) or workgroup
-// (2048 <= deg < 16384), the rest by a workgroup-wide gather over the
-// concatenated small adjacency lists; vertices of degree >= 16384 are cut
-// into 8192-edge chunks and queued for a second, grid-wide kernel.
+// Load balance: each workgroup takes 256 frontier vertices; vertices of
+// degree 64 <= deg < 512 are expanded by the whole wave, the rest by a
+// workgroup-wide gather over the concatenated small adjacency lists;
+// vertices of degree >= 512 are cut into 2048-edge chunks and queued for a
+// second, grid-wide kernel (a small frontier of hubs then still fills the
+// chip).
 #include "common.hpp"
 #include "exchange.hpp"
 
 namespace bfsc {
 
 constexpr uint32_t kExpandThreads = 256;
-constexpr uint32_t kMedium = 64, kLarge = 2048, kHuge = 16384, kHugeChunk = 8192;
+constexpr uint32_t kMedium = 64, kHuge = 512, kHugeChunk = 2048;
 constexpr uint32_t kCompactWords = 1024;  // bitmap words per compaction chunk
 
 struct BfsWs {
@@ -123,9 +124,6 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
     __shared__ uint32_t s_u[kExpandThreads];
     __shared__ uint64_t s_start[kExpandThreads];
     __shared__ uint32_t s_total;
-    __shared__ uint32_t s_big_u, s_big_len;
-    __shared__ uint64_t s_big_start;
-    __shared__ int s_big_owner;
     const uint32_t tid = threadIdx.x, lane = tid & 63;
     const uint32_t n = *frontier_len;
     for (uint64_t base = (uint64_t)blockIdx.x * kExpandThreads; base < n;
@@ -139,38 +137,24 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
             deg = (uint32_t)(row_ptr[f + 1] - start);
             u = vis.tag(f);
         }
-        // huge: queue 8192-edge chunks for the grid-wide pass
-        if (deg >= kHuge) {
-            const uint32_t nch = (deg + kHugeChunk - 1) / kHugeChunk;
-            const uint32_t q = atomicAdd(ws.qcount, nch);
-            for (uint32_t c = 0; c < nch; ++c) {
-                if (q + c < ws.qcap) {
-                    const uint64_t s = start + (uint64_t)c * kHugeChunk;
-                    const uint32_t len = min(kHugeChunk, deg - c * kHugeChunk);
-                    ws.queue[q + c] = make_uint4(u, (uint32_t)s, (uint32_t)(s >> 32), len);
+        // huge: queue 2048-edge chunks for the grid-wide pass, one atomic per wave
+        {
+            const uint32_t nch = deg >= kHuge ? (deg + kHugeChunk - 1) / kHugeChunk : 0u;
+            const uint32_t cincl = wave_incl_scan(nch);
+            const uint32_t ctot = readlane(cincl, 63);
+            if (ctot) {  // uniform over the wave
+                uint32_t qb = 0;
+                if (lane == 0) qb = atomicAdd(ws.qcount, ctot);
+                const uint32_t q = readlane(qb, 0) + cincl - nch;
+                for (uint32_t c = 0; c < nch; ++c) {
+                    if (q + c < ws.qcap) {  // never false: qcap bounds the chunks of distinct vertices
+                        const uint64_t s = start + (uint64_t)c * kHugeChunk;
+                        const uint32_t len = min(kHugeChunk, deg - c * kHugeChunk);
+                        ws.queue[q + c] = make_uint4(u, (uint32_t)s, (uint32_t)(s >> 32), len);
+                    }
                 }
+                if (nch) deg = 0;
             }
-            deg = 0;
-        }
-        // large: whole workgroup, one vertex at a time
-        for (;;) {
-            if (tid == 0) s_big_owner = -1;
-            __syncthreads();
-            if (deg >= kLarge) s_big_owner = (int)tid;  // any writer wins
-            __syncthreads();
-            const int owner = s_big_owner;
-            if (owner < 0) break;
-            if ((int)tid == owner) {
-                s_big_u = u;
-                s_big_start = start;
-                s_big_len = deg;
-                deg = 0;
-            }
-            __syncthreads();
-            const uint32_t bu = s_big_u, blen = s_big_len;
-            const uint64_t bs = s_big_start;
-            for (uint32_t e = tid; e < blen; e += kExpandThreads) vis(col_idx[bs + e], bu);
-            __syncthreads();
         }
         // medium: whole wave, one vertex at a time
         for (;;) {
