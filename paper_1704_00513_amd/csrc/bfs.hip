@@ -6,18 +6,17 @@
 // compacted in vertex order.
 //
 // Load balance: each workgroup takes 256 frontier vertices; vertices of
-// degree 64 <= deg < 512 are expanded by the whole wave, the rest by a
-// workgroup-wide gather over the concatenated small adjacency lists;
-// vertices of degree >= 512 are cut into 2048-edge chunks and queued for a
-// second, grid-wide kernel (a small frontier of hubs then still fills the
-// chip).
+// degree < 512 are expanded by a workgroup-wide gather over their
+// concatenated adjacency lists; vertices of degree >= 512 are cut into
+// 2048-edge chunks and queued for a second, grid-wide kernel (a small
+// frontier of hubs then still fills the chip).
 #include "common.hpp"
 #include "exchange.hpp"
 
 namespace bfsc {
 
 constexpr uint32_t kExpandThreads = 256;
-constexpr uint32_t kMedium = 64, kHuge = 512, kHugeChunk = 2048;
+constexpr uint32_t kHuge = 512, kHugeChunk = 2048;
 constexpr uint32_t kCompactWords = 1024;  // bitmap words per compaction chunk
 
 struct BfsWs {
@@ -156,18 +155,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
                 if (nch) deg = 0;
             }
         }
-        // medium: whole wave, one vertex at a time
-        for (;;) {
-            const uint64_t m = ballot(deg >= kMedium);
-            if (!m) break;
-            const uint32_t src = (uint32_t)__builtin_ctzll(m);
-            const uint32_t mu = readlane(u, src), mlen = readlane(deg, src);
-            const uint64_t ms = ((uint64_t)readlane((uint32_t)(start >> 32), src) << 32) |
-                                readlane((uint32_t)start, src);
-            if (lane == src) deg = 0;
-            for (uint32_t e = lane; e < mlen; e += 64) vis(col_idx[ms + e], mu);
-        }
-        // small: gather over the concatenated lists
+        // the rest: a workgroup-wide gather over the concatenated lists
         uint32_t tot;
         {
             // workgroup exclusive scan of deg (4 waves)
@@ -185,14 +173,27 @@ __global__ __launch_bounds__(kExpandThreads) void k_bfs_expand(
         }
         __syncthreads();
         tot = s_total;
-        for (uint32_t e = tid; e < tot; e += kExpandThreads) {
-            // owner: last thread whose scan start <= e
-            uint32_t lo = 0, hi = kExpandThreads;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_deg_scan[mid] <= e) lo = mid; else hi = mid;
+        // four arcs per thread per step, their loads issued together
+        for (uint32_t e0 = tid; e0 < tot; e0 += 4 * kExpandThreads) {
+            uint32_t x[4], tg[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t e = e0 + k * kExpandThreads;
+                x[k] = 0u;
+                tg[k] = 0u;
+                if (e < tot) {
+                    // owner: the last thread whose scan start is <= e
+                    uint32_t lo = 0;
+#pragma unroll
+                    for (uint32_t st = kExpandThreads / 2; st > 0; st >>= 1)
+                        if (s_deg_scan[lo + st] <= e) lo += st;
+                    tg[k] = s_u[lo];
+                    x[k] = col_idx[s_start[lo] + (e - s_deg_scan[lo])];
+                }
             }
-            vis(col_idx[s_start[lo] + (e - s_deg_scan[lo])], s_u[lo]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (e0 + k * kExpandThreads < tot) vis(x[k], tg[k]);
         }
         __syncthreads();
     }
