@@ -27,8 +27,14 @@ struct BfsWs {
     uint4 *queue;        // huge chunks {u, start_lo, start_hi, len}
     uint32_t *front_bm;  // V/32 words: the current frontier as a bitmap (bottom-up levels read it)
     unsigned long long *stat;  // direction state, see k_bfs_decide
+    unsigned long long *part;  // [kParts] per-workgroup sums of the new frontier's arcs
     uint32_t words, nchunks, qcap;
 };
+
+// Workgroups of the kernels that sum the new frontier's arcs (k_bfs_bu,
+// k_bfs_arcs): each writes its own partial sum, since same-address atomics
+// from every workgroup of the chip serialise.
+constexpr uint32_t kParts = 4096;
 
 // Direction state (stat[]): [0] arcs of the unvisited vertices, [1] the
 // previous frontier's size, [2] this level's direction (0 top-down, 1
@@ -56,6 +62,8 @@ static inline BfsWs bfs_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, size_t 
     off = align256(off + (size_t)w.words * 4);
     w.stat = (unsigned long long *)(b + off);
     off = align256(off + 32);
+    w.part = (unsigned long long *)(b + off);
+    off = align256(off + (size_t)kParts * 8);
     if (bytes) *bytes = off;
     return w;
 }
@@ -259,9 +267,8 @@ __global__ __launch_bounds__(1024) void k_bfs_scan(BfsWs ws, uint32_t *next_len)
 }
 
 // Pass 3: write the set bits' vertex IDs in order and clear the bitmap; the
-// bitmap becomes the frontier bitmap of the next level.  With row_ptr, the
-// new frontier's arcs are summed for the direction choice.
-__global__ __launch_bounds__(256) void k_bfs_emit(BfsWs ws, uint32_t *next, const uint64_t *row_ptr) {
+// bitmap becomes the frontier bitmap of the next level.
+__global__ __launch_bounds__(256) void k_bfs_emit(BfsWs ws, uint32_t *next) {
     __shared__ uint32_t s_wt[4];
     const uint32_t c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const uint32_t w0 = c * kCompactWords + tid * 4;  // 4 consecutive words per thread
@@ -277,25 +284,43 @@ __global__ __launch_bounds__(256) void k_bfs_emit(BfsWs ws, uint32_t *next, cons
     uint32_t wb = 0;
     for (uint32_t q = 0; q < (tid >> 6); ++q) wb += s_wt[q];
     uint32_t pos = ws.chunk[c] + wb + incl - cnt;
-    unsigned long long arcs = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         uint32_t v = x[k];
         while (v) {
             const uint32_t b = __builtin_ctz(v);
             v &= v - 1;
-            const uint32_t id = (w0 + k) * 32 + b;
-            next[pos++] = id;
-            if (row_ptr) arcs += row_ptr[id + 1] - row_ptr[id];
+            next[pos++] = (w0 + k) * 32 + b;
         }
         if (x[k]) ws.next_bm[w0 + k] = 0u;
         if (w0 + k < ws.words) ws.front_bm[w0 + k] = x[k];
     }
-    if (row_ptr) {  // uniform
+}
+
+// Sum over a 256-thread workgroup (every thread calls it).
+__device__ __forceinline__ unsigned long long block_sum64(unsigned long long x) {
+    __shared__ unsigned long long s_w[4];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) arcs += __shfl_xor(arcs, o, 64);
-        if (lane == 0 && arcs) atomicAdd(&ws.stat[kStatMf], arcs);
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// The new frontier's arcs after a top-down level, summed for the direction
+// choice of the next level (one ID per thread, a partial sum per workgroup);
+// a bottom-up level sums its winners' arcs itself.
+__global__ __launch_bounds__(256) void k_bfs_arcs(const uint32_t *next, const uint32_t *next_len,
+                                                  const uint64_t *row_ptr, BfsWs ws) {
+    if (ws.stat[kStatDir] != 0ull) return;  // uniform over the grid
+    const uint32_t n = *next_len;
+    unsigned long long arcs = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t v = next[i];
+        arcs += row_ptr[v + 1] - row_ptr[v];
     }
+    arcs = block_sum64(arcs);
+    if (threadIdx.x == 0) ws.part[blockIdx.x] = arcs;
 }
 
 __global__ void k_bfs_fill(int32_t *level, int32_t *parent, uint32_t V, BfsWs ws) {
@@ -309,6 +334,7 @@ __global__ void k_bfs_fill(int32_t *level, int32_t *parent, uint32_t V, BfsWs ws
         ws.next_bm[i] = 0u;
         ws.front_bm[i] = 0u;
     }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kParts; i += stride) ws.part[i] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) *ws.qcount = 0;
 }
 
@@ -331,9 +357,16 @@ __global__ void k_bfs_root(uint32_t root, int32_t *level, int32_t *parent, uint3
 // the unvisited vertices, a top-down traversal turns bottom-up when
 // m_f > m_u / alpha while the frontier grows, and a bottom-up one turns back
 // when the frontier holds fewer than V / beta vertices while it shrinks.
-__global__ void k_bfs_decide(BfsWs ws, const uint32_t *frontier_len, uint32_t V, float alpha, float beta) {
+// One workgroup of 256 threads: it first adds up the partial sums of the
+// new frontier's arcs left by the previous level (nparts of them).
+__global__ __launch_bounds__(256) void k_bfs_decide(BfsWs ws, const uint32_t *frontier_len, uint32_t V,
+                                                    float alpha, float beta, uint32_t nparts) {
+    unsigned long long part = 0;
+    for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) part += ws.part[i];
+    part = block_sum64(part);
+    if (threadIdx.x != 0) return;
     unsigned long long *st = ws.stat;
-    const unsigned long long mf = st[kStatMf];
+    const unsigned long long mf = st[kStatMf] + part;
     const unsigned long long mu = st[kStatMu] - min(mf, st[kStatMu]);  // the frontier is visited now
     const unsigned long long nf = *frontier_len, prev = st[kStatPrevN];
     unsigned long long dir = st[kStatDir];
@@ -343,7 +376,7 @@ __global__ void k_bfs_decide(BfsWs ws, const uint32_t *frontier_len, uint32_t V,
         dir = 0ull;
     }
     st[kStatMu] = mu;
-    st[kStatMf] = 0ull;  // the emit pass sums the next frontier's arcs here
+    st[kStatMf] = 0ull;  // only the root's arcs come this way
     st[kStatPrevN] = nf;
     st[kStatDir] = dir;
 }
@@ -359,17 +392,19 @@ __global__ __launch_bounds__(256) void k_bfs_bu(const uint64_t *row_ptr, const u
     const int32_t nl = level_dev ? *level_dev + 1 : nl_host;
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned long long acc = 0;  // the winners' arcs, for the next direction choice
     for (uint64_t wv = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wv * 64 < V; wv += nwaves) {
         const uint32_t v = (uint32_t)(wv * 64) + lane;
         bool found = false;
         uint32_t par = 0;
         if (v < V && !((ws.visited[v >> 5] >> (v & 31)) & 1u)) {
-            const uint64_t e1 = row_ptr[v + 1];
-            for (uint64_t e = row_ptr[v]; e < e1; ++e) {
+            const uint64_t e0 = row_ptr[v], e1 = row_ptr[v + 1];
+            for (uint64_t e = e0; e < e1; ++e) {
                 const uint32_t u = col_idx[e];
                 if ((ws.front_bm[u >> 5] >> (u & 31)) & 1u) {
                     found = true;
                     par = u;
+                    acc += e1 - e0;
                     break;
                 }
             }
@@ -385,6 +420,8 @@ __global__ __launch_bounds__(256) void k_bfs_bu(const uint64_t *row_ptr, const u
             ws.next_bm[wi] = bits;  // cleared by the previous emit pass
         }
     }
+    acc = block_sum64(acc);
+    if (threadIdx.x == 0) ws.part[blockIdx.x] = acc;
 }
 
 int launch_bfs_init(bfsc_ctx *ctx, const bfsc_csr *g, uint32_t root, int32_t *level,
@@ -416,19 +453,24 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
     const int slot = timing_begin(ctx, BFSC_OP_BFS, s);
     const bool dopt = ctx->bfs_alpha > 0.f;
+    // k_bfs_bu and k_bfs_arcs run on the same grid, so whichever ran last
+    // level wrote every partial sum that k_bfs_decide adds up
+    const uint32_t dgrid = min(grid, kParts);
     if (dopt)
-        hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(1), 0, s, ws, frontier_len, g->n_vertices, ctx->bfs_alpha,
-                           ctx->bfs_beta);
+        hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(256), 0, s, ws, frontier_len, g->n_vertices, ctx->bfs_alpha,
+                           ctx->bfs_beta, dgrid);
     const BfsVisit vis{ws, level, parent, nl, cur_level_dev, dopt ? ws.stat + kStatDir : nullptr};
     hipLaunchKernelGGL(k_bfs_expand<BfsVisit>, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
                        frontier, frontier_len, vis, ws);
     hipLaunchKernelGGL(k_bfs_huge<BfsVisit>, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, vis, ws);
     if (dopt)
-        hipLaunchKernelGGL(k_bfs_bu, dim3(grid), dim3(256), 0, s, g->row_ptr, g->col_idx, level, parent, nl,
+        hipLaunchKernelGGL(k_bfs_bu, dim3(dgrid), dim3(256), 0, s, g->row_ptr, g->col_idx, level, parent, nl,
                            cur_level_dev, ws, g->n_vertices);
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.nchunks), dim3(256), 0, s, ws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws, next_len);
-    hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next, dopt ? g->row_ptr : nullptr);
+    hipLaunchKernelGGL(k_bfs_emit, dim3(ws.nchunks), dim3(256), 0, s, ws, next);
+    if (dopt)
+        hipLaunchKernelGGL(k_bfs_arcs, dim3(dgrid), dim3(256), 0, s, next, next_len, g->row_ptr, ws);
     timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
@@ -479,6 +521,7 @@ static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, uint32_t 
     off = align256(off + (size_t)w.cb.qcap * 16);
     w.cb.front_bm = nullptr;  // the candidate compaction uses k_ex_emit, which has no frontier bitmap
     w.cb.stat = nullptr;
+    w.cb.part = nullptr;
     w.keyb = (uint32_t *)(b + off);
     off = align256(off + ((size_t)nseg * nseg + 1) * 4);
     w.count = (uint32_t *)(b + off);
@@ -660,7 +703,7 @@ int launch_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, con
     hipLaunchKernelGGL(k_ex_filter, dim3(grid), dim3(256), 0, s, ws.merged, bws, level, cur_level + 1);
     hipLaunchKernelGGL(k_bfs_count, dim3(bws.nchunks), dim3(256), 0, s, bws);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, bws, next_len);
-    hipLaunchKernelGGL(k_bfs_emit, dim3(bws.nchunks), dim3(256), 0, s, bws, next, (const uint64_t *)nullptr);
+    hipLaunchKernelGGL(k_bfs_emit, dim3(bws.nchunks), dim3(256), 0, s, bws, next);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
