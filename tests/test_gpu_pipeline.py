@@ -66,6 +66,21 @@ def test_pipeline_levels_exact(ctx, use_graph, kind, scale, nseg, zipf):
         run_pipeline(ctx, g, int(root), bounds, use_graph)
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("alpha,beta", [(14.0, 24.0), (1e9, 1e9)])
+def test_pipeline_direction_optimizing(ctx, use_graph, alpha, beta):
+    """Direction-optimizing levels inside the captured pipeline: the
+    direction is decided on the device at every replay."""
+    g = inputs.graph(inputs.RMAT, 15, 16, 3)
+    ctx.bfs_set_direction(alpha, beta)
+    try:
+        for root in inputs.roots(g, 2, 3):
+            print("pipeline-do graph=%s alpha=%g root=%d" % (use_graph, alpha, root), flush=True)
+            run_pipeline(ctx, g, int(root), inputs.bounds_equal(g.n_vertices, 16), use_graph)
+    finally:
+        ctx.bfs_set_direction(0.0, 0.0)
+
+
 def test_pipeline_plain_mode(ctx):
     g = inputs.graph(inputs.RMAT, 14, 16, 2)
     root = int(inputs.roots(g, 1, 2)[0])
