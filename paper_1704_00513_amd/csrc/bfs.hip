@@ -1,9 +1,13 @@
-// Top-down BFS level on gfx950: the frontier expansion t = A (x) f followed by
-// the visited filter of the baseline BFS algorithm (Romera, arXiv 1704.00513,
-// "Our Baseline algorithm": SpMV step, then the element-wise product with the
-// complement of the visited list), producing the next frontier as a sorted
-// vertex list without sorting: winners mark a next-level bitmap, which is
-// compacted in vertex order.
+// BFS level on gfx950.  Top-down: the frontier expansion t = A (x) f followed
+// by the visited filter of the baseline BFS algorithm (Romera, arXiv
+// 1704.00513, "Our Baseline algorithm": SpMV step, then the element-wise
+// product with the complement of the visited list).  Bottom-up, on the levels
+// the direction rule picks (the paper's related work, "Direction
+// optimization"): each unvisited vertex looks for a frontier neighbour.  The
+// next frontier comes out as a sorted vertex list without sorting: winners
+// mark a next-level bitmap, which is compacted in vertex order.  The
+// candidate exchange of the compressed 2D BFS (end of this file) reuses the
+// top-down expansion.
 //
 // Load balance: each workgroup takes 256 frontier vertices; vertices of
 // degree < 512 are expanded by a workgroup-wide gather over their
@@ -38,7 +42,7 @@ constexpr uint32_t kParts = 4096;
 
 // Direction state (stat[]): [0] arcs of the unvisited vertices, [1] the
 // previous frontier's size, [2] this level's direction (0 top-down, 1
-// bottom-up), [3] arcs of the frontier being emitted.
+// bottom-up), [3] the root's arcs (later frontiers' arcs come as partial sums).
 enum { kStatMu = 0, kStatPrevN = 1, kStatDir = 2, kStatMf = 3 };
 
 static inline BfsWs bfs_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, size_t *bytes) {
@@ -47,6 +51,8 @@ static inline BfsWs bfs_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, size_t 
     size_t off = 0;
     w.words = (V + 31) / 32;
     w.nchunks = (w.words + kCompactWords - 1) / kCompactWords;
+    // a vertex of degree d >= kHuge gives at most d / kHugeChunk + 1 chunks,
+    // and fewer than n_arcs / kHuge such vertices exist
     w.qcap = (uint32_t)(n_arcs / kHugeChunk + n_arcs / kHuge + 16);
     w.visited = (uint32_t *)(b + off);
     off = align256(off + (size_t)w.words * 4);
