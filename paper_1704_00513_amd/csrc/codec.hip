@@ -1321,6 +1321,24 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint64_t capw = a.out_cap >> 2;
     // segment and its first tile as recorded by the pack pass (no search)
     const uint2 ts = a.p.tile_seg[t];
+    // what depends on t alone is loaded first, so that the slot's words are
+    // in flight while the offsets are worked out.  Up to 512 payload words
+    // and the directory words are held in registers; every index stays
+    // inside the tile's slot whatever the unit sizes read
+    const uint32_t A0 = readfirst(a.p.unit_words[2 * t]), A1 = readfirst(a.p.unit_words[2 * t + 1]);
+    const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+    constexpr uint32_t kC = 8;
+    const uint32_t nw = A0 + A1;
+    auto src = [&](uint32_t q) {
+        return q < A0 ? kSlotDirWords + q : kSlotDirWords + kSlotHalfWords + (q - A0);
+    };
+    uint32_t x[kC];
+#pragma unroll
+    for (uint32_t i = 0; i < kC; ++i) {
+        const uint32_t q = lane + 64 * i;
+        x[i] = q < nw ? slot[src(q)] : 0u;
+    }
+    const uint32_t dirw = lane < kSlotDirWords ? slot[lane] : 0u;
     const uint32_t r = readfirst(ts.x);
     const uint32_t t_first = readfirst(ts.y);
     const uint32_t bb = readfirst(a.p.blk_base[r]);
@@ -1356,31 +1374,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t nblk = nb > k0 ? min(kGroup, nb - k0) : 0u;
     if (!nblk) return;
     const uint64_t rel = Pt - P;
-    const uint32_t A0 = readfirst(a.p.unit_words[2 * t]), A1 = readfirst(a.p.unit_words[2 * t + 1]);
     const uint64_t pwb = sw + 4 + 2ull * nb + ng + rel;
     const uint64_t dwb = sw + 4 + 2ull * k0;
     if (pwb + A0 + A1 > capw || sw + 4 + 2ull * nb + ng > capw) {
         if (lane == 0) raise_err(a.err, kErrCapacity);
         return;
     }
-    const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-    if (lane < 2 * nblk) a.out[dwb + lane] = slot[lane];
+    if (lane < 2 * nblk) a.out[dwb + lane] = dirw;
     if (lane == 0) a.out[sw + 4 + 2ull * nb + g] = (uint32_t)rel;
-    // payload words q < A0 + A1 of the tile (half 0, then half 1): up to 512
-    // are loaded before any is stored (the stores may alias the slot as far
-    // as the compiler knows, which would otherwise put one load latency on
-    // every 64 words), the rest in a loop
-    constexpr uint32_t kC = 8;
-    const uint32_t nw = A0 + A1;
-    auto src = [&](uint32_t q) {
-        return q < A0 ? kSlotDirWords + q : kSlotDirWords + kSlotHalfWords + (q - A0);
-    };
-    uint32_t x[kC];
-#pragma unroll
-    for (uint32_t i = 0; i < kC; ++i) {
-        const uint32_t q = lane + 64 * i;
-        x[i] = q < nw ? slot[src(q)] : 0u;
-    }
+    // payload words q < A0 + A1 of the tile (half 0, then half 1): the first
+    // 512 were loaded above, before any store (the stores may alias the slot
+    // as far as the compiler knows), the rest in a loop
 #pragma unroll
     for (uint32_t i = 0; i < kC; ++i) {
         const uint32_t q = lane + 64 * i;
