@@ -58,3 +58,26 @@ def test_status_strings_and_host_errors(lib):
     assert lib.bfsc_create(ctypes.byref(h), -1) == 1
     lib.bfsc_mlp_param_count.restype = ctypes.c_int
     assert lib.bfsc_mlp_param_count() == 7011
+
+
+def test_exchange_key_space_limit_is_checked_on_the_host(lib):
+    """Candidate keys are p * 32*ceil(V/32) + w in 32 bits: nseg * 32*ceil(V/32)
+    must stay below 2^32; the BFS and exchange workspaces need no GPU."""
+    from paper_1704_00513_amd import _lib
+    csr = _lib.CSR()
+    csr.n_vertices = 1 << 26
+    csr.n_arcs = 1 << 30
+    out = ctypes.c_size_t()
+    size = lib.bfsc_exchange_workspace_size
+    assert size(ctypes.byref(csr), 63, ctypes.byref(out)) == 0
+    # 63 candidate bitmaps + the merge and frontier bitmaps, V/8 bytes each at least
+    assert out.value >= 64 * (1 << 26) // 8
+    assert size(ctypes.byref(csr), 64, ctypes.byref(out)) == 1
+    assert size(ctypes.byref(csr), 0, ctypes.byref(out)) == 1
+    csr.n_vertices = (1 << 26) - 31  # rounds up to the same 32-bit stride
+    assert size(ctypes.byref(csr), 64, ctypes.byref(out)) == 1
+    csr.n_vertices = (1 << 26) - 32
+    assert size(ctypes.byref(csr), 64, ctypes.byref(out)) == 0
+    bfs = ctypes.c_size_t()
+    assert lib.bfsc_bfs_workspace_size(ctypes.byref(csr), ctypes.byref(bfs)) == 0
+    assert bfs.value >= 3 * ((1 << 26) - 32) // 8  # visited, next-level and frontier bitmaps
