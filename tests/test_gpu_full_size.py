@@ -1,10 +1,13 @@
-"""Parity at the size the benchmark times: R-MAT s22 (edge factor 16, seed 1),
-8 roots, every level split into 16 equal vertex ranges, exhaustive choice, in
-the default launch configuration, with the frontiers made by the
-direction-optimizing BFS as the benchmark makes them.  The oracle checks what
-it can compute piece by piece: the first root's levels and parents, and
-sampled segments byte for byte (segments are independent); the full round
-trip and the offsets are checked at full size."""
+"""Parity at full size, with the frontiers made by the direction-optimizing
+BFS as the benchmark makes them: R-MAT s22 (edge factor 16, seed 1), 8 roots,
+every level split into 16 equal vertex ranges, exhaustive choice, default
+launch configuration (the benchmark's timed workload); and R-MAT s24, 8
+roots, 256 Zipf-sized ranges per level, launch shapes from the autotuner.  The oracle checks what it can compute piece by piece: the first
+root's levels and parents, and sampled segments byte for byte (segments are
+independent); the full round trip and the offsets are checked at full size.
+The uniform s24 and the s26 workloads are checked the same way by the
+benchmark itself before it times them (sampled segments, full round trip),
+which keeps this file near a minute."""
 import numpy as np
 import pytest
 
@@ -15,7 +18,8 @@ from gpu_util import torch
 
 pytestmark = pytest.mark.gpu
 
-SCALE, ROOTS, NSEG = 22, 8, 16
+ROOTS = 8
+CASES = [(inputs.RMAT, 22, 16, False), (inputs.RMAT, 24, 256, True)]
 
 
 @pytest.fixture(scope="module")
@@ -26,16 +30,17 @@ def ctx():
     c.close()
 
 
-@pytest.fixture(scope="module")
-def full(ctx):
+@pytest.fixture(scope="module", params=CASES, ids=["rmat-s22-equal16", "rmat-s24-zipf256"])
+def full(ctx, request):
     import paper_1704_00513_amd as P
     t = torch()
-    print("full-size batch: R-MAT s%d, %d roots, %d segments per level" % (SCALE, ROOTS, NSEG), flush=True)
-    g = inputs.graph(inputs.RMAT, SCALE, 16, 1)
+    kind, scale, NSEG, zipf = request.param
+    print("full-size batch: kind=%d s%d, %d roots, %d segments per level" % (kind, scale, ROOTS, NSEG), flush=True)
+    g = inputs.graph(kind, scale, 16, 1, cache=False)
     roots = inputs.roots(g, ROOTS, 1)
     V = g.n_vertices
     dg = P.DeviceGraph.from_host(g)
-    bounds_h = inputs.bounds_equal(V, NSEG)
+    bounds_h = inputs.bounds_zipf(V, NSEG, 1)[0] if zipf else inputs.bounds_equal(V, NSEG)
     bounds = t.from_numpy(bounds_h.view(np.int32)).cuda()
     i32 = dict(dtype=t.int32, device="cuda")
     all_ids = t.empty(V * (ROOTS + 1), **i32)
@@ -74,7 +79,9 @@ def full(ctx):
     b = P.DeviceBatch(all_ids[:base], t.from_numpy(seg_off.view(np.int64)).cuda(),
                       t.from_numpy(lo.view(np.int32)).cuda(), t.from_numpy(hi.view(np.int32)).cuda(),
                       t.from_numpy(np.concatenate(levs)).cuda(), max_ids=base)
-    return dict(g=g, b=b, seg_off=seg_off, lo=lo, hi=hi, lev=np.concatenate(levs), n=base, root0=root0)
+    yield dict(g=g, b=b, seg_off=seg_off, lo=lo, hi=hi, lev=np.concatenate(levs), n=base, root0=root0,
+               autotune=zipf)
+    del b, all_ids, dg
 
 
 def test_full_size_first_root_levels_and_parents(full):
@@ -90,7 +97,17 @@ def test_full_size_round_trip_and_sampled_segments(ctx, full):
     t = torch()
     b, N = full["b"], full["n"]
     R = b.nseg
+    before = ctx.get_tune()
+    if full["autotune"]:
+        print("full-size autotune:", ctx.autotune(b), flush=True)
     print("full-size encode/decode: %d IDs in %d segments" % (N, R), flush=True)
+    try:
+        _round_trip_and_samples(ctx, full, P, t, b, N, R)
+    finally:
+        ctx.set_tune(**before)
+
+
+def _round_trip_and_samples(ctx, full, P, t, b, N, R):
     cap = P.Context.encode_bound(N, R)
     out = t.zeros(cap, dtype=t.uint8, device="cuda")
     sbo = t.zeros(R + 1, dtype=t.int64, device="cuda")
