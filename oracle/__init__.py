@@ -31,6 +31,12 @@ PLAIN_BP, EXHAUSTIVE = 0, 1
 CLS_BITMAP, CLS_PFOR = 0, 34
 BLOCK = 128
 GROUP = 16
+# Compression threshold: segments of fewer IDs are sent raw (the "Usage of
+# compression thresholds" section).  The value is this project's reading:
+# on the R-MAT and uniform frontiers measured, the compressed form is never
+# smaller than raw below about 15 IDs, and below about 33 at the widest gaps a
+# scale-26 segment can have.
+RAW_BELOW = 32
 
 
 def build(force: bool = False) -> str:
@@ -60,8 +66,8 @@ def _load():
                 "ref_encode_bound": (u64, [u64, u32]),
                 "ref_select": (i32, [vp, vp, vp, vp, u32, i32, vp]),
                 "ref_block_details": (i32, [vp, vp, u32, vp, vp, vp, vp, vp, vp]),
-                "ref_encode": (i32, [vp, vp, vp, vp, u32, vp, i32, vp, u64, vp]),
-                "ref_encoded_size": (u64, [vp, vp, u32, vp, i32]),
+                "ref_encode": (i32, [vp, vp, vp, vp, u32, vp, i32, u32, vp, u64, vp]),
+                "ref_encoded_size": (u64, [vp, vp, u32, vp, i32, u32]),
                 "ref_decode": (i32, [vp, vp, u32, vp, u64, vp]),
                 "ref_f32_to_f16": (ctypes.c_uint16, [ctypes.c_float]),
                 "ref_features": (i32, [vp, vp, u32, vp, vp]),
@@ -197,30 +203,35 @@ def block_details(b: Batch, classes=None):
     return {k: v[:nb] for k, v in out.items()}
 
 
-def encode(b: Batch, classes=None, mode: int = EXHAUSTIVE, cap: int | None = None):
-    """-> (stream u8[total], seg_byte_off u64[R+1]); raises on INVAL/CAPACITY."""
-    st, buf, sbo = encode_status(b, classes, mode, cap)
+def encode(b: Batch, classes=None, mode: int = EXHAUSTIVE, cap: int | None = None,
+           raw_below: int = RAW_BELOW):
+    """-> (stream u8[total], seg_byte_off u64[R+1]); raises on INVAL/CAPACITY.
+    Segments of fewer than raw_below IDs are written raw, empty ones as no
+    bytes."""
+    st, buf, sbo = encode_status(b, classes, mode, cap, raw_below)
     if st != ST_OK:
         raise ValueError("oracle encode: status %d" % st)
     return buf, sbo
 
 
-def encode_status(b: Batch, classes=None, mode: int = EXHAUSTIVE, cap: int | None = None):
+def encode_status(b: Batch, classes=None, mode: int = EXHAUSTIVE, cap: int | None = None,
+                  raw_below: int = RAW_BELOW):
     if cap is None:
         cap = encode_bound(b.n_ids, b.nseg)
     buf = np.zeros(max(1, cap), np.uint8)
     sbo = np.zeros(b.nseg + 1, np.uint64)
     cls = None if classes is None else np.ascontiguousarray(classes, np.uint8)
     st = _load().ref_encode(_p(b.ids), _p(b.seg_off), _p(b.seg_lo), _p(b.seg_hi), b.nseg, _p(cls),
-                            mode, _p(buf), cap, _p(sbo))
+                            mode, int(raw_below), _p(buf), cap, _p(sbo))
     if st != ST_OK:
         return st, None, None
     return st, buf[:int(sbo[-1])].copy(), sbo
 
 
-def encoded_size(b: Batch, classes=None, mode: int = EXHAUSTIVE) -> int:
+def encoded_size(b: Batch, classes=None, mode: int = EXHAUSTIVE, raw_below: int = RAW_BELOW) -> int:
     cls = None if classes is None else np.ascontiguousarray(classes, np.uint8)
-    return int(_load().ref_encoded_size(_p(b.ids), _p(b.seg_off), b.nseg, _p(cls), mode))
+    return int(_load().ref_encoded_size(_p(b.ids), _p(b.seg_off), b.nseg, _p(cls), mode,
+                                        int(raw_below)))
 
 
 def decode(stream: np.ndarray, seg_byte_off: np.ndarray, out_cap: int | None = None):
@@ -231,8 +242,8 @@ def decode(stream: np.ndarray, seg_byte_off: np.ndarray, out_cap: int | None = N
     sbo = _u64(seg_byte_off)
     nseg = sbo.size - 1
     if out_cap is None:
-        # a segment of n IDs takes at least 16 + 8 ceil(n/128) bytes, so
-        # n <= 16 * bytes
+        # a segment of n IDs takes at least 4 n bytes (raw) or 16 + 8
+        # ceil(n/128) bytes (compressed), so n <= 16 * bytes
         out_cap = 16 * (int(sbo[-1]) if nseg else 0) + 1
     out = np.zeros(max(1, out_cap), np.uint32)
     off = np.zeros(nseg + 1, np.uint64)

@@ -15,13 +15,22 @@
  * format itself is this project's own reading (the paper used third-party
  * codec libraries and prints no format): see the format notes below.
  *
- * Stream format of one segment (little-endian 32-bit words):
- *   header    16 B : n, lo, hi, magic 0x31434642
- *   directory 8 B per 128-ID block: first (= v0 - lo), class u8, param u8, aux u16
- *   group tab 4 B per 16 blocks: payload word offset of block 16g
- *   payloads  whole words per block, in block order
- * Block classes: 0 = dense bitmap, 1..33 = bit-packed deltas of width
- * class-1, 34 = patched frame of reference (PFOR) with exceptions.
+ * Stream format of one segment of n IDs (little-endian 32-bit words).  The
+ * form depends on n and the compression threshold T, the least sequence
+ * length that is compressed (the "Usage of compression thresholds" section:
+ * shorter sequences are sent as they are):
+ *   n = 0       empty form: no bytes at all
+ *   0 < n < T   raw form: the n IDs, 4 n bytes
+ *   n >= T      compressed form:
+ *     header    16 B : n, hi, lo, magic 0x31434642
+ *     directory 8 B per 128-ID block: first (= v0 - lo), class u8, param u8, aux u16
+ *     group tab 4 B per 16 blocks: payload word offset of block 16g
+ *     payloads  whole words per block, in block order
+ * The reader tells the forms apart by the segment's byte length L and its
+ * words 1 and 2: L = 0 is empty; L < 16, or word 1 < word 2 (IDs strictly
+ * increase), is raw; word 1 > word 2 (hi > lo in the header) is compressed.
+ * It needs no T.  Block classes: 0 = dense bitmap, 1..33 = bit-packed deltas
+ * of width class-1, 34 = patched frame of reference (PFOR) with exceptions.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -406,7 +415,7 @@ int ref_block_details(const uint32_t *ids, const uint64_t *seg_off, uint32_t nse
  * exchange; here one segment = one destination's sequence. */
 int ref_encode(const uint32_t *ids, const uint64_t *seg_off, const uint32_t *seg_lo,
                const uint32_t *seg_hi, uint32_t nseg, const uint8_t *classes, int mode,
-               uint8_t *out, uint64_t out_cap, uint64_t *seg_byte_off)
+               uint32_t raw_below, uint8_t *out, uint64_t out_cap, uint64_t *seg_byte_off)
 {
     blockinfo *b = (blockinfo *)malloc(sizeof(blockinfo));
     uint32_t *payload = (uint32_t *)malloc(BLK * 4 * 2);
@@ -419,12 +428,22 @@ int ref_encode(const uint32_t *ids, const uint64_t *seg_off, const uint32_t *seg
         if (n > 0xFFFFFFFFull || lo > hi || !seg_ids_ok(v, n, lo, hi)) { st = ST_INVAL; break; }
         uint64_t nb = seg_nblocks(n), ng = ceil_div(nb, GRP);
         seg_byte_off[r] = pos;
+        if (n == 0) continue;  /* empty form */
+        if (n < raw_below) {
+            /* raw form: below the threshold the IDs go as they are; their
+             * classes (if given) are skipped */
+            if (pos + 4 * n > out_cap) { st = ST_CAPACITY; break; }
+            for (uint64_t i = 0; i < n; ++i) put_u32(out + pos + 4 * i, v[i]);
+            pos += 4 * n;
+            k += nb;
+            continue;
+        }
         uint64_t meta = 16 + 8 * nb + 4 * ng;
         if (pos + meta > out_cap) { st = ST_CAPACITY; break; }
         uint8_t *seg = out + pos;
         put_u32(seg + 0, (uint32_t)n);
-        put_u32(seg + 4, lo);
-        put_u32(seg + 8, hi);
+        put_u32(seg + 4, hi);
+        put_u32(seg + 8, lo);
         put_u32(seg + 12, MAGIC);
         uint64_t pw = 0; /* payload words so far in this segment */
         for (uint64_t blk = 0; blk < nb; ++blk, ++k) {
@@ -455,9 +474,10 @@ int ref_encode(const uint32_t *ids, const uint64_t *seg_off, const uint32_t *seg
 }
 
 /* Encoded size of a batch from the closed-form size model (no stream):
- * 16 + 8 nb + 4 ceil(nb/16) + 4 sum(words) per segment. */
+ * 16 + 8 nb + 4 ceil(nb/16) + 4 sum(words) per compressed segment, 4 n per
+ * raw one, 0 per empty one. */
 uint64_t ref_encoded_size(const uint32_t *ids, const uint64_t *seg_off, uint32_t nseg,
-                          const uint8_t *classes, int mode)
+                          const uint8_t *classes, int mode, uint32_t raw_below)
 {
     blockinfo *b = (blockinfo *)malloc(sizeof(blockinfo));
     uint64_t total = 0, k = 0;
@@ -465,6 +485,8 @@ uint64_t ref_encoded_size(const uint32_t *ids, const uint64_t *seg_off, uint32_t
         uint64_t n = seg_off[r + 1] - seg_off[r];
         const uint32_t *v = ids + seg_off[r];
         uint64_t nb = seg_nblocks(n);
+        if (n == 0) continue;
+        if (n < raw_below) { total += 4 * n; k += nb; continue; }
         total += 16 + 8 * nb + 4 * ceil_div(nb, GRP);
         for (uint64_t s = 0; s < n; s += BLK, ++k) {
             uint32_t nk = (uint32_t)((n - s) < BLK ? (n - s) : BLK);
@@ -484,13 +506,39 @@ static uint32_t popcount32(uint32_t x)
     return c;
 }
 
-/* Reads one segment; returns ST_OK or ST_CORRUPT.  Values go to out (if
- * not NULL).  *n_out receives the header count. */
+/* Form of a segment of `bytes` bytes: 0 empty, 1 raw, 2 compressed, -1 neither
+ * (see the format notes at the top). */
+static int segment_form(const uint8_t *seg, uint64_t bytes)
+{
+    if (bytes == 0) return 0;
+    if (bytes % 4) return -1;
+    if (bytes < 16) return 1;
+    uint32_t w1 = get_u32(seg + 4), w2 = get_u32(seg + 8);
+    if (w1 < w2) return 1;
+    if (w1 > w2) return 2;
+    return -1;
+}
+
+/* Reads a raw segment: its words are the IDs, strictly increasing. */
+static int decode_raw(const uint8_t *seg, uint64_t bytes, uint32_t *out, uint64_t *n_out)
+{
+    uint64_t n = bytes / 4;
+    *n_out = n;
+    for (uint64_t i = 1; i < n; ++i)
+        if (get_u32(seg + 4 * i) <= get_u32(seg + 4 * (i - 1))) return ST_CORRUPT;
+    if (out)
+        for (uint64_t i = 0; i < n; ++i) out[i] = get_u32(seg + 4 * i);
+    return ST_OK;
+}
+
+/* Reads one compressed segment; returns ST_OK or ST_CORRUPT.  Values go to
+ * out (if not NULL).  *n_out receives the header count. */
 static int decode_segment(const uint8_t *seg, uint64_t bytes, uint32_t *out, uint64_t *n_out)
 {
     if (bytes < 16) return ST_CORRUPT;
-    uint32_t n = get_u32(seg), lo = get_u32(seg + 4), hi = get_u32(seg + 8);
-    if (get_u32(seg + 12) != MAGIC || lo > hi || n > hi - lo) return ST_CORRUPT;
+    uint32_t n = get_u32(seg), hi = get_u32(seg + 4), lo = get_u32(seg + 8);
+    /* the compressed form is only used for non-empty segments */
+    if (get_u32(seg + 12) != MAGIC || lo > hi || n == 0 || n > hi - lo) return ST_CORRUPT;
     *n_out = n;
     uint64_t nb = seg_nblocks(n), ng = ceil_div(nb, GRP);
     uint64_t meta = 16 + 8 * nb + 4 * ng;
@@ -577,14 +625,19 @@ int ref_decode(const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
         const uint8_t *seg = in + seg_byte_off[r];
         uint64_t n = 0;
         out_off[r] = acc;
-        if (bytes >= 16) {
+        int form = segment_form(seg, bytes), st = ST_OK;
+        if (form < 0) return ST_CORRUPT;
+        if (form == 1) {
+            if (acc + bytes / 4 > out_cap) return ST_CAPACITY;
+            st = decode_raw(seg, bytes, out_ids + acc, &n);
+        } else if (form == 2) {
             n = get_u32(seg);
             uint64_t nb = seg_nblocks(n);
             /* a count the segment cannot hold is damage, not a capacity problem */
             if (16 + 8 * nb + 4 * ceil_div(nb, GRP) <= bytes && acc + n > out_cap)
                 return ST_CAPACITY;
+            st = decode_segment(seg, bytes, out_ids + acc, &n);
         }
-        int st = decode_segment(seg, bytes, out_ids + acc, &n);
         if (st != ST_OK) return st;
         acc += n;
     }

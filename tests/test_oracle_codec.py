@@ -21,8 +21,8 @@ def one_segment(ids, lo=0, hi=None, level=0):
     return Batch(ids, [0, ids.size], [lo], [hi], [level])
 
 
-def roundtrip(b, classes=None, mode=oracle.EXHAUSTIVE):
-    stream, sbo = oracle.encode(b, classes, mode)
+def roundtrip(b, classes=None, mode=oracle.EXHAUSTIVE, raw_below=oracle.RAW_BELOW):
+    stream, sbo = oracle.encode(b, classes, mode, raw_below=raw_below)
     st, out, off = oracle.decode(stream, sbo)
     assert st == oracle.ST_OK
     np.testing.assert_array_equal(out, b.ids)
@@ -78,15 +78,17 @@ def test_eq8_analog_outlier_becomes_exception():
 def test_single_id_block_is_width_zero():
     b = one_segment([12345], lo=0, hi=20000)
     assert list(oracle.select(b)) == [1]
-    stream, sbo = roundtrip(b)
+    stream, sbo = roundtrip(b, raw_below=0)
     assert int(sbo[-1]) == 16 + 8 + 4  # no payload words
+    assert struct.unpack("<IIII", stream[:16].tobytes()) == (1, 20000, 0, 0x31434642)
 
 
-def test_empty_segment_is_header_only():
-    b = Batch(np.zeros(0, np.uint32), [0, 0], [0], [10])
-    stream, sbo = roundtrip(b)
-    assert int(sbo[-1]) == 16
-    assert struct.unpack("<IIII", stream.tobytes()) == (0, 0, 10, 0x31434642)
+def test_empty_segment_is_no_bytes():
+    # whatever the threshold, an empty segment takes no bytes
+    for T in (0, 1, oracle.RAW_BELOW):
+        b = Batch(np.zeros(0, np.uint32), [0, 0], [0], [10])
+        stream, sbo = roundtrip(b, raw_below=T)
+        assert int(sbo[-1]) == 0 and stream.size == 0
 
 
 # ------------------------------------------------------------ independent reader
@@ -104,7 +106,13 @@ def string_decode(stream):
     """A second, bit-string based reading of one segment (no shared code with
     the C reader): returns the values."""
     words = np.frombuffer(stream.tobytes(), np.uint32)
-    n, lo, hi, magic = (int(x) for x in words[:4])
+    if words.size == 0:
+        return np.zeros(0, np.uint64)
+    if words.size < 4 or words[1] < words[2]:
+        # raw: the IDs themselves
+        assert (np.diff(words.astype(np.int64)) > 0).all()
+        return words.astype(np.uint64)
+    n, hi, lo, magic = (int(x) for x in words[:4])
     assert magic == 0x31434642
     nb = (n + BLOCK - 1) // BLOCK
     ng = (nb + 15) // 16
@@ -179,15 +187,16 @@ def test_every_class_and_pfor_width_round_trips():
         for cls in [0] + list(range(1 + wmin, 34)) + [34]:
             if cls == 0 and d["span"][0] > 4096:
                 continue
-            stream, sbo = roundtrip(b, np.array([cls], np.uint8))
+            stream, sbo = roundtrip(b, np.array([cls], np.uint8), raw_below=0)
             np.testing.assert_array_equal(string_decode(stream), ids.astype(np.uint64))
 
 
 def test_top_of_u32_range():
     ids = np.array([0, 1, 0xFFFFFFF0, 0xFFFFFFFD], np.uint32)
     b = one_segment(ids, lo=0, hi=0xFFFFFFFE)
-    stream, _ = roundtrip(b)
-    np.testing.assert_array_equal(string_decode(stream), ids.astype(np.uint64))
+    for T in (0, oracle.RAW_BELOW):
+        stream, _ = roundtrip(b, raw_below=T)
+        np.testing.assert_array_equal(string_decode(stream), ids.astype(np.uint64))
 
 
 # ------------------------------------------------------------ brute force
@@ -219,7 +228,7 @@ def test_bruteforce_exhaustive_is_optimal_on_all_subsets_of_16():
         sub = Batch(np.concatenate([ids[off[i]:off[i + 1]] for i in sel]),
                     np.concatenate([[0], np.cumsum([off[i + 1] - off[i] for i in sel])]),
                     np.zeros(sel.size, np.uint32), np.full(sel.size, 16, np.uint32))
-        stream, sbo = oracle.encode(sub, np.full(sel.size, cls, np.uint8))
+        stream, sbo = oracle.encode(sub, np.full(sel.size, cls, np.uint8), raw_below=0)
         st, out, _ = oracle.decode(stream, sbo)
         assert st == oracle.ST_OK
         np.testing.assert_array_equal(out, sub.ids)
@@ -232,7 +241,7 @@ def test_bruteforce_exhaustive_is_optimal_on_all_subsets_of_16():
     want = np.array([next(c for c in order if sizes[i, c] == best[i]) for i in range(R)])
     np.testing.assert_array_equal(ex, want)
     # and the exhaustive stream is that size
-    stream, sbo = oracle.encode(b)
+    stream, sbo = oracle.encode(b, raw_below=0)
     np.testing.assert_array_equal(np.diff(sbo.astype(np.int64)), best)
 
 
@@ -296,9 +305,9 @@ def test_capacity_and_invalid_inputs():
     assert oracle.encode_status(bad)[0] == oracle.ST_INVAL
     out_of_range = Batch(np.array([1, 2, 30], np.uint32), [0, 3], [0], [20])
     assert oracle.encode_status(out_of_range)[0] == oracle.ST_INVAL
-    # a forced class that cannot hold the block
+    # a forced class that cannot hold the block (in the compressed form)
     b = one_segment(np.array([0, 1000], np.uint32), hi=2000)
-    assert oracle.encode_status(b, classes=np.array([3], np.uint8))[0] == oracle.ST_INVAL
+    assert oracle.encode_status(b, classes=np.array([3], np.uint8), raw_below=0)[0] == oracle.ST_INVAL
 
 
 # ------------------------------------------------------------ damaged streams

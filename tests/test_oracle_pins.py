@@ -27,8 +27,8 @@ MAGIC = 0x31434642
 
 
 def seg_header(n, lo, hi):
-    """The 16-byte header of a compressed segment."""
-    return struct.pack("<IIII", n, lo, hi, MAGIC)
+    """The 16-byte header of a compressed segment: n, hi, lo, magic."""
+    return struct.pack("<IIII", n, hi, lo, MAGIC)
 
 
 def one_segment(ids, lo=0, hi=None):
@@ -187,7 +187,8 @@ def test_every_pfor_width_decodes_from_a_hand_built_stream():
             np.testing.assert_array_equal(out, ids)
             seen.add(b)
             if b == chosen:
-                want, _ = oracle.encode(Batch(ids, [0, n], [lo], [hi]), np.array([oracle.CLS_PFOR], np.uint8))
+                want, _ = oracle.encode(Batch(ids, [0, n], [lo], [hi]), np.array([oracle.CLS_PFOR], np.uint8),
+                                        raw_below=0)
                 np.testing.assert_array_equal(stream, want)
     assert seen >= set(range(1, 25))
     # b = 0 leaves every delta (>= 1) an exception, so only a one-ID block
@@ -249,3 +250,116 @@ def test_forward_rounding_of_negative_hidden_values_is_relu_first():
     paths = [(1.0, -2.0, 1.0, 0.0, 1.0, 0.5), (2.0 ** -26, 0.0, 1.0, 0.0, 1.0, 0.25)]
     z, _ = mlp.forward(diagonal_net(paths), np.array([[1.0, 1.0, 0, 0, 0, 0, 0, 0]]))
     assert list(z[0, :2]) == [0.5, 0.25]
+
+
+# ------------------------------------------------------------ compression threshold
+
+def test_raw_form_is_the_ids_verbatim():
+    # below the threshold a sequence is sent as it is ("Usage of compression
+    # thresholds" section): 4 bytes per ID, no header
+    for n in (1, 2, 3, 4, 5, 31):
+        ids = np.sort(np.random.default_rng(n).choice(1 << 20, n, replace=False)).astype(np.uint32)
+        stream, sbo = oracle.encode(one_segment(ids, hi=1 << 20), raw_below=32)
+        assert int(sbo[-1]) == 4 * n
+        np.testing.assert_array_equal(stream.view(np.uint32), ids)
+        st, out, _ = oracle.decode(stream, sbo)
+        assert st == oracle.ST_OK
+        np.testing.assert_array_equal(out, ids)
+
+
+def test_threshold_boundary():
+    # n = T - 1 raw, n = T compressed (header n, hi, lo, magic)
+    T = 40
+    ids = np.arange(100, 100 + 3 * T, 3).astype(np.uint32)
+    s1, o1 = oracle.encode(one_segment(ids[:T - 1], hi=1000), raw_below=T)
+    s2, o2 = oracle.encode(one_segment(ids[:T], hi=1000), raw_below=T)
+    assert int(o1[-1]) == 4 * (T - 1)
+    assert struct.unpack("<IIII", s2[:16].tobytes()) == (T, 1000, 0, MAGIC)
+    # bit-pack at width 2: 16 + 8 + 4 + ceil(39 * 2 / 32) words
+    assert int(o2[-1]) == 16 + 8 + 4 + 4 * 3
+    # T = 0 and T = 1 compress every non-empty segment
+    for T0 in (0, 1):
+        s, o = oracle.encode(one_segment(ids[:1], hi=1000), raw_below=T0)
+        assert int(o[-1]) == 28
+
+
+def test_mixed_batch_offsets_and_round_trip():
+    rng = np.random.default_rng(8)
+    sizes = [0, 1, 31, 32, 0, 500, 7, 0, 129]
+    segs, lo, hi = [], [], []
+    base = 0
+    for n in sizes:
+        segs.append(np.sort(rng.choice(10000, n, replace=False)).astype(np.uint32) + base)
+        lo.append(base)
+        hi.append(base + 10000)
+        base += 10000
+    ids = np.concatenate(segs)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    b = Batch(ids, off, lo, hi)
+    stream, sbo = oracle.encode(b, raw_below=32)
+    lens = np.diff(sbo.astype(np.int64))
+    for n, L, s0 in zip(sizes, lens, sbo[:-1]):
+        if n == 0:
+            assert L == 0
+        elif n < 32:
+            assert L == 4 * n
+        else:
+            w = stream[int(s0):int(s0) + 16].view(np.uint32)
+            assert w[0] == n and w[1] > w[2] and w[3] == MAGIC
+    assert oracle.encoded_size(b, raw_below=32) == int(sbo[-1])
+    st, out, oo = oracle.decode(stream, sbo)
+    assert st == oracle.ST_OK
+    np.testing.assert_array_equal(out, ids)
+    np.testing.assert_array_equal(oo, off)
+    # the reader needs no threshold: every T gives the same IDs
+    for T in (0, 1, 8, 600):
+        s, o = oracle.encode(b, raw_below=T)
+        st, out, _ = oracle.decode(s, o)
+        assert st == oracle.ST_OK
+        np.testing.assert_array_equal(out, ids)
+
+
+def test_single_id_segments_have_ratio_one():
+    # a first level of 8 roots split over 16 destinations: 8 one-ID segments
+    # and 8 empty ones are 32 bytes, ratio 1 (the compressed form would need
+    # 28 bytes per ID)
+    roots = np.array([5, 900, 2000, 7000, 9100, 12000, 14500, 16000], np.uint32)
+    b = oracle.batch_from_frontier(roots, inputs.bounds_equal(1 << 14, 16))
+    stream, sbo = oracle.encode(b)
+    assert int(sbo[-1]) == 32
+    assert oracle.ratio(4 * roots.size, int(sbo[-1])) == 1.0
+
+
+def test_reader_rejects_impossible_forms():
+    ids = np.arange(10, 50).astype(np.uint32)
+    good, sbo = oracle.encode(one_segment(ids, hi=100), raw_below=0)
+    # a length that is not a whole number of words
+    st, _, _ = oracle.decode(np.concatenate([good, [0]]).astype(np.uint8), np.array([0, good.size + 1], np.uint64))
+    assert st == oracle.ST_CORRUPT
+    # words 1 and 2 equal: neither form
+    s = good.copy().view(np.uint32)
+    s[2] = s[1]
+    assert oracle.decode(s.view(np.uint8), sbo)[0] == oracle.ST_CORRUPT
+    # a compressed header holding no IDs
+    s = good.copy().view(np.uint32)
+    s[0] = 0
+    assert oracle.decode(s.view(np.uint8), sbo)[0] == oracle.ST_CORRUPT
+    # raw segments must increase strictly
+    for bad in ([5, 5], [9, 3], [1, 2, 3, 3, 4]):
+        raw = np.array(bad, np.uint32).view(np.uint8)
+        assert oracle.decode(raw, np.array([0, raw.size], np.uint64))[0] == oracle.ST_CORRUPT
+
+
+def test_default_threshold_gives_ratio_at_least_one_per_level():
+    # every BFS level, and every exchanged candidate level, of R-MAT and
+    # uniform scale-16 graphs split over 16 equal and 256 Zipf ranges
+    for kind in (inputs.RMAT, inputs.UNIFORM):
+        g = inputs.graph(kind, 16, 16, 1)
+        root = int(inputs.roots(g, 1, 1)[0])
+        level, _, depth = oracle.bfs(g, root)
+        for bounds in (inputs.bounds_equal(g.n_vertices, 16), inputs.bounds_zipf(g.n_vertices, 256, 1)[0]):
+            for L in range(depth + 1):
+                f = oracle.frontier(level, L)
+                for b in (oracle.batch_from_frontier(f, bounds, L), oracle.candidates(g, f, bounds[::16] if bounds.size > 17 else bounds, L)):
+                    stream, sbo = oracle.encode(b)
+                    assert oracle.ratio(4 * b.n_ids, int(sbo[-1])) >= 1.0 if b.n_ids else int(sbo[-1]) == 0
