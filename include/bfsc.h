@@ -30,11 +30,20 @@
  *    lengths, segment offsets) are never read back by the host, so every
  *    entry point can be captured into a HIP graph.
  *
- * Stream format of one compressed segment (little-endian 32-bit words):
- *   header    16 B : n (IDs), lo, hi (the segment's ID range [lo, hi)), magic 0x31434642
- *   directory 8 B per block of 128 IDs: first (= v0 - lo), class u8, param u8, aux u16
- *   group tab 4 B per 16 blocks: payload word offset of block 16g in this segment
- *   payloads  a whole number of words per block, in block order
+ * Stream format of one segment of n IDs (little-endian 32-bit words).  Its
+ * form depends on n and the context's compression threshold T (the least
+ * sequence length that is compressed; shorter ones are sent as they are, the
+ * "Usage of compression thresholds" section):
+ *   n = 0       empty: no bytes
+ *   0 < n < T   raw: the n IDs, 4 n bytes
+ *   n >= T      compressed:
+ *     header    16 B : n (IDs), hi, lo (the segment's ID range [lo, hi)), magic 0x31434642
+ *     directory 8 B per block of 128 IDs: first (= v0 - lo), class u8, param u8, aux u16
+ *     group tab 4 B per 16 blocks: payload word offset of block 16g in this segment
+ *     payloads  a whole number of words per block, in block order
+ * The decoder needs no T: a segment of L bytes is empty if L = 0, raw if
+ * L < 16 or its words 1 and 2 increase (strictly increasing IDs), compressed
+ * if they decrease (hi > lo).
  * Block classes: 0 = dense bitmap of the span after v0 (param 0, aux = span,
  * span <= 4096); 1..33 = delta bit-packing at width class-1 (param = width,
  * the binary packing of the compression-techniques section, delta coding with
@@ -67,6 +76,7 @@ enum {
 
 /* Codec choice per block. */
 enum {
+    BFSC_SEL_DEFAULT = -1,   /* the context's configured choice (bfsc_config.selector) */
     BFSC_SEL_PLAIN_BP = 0,   /* bit-packing at the minimal width (the paper's S4-BP128-like plain method) */
     BFSC_SEL_EXHAUSTIVE = 1, /* fewest payload words among bitmap / all widths / PFOR */
     BFSC_SEL_LEARNED = 2     /* MLP prediction, resolved to a valid class (exhaustive fallback) */
@@ -138,11 +148,42 @@ typedef struct {
                                 current one decodes (bit 0 is then ignored) */
 } bfsc_tune;
 
-/* Creates a context on HIP device `device`: queries the device, allocates
- * the error word and the selector's parameters (device memory owned by the
- * context).  Synchronous.  *out is NULL on failure. */
-int bfsc_create(bfsc_ctx **out, int device);
+/* Context settings, fixed at bfsc_create.
+ *   selector        codec choice of calls given BFSC_SEL_DEFAULT (default
+ *                   BFSC_SEL_EXHAUSTIVE)
+ *   raw_below       compression threshold T: segments of 1 .. T-1 IDs are
+ *                   written raw (the "Usage of compression thresholds"
+ *                   section: compressing a short sequence costs more than it
+ *                   saves).  0 or 1: every non-empty segment is compressed.
+ *                   Default 32; at most 2048
+ *   resolve_literal how the learned choice turns a predicted bit-pack width
+ *                   into a class: 0 (default) the block's minimal width;
+ *                   1 the predicted width if it holds the block, else the
+ *                   exhaustive class (a diagnostic of the network's widths)
+ *   autotune        1: bfsc_create takes the launch shapes stored for this
+ *                   device (architecture name and compute-unit count) in the
+ *                   file tune_cache, if it has them, and bfsc_autotune
+ *                   stores what it measures there; 0: fixed default shapes
+ *   tune_cache      path of that text file (NULL: none; copied at create) */
+typedef struct {
+    int32_t selector;
+    uint32_t raw_below;
+    uint32_t resolve_literal;
+    uint32_t autotune;
+    const char *tune_cache;
+} bfsc_config;
+
+/* Fills *cfg with the defaults above. */
+void bfsc_config_default(bfsc_config *cfg);
+
+/* Creates a context on HIP device `device` with settings cfg (NULL: the
+ * defaults): queries the device, allocates the error word and the
+ * selector's parameters (device memory owned by the context).  Synchronous.
+ * BFSC_E_INVAL for settings out of range.  *out is NULL on failure. */
+int bfsc_create(bfsc_ctx **out, int device, const bfsc_config *cfg);
 int bfsc_destroy(bfsc_ctx *ctx);
+/* The context's settings (tune_cache points at the context's copy). */
+int bfsc_get_config(const bfsc_ctx *ctx, bfsc_config *cfg);
 
 /* Bytes of workspace an operation needs for a batch of at most max_ids IDs
  * in nseg segments (BFSC_OP_MLP: max_ids = samples per call; BFSC_OP_BFS is
@@ -242,11 +283,22 @@ int bfsc_merge_filter(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const
                       void *bfs_ws, void *ws, void *stream);
 
 /* Chooses a class per block (0 bitmap, 1..33 bit-pack width 0..32, 34 PFOR)
- * for every 128-ID block of every segment, in segment order: classes u8,
- * capacity ceil(max_ids/128) + nseg.  BFSC_SEL_LEARNED resolves the MLP's
- * prediction to a valid class (bitmap -> exhaustive if the span is too wide,
- * any width -> the minimal width, PFOR kept); blocks that fell back are
- * counted in *fallbacks_dev (u64, device, may be NULL; added to). */
+ * for every 128-ID block of every segment, in segment order (raw and empty
+ * segments included): classes u8, capacity ceil(max_ids/128) + nseg.  The
+ * candidates are the compression techniques' options for a sorted block:
+ * delta coding with binary packing at a width of eqs. (6)-(7), patched
+ * coding with exceptions (eqs. (8)-(9)), and a bitmap index.  The
+ * "Experimental performance comparison" subsection sums up which family
+ * suits which data: frame of reference plus delta coding for sequences with
+ * small gaps, bitmap indexes for low cardinality (dense sets); this choice
+ * is made per block instead of once for all data.
+ * BFSC_SEL_PLAIN_BP takes the minimal width (the paper's single fixed
+ * codec); BFSC_SEL_EXHAUSTIVE the fewest payload words (ties: bit-pack with
+ * the smallest width, then bitmap, then PFOR); BFSC_SEL_LEARNED resolves the
+ * MLP's prediction to a valid class (bitmap -> exhaustive if the span is too
+ * wide; a width -> the minimal width, or with resolve_literal the predicted
+ * width if it holds the block, else exhaustive; PFOR kept); blocks that fell
+ * back are counted in *fallbacks_dev (u64, device, may be NULL; added to). */
 int bfsc_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes,
                 uint64_t *fallbacks_dev, void *ws, void *stream);
 
@@ -259,8 +311,11 @@ int bfsc_encode_bound(uint64_t n_ids, uint32_t nseg, size_t *bytes);
  * bfsc_select, or NULL to choose with `mode` inside the encoder; with
  * BFSC_SEL_LEARNED and NULL classes the network runs inside the pack pass
  * (on the matrix cores, per unit of 8 blocks) and the stream equals the one
- * that bfsc_select + bfsc_encode produce (fallbacks are not counted).  The
- * batch's seg_level is then a feature and must be given.  Writes the
+ * that bfsc_select + bfsc_encode produce (fallbacks are not counted; with
+ * resolve_literal the selection runs as a separate pass into the workspace
+ * first).  The batch's seg_level is then a feature and must be given.
+ * Segments shorter than the context's threshold are written raw, empty ones
+ * as no bytes (their classes, if given, are skipped).  Writes the
  * segments back to back into out (capacity out_cap bytes) and
  * seg_byte_off u64[nseg+1] (device): segment r occupies
  * out[seg_byte_off[r] .. seg_byte_off[r+1]).  Overflow latches
@@ -281,13 +336,24 @@ int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, 
 /* Selector features: 8 fp16 values per block (bit patterns as u16, row
  * major [block][8]): n/128, bitlen(min delta)/32, bitlen(max delta)/32,
  * bitlen(floor(span/m))/32, bitlen(span)/32, fp16(fp32(n)/fp32(span+1)),
- * min(level,63)/64, bitlen(segment length)/32. */
+ * min(level,63)/64, bitlen(segment length)/32.  They are the data
+ * properties that the "Experimental performance comparison" subsection
+ * chooses a codec family by: the size of the gaps (eq. (6)'s width of
+ * max - min, here of the deltas), outliers that favour patched coding
+ * (eq. (8)), cardinality / density for bitmap indexes, and the length of
+ * the sequence; bitlen(x) = ceil(log2(x + 1)) is eq. (6)'s width. */
 int bfsc_features(bfsc_ctx *ctx, const bfsc_batch *b, uint16_t *feat, void *ws, void *stream);
 
 /* Selector network 8 -> 64 -> 64 -> 35 (ReLU), fp32 master parameters in the
  * order W1[64][8] b1[64] W2[64][64] b2[64] W3[35][64] b3[35] (7,011 floats).
  * set/get copy host <-> context and are synchronous; set resets Adam state. */
 int bfsc_mlp_param_count(void);
+/* He-uniform initial parameters: weight i of layer l (0..2) is
+ * lim * (2 u - 1) with lim = sqrt(6 / fan_in) and u = (x >> 40) * 2^-24,
+ * x = mix(mix(seed + G (100 + l + 1)) + G (i + 1)) (G = 0x9E3779B97F4A7C15,
+ * mix the SplitMix64 finaliser of Steele, Lea & Flood, OOPSLA 2014);
+ * biases 0.  Resets Adam state.  Synchronous. */
+int bfsc_mlp_init(bfsc_ctx *ctx, uint64_t seed);
 int bfsc_mlp_set_weights(bfsc_ctx *ctx, const float *host_params);
 int bfsc_mlp_get_weights(bfsc_ctx *ctx, float *host_params);
 

@@ -15,11 +15,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (E_CAPACITY, E_CORRUPT, E_HIP, E_INVAL, N_PARAMS, OK, OP_DECODE, OP_ENCODE,
-                   OP_FEATURES, OP_MLP, OP_SELECT, SEL_EXHAUSTIVE, SEL_LEARNED, SEL_PLAIN_BP,
-                   BfscError, check, ptr)
+                   OP_FEATURES, OP_MLP, OP_SELECT, RAW_BELOW, SEL_DEFAULT, SEL_EXHAUSTIVE, SEL_LEARNED,
+                   SEL_PLAIN_BP, BfscError, check, ptr)
 
-__all__ = ["Context", "DeviceGraph", "DeviceBatch", "SEL_PLAIN_BP", "SEL_EXHAUSTIVE",
-           "SEL_LEARNED", "BfscError", "OK", "E_INVAL", "E_CAPACITY", "E_CORRUPT", "E_HIP"]
+__all__ = ["Context", "DeviceGraph", "DeviceBatch", "SEL_DEFAULT", "SEL_PLAIN_BP", "SEL_EXHAUSTIVE",
+           "SEL_LEARNED", "RAW_BELOW", "BfscError", "OK", "E_INVAL", "E_CAPACITY", "E_CORRUPT", "E_HIP"]
 
 
 def _torch():
@@ -151,17 +151,37 @@ class Pipeline:
 class Context:
     """One bfsc context on one GPU, with grow-only workspaces."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, selector: int | None = None, raw_below: int | None = None,
+                 resolve_literal: bool | None = None, autotune: bool | None = None,
+                 tune_cache: str | None = None):
+        """Settings left at None keep the library's defaults (bfsc_config_default)."""
         lib = _lib.load()
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("bfsc needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = device
         torch.cuda.set_device(device)
+        cfg = _lib.default_config()
+        if selector is not None:
+            cfg.selector = int(selector)
+        if raw_below is not None:
+            cfg.raw_below = int(raw_below)
+        if resolve_literal is not None:
+            cfg.resolve_literal = int(bool(resolve_literal))
+        if autotune is not None:
+            cfg.autotune = int(bool(autotune))
+        self._tune_cache = None if tune_cache is None else str(tune_cache).encode()
+        cfg.tune_cache = self._tune_cache
         h = ctypes.c_void_p()
-        check(lib.bfsc_create(ctypes.byref(h), device), "bfsc_create")
+        check(lib.bfsc_create(ctypes.byref(h), device, ctypes.byref(cfg)), "bfsc_create")
         self.h = h
         self._ws = {}
+
+    def config(self) -> dict:
+        c = _lib.Config()
+        check(_lib.load().bfsc_get_config(self.h, ctypes.byref(c)), "bfsc_get_config")
+        return dict(selector=c.selector, raw_below=c.raw_below, resolve_literal=bool(c.resolve_literal),
+                    autotune=bool(c.autotune), tune_cache=None if c.tune_cache is None else c.tune_cache.decode())
 
     def close(self):
         if getattr(self, "h", None):
@@ -317,6 +337,10 @@ class Context:
         return self.get_tune()
 
     # ---------------------------------------------------------- MLP
+
+    def mlp_init(self, seed: int):
+        """He-uniform initial parameters from the counter RNG (bfsc_mlp_init)."""
+        check(_lib.load().bfsc_mlp_init(self.h, int(seed)), "bfsc_mlp_init")
 
     def mlp_set_weights(self, params: np.ndarray):
         p = np.ascontiguousarray(params, np.float32)

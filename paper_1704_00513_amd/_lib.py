@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbfsc.so")
 
 OK, E_INVAL, E_CAPACITY, E_CORRUPT, E_HIP, E_UNIMPLEMENTED = 0, 1, 2, 3, 4, 5
-SEL_PLAIN_BP, SEL_EXHAUSTIVE, SEL_LEARNED = 0, 1, 2
+SEL_DEFAULT, SEL_PLAIN_BP, SEL_EXHAUSTIVE, SEL_LEARNED = -1, 0, 1, 2
+RAW_BELOW = 32  # the library's default compression threshold
 OP_BFS, OP_SELECT, OP_ENCODE, OP_DECODE, OP_FEATURES, OP_MLP = 0, 1, 2, 3, 4, 5
 OP_ENCODE_PLACE, OP_PIPELINE = 6, 7
 N_PARAMS = 7011
@@ -44,6 +45,11 @@ class Tune(ctypes.Structure):
                 ("dec_wg_per_cu", u32), ("enc_pack", u32), ("dec_mode", u32)]
 
 
+class Config(ctypes.Structure):
+    _fields_ = [("selector", i32), ("raw_below", u32), ("resolve_literal", u32), ("autotune", u32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
 class PipelineBufs(ctypes.Structure):
     _fields_ = [("frontier", vp), ("frontier_len", vp), ("prev_frontier", vp),
                 ("prev_frontier_len", vp), ("level", vp), ("parent", vp), ("seg_off", vp),
@@ -59,8 +65,9 @@ _SIGS = {
     "bfsc_pipeline_buffers": [vp, P(PipelineBufs)],
     "bfsc_pipeline_destroy": [vp],
     "bfsc_memcpy": [vp, vp, sz],
-    "bfsc_create": [P(vp), ctypes.c_int],
+    "bfsc_create": [P(vp), ctypes.c_int, P(Config)],
     "bfsc_destroy": [vp],
+    "bfsc_get_config": [vp, P(Config)],
     "bfsc_workspace_size": [vp, ctypes.c_int, u64, u32, P(sz)],
     "bfsc_bfs_workspace_size": [P(CSR), P(sz)],
     "bfsc_bfs_init": [vp, P(CSR), u32, vp, vp, vp, vp, vp, vp],
@@ -77,6 +84,7 @@ _SIGS = {
     "bfsc_decode": [vp, vp, vp, u32, u64, vp, u64, vp, vp, vp],
     "bfsc_features": [vp, P(BatchDesc), vp, vp, vp],
     "bfsc_mlp_param_count": [],
+    "bfsc_mlp_init": [vp, u64],
     "bfsc_mlp_set_weights": [vp, vp],
     "bfsc_mlp_get_weights": [vp, vp],
     "bfsc_mlp_forward": [vp, vp, u32, vp, vp, vp],
@@ -115,12 +123,20 @@ def load() -> ctypes.CDLL:
                 fn.restype = ctypes.c_int
             lib.bfsc_status_string.argtypes = [ctypes.c_int]
             lib.bfsc_status_string.restype = ctypes.c_char_p
+            lib.bfsc_config_default.argtypes = [P(Config)]
+            lib.bfsc_config_default.restype = None
             _lib = lib
     return _lib
 
 
 def exported_symbols():
-    return list(_SIGS) + ["bfsc_status_string"]
+    return list(_SIGS) + ["bfsc_status_string", "bfsc_config_default"]
+
+
+def default_config() -> Config:
+    c = Config()
+    load().bfsc_config_default(ctypes.byref(c))
+    return c
 
 
 class BfscError(RuntimeError):

@@ -1,5 +1,6 @@
 // C-ABI entry points of libbfsc.so: argument checks on the host, workspace
 // carving, and kernel launches on the caller's stream (declared in bfsc.h).
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -59,11 +60,106 @@ static bool batch_ok(const bfsc_batch *b) {
            b->max_ids < (1ull << 40);
 }
 
+// ------------------------------------------------------------------ tune cache
+// One line per device: "<arch name> <compute units> enc_waves enc_wg_per_cu
+// dec_waves dec_wg_per_cu enc_pack dec_mode".
+
+static void device_key(int device, char *arch, size_t cap, int *n_cu) {
+    hipDeviceProp_t prop;
+    arch[0] = 0;
+    *n_cu = 0;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return;
+    snprintf(arch, cap, "%s", prop.gcnArchName);
+    for (char *q = arch; *q; ++q)
+        if (*q == ' ' || *q == '\n') *q = '_';
+    *n_cu = prop.multiProcessorCount;
+}
+
+static bool tune_valid(const bfsc_tune *t);
+
+static void tune_cache_load(bfsc_ctx *c) {
+    if (!c->cfg.autotune || !c->tune_cache[0]) return;
+    FILE *f = fopen(c->tune_cache, "r");
+    if (!f) return;
+    char arch[256], want[256], line[512];
+    int n_cu = 0, want_cu = 0;
+    device_key(c->device, want, sizeof want, &want_cu);
+    while (fgets(line, sizeof line, f)) {
+        bfsc_tune t;
+        if (sscanf(line, "%255s %d %u %u %u %u %u %u", arch, &n_cu, &t.enc_waves, &t.enc_wg_per_cu,
+                   &t.dec_waves, &t.dec_wg_per_cu, &t.enc_pack, &t.dec_mode) == 8 &&
+            n_cu == want_cu && strcmp(arch, want) == 0 && tune_valid(&t))
+            c->tune = t;
+    }
+    fclose(f);
+}
+
+namespace bfsc {
+// Rewrites the cache file with this device's line replaced (other devices'
+// lines kept).  Best effort: a file that cannot be written is left alone.
+void tune_cache_store(const bfsc_ctx *c) {
+    if (!c->cfg.autotune || !c->tune_cache[0]) return;
+    char want[256];
+    int want_cu = 0;
+    device_key(c->device, want, sizeof want, &want_cu);
+    char keep[64][512];
+    int nk = 0;
+    if (FILE *f = fopen(c->tune_cache, "r")) {
+        char line[512], arch[256];
+        int n_cu = 0;
+        while (nk < 64 && fgets(line, sizeof line, f)) {
+            if (sscanf(line, "%255s %d", arch, &n_cu) == 2 && !(n_cu == want_cu && strcmp(arch, want) == 0))
+                snprintf(keep[nk++], sizeof keep[0], "%s", line);
+        }
+        fclose(f);
+    }
+    FILE *f = fopen(c->tune_cache, "w");
+    if (!f) return;
+    for (int i = 0; i < nk; ++i) fputs(keep[i], f);
+    const bfsc_tune &t = c->tune;
+    fprintf(f, "%s %d %u %u %u %u %u %u\n", want, want_cu, t.enc_waves, t.enc_wg_per_cu, t.dec_waves,
+            t.dec_wg_per_cu, t.enc_pack, t.dec_mode);
+    fclose(f);
+}
+}  // namespace bfsc
+
+static bool waves_ok(uint32_t w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
+
+static bool tune_valid(const bfsc_tune *t) {
+    return waves_ok(t->enc_waves) && waves_ok(t->dec_waves) && t->enc_wg_per_cu >= 1 && t->enc_wg_per_cu <= 64 &&
+           t->dec_wg_per_cu >= 1 && t->dec_wg_per_cu <= 64 && t->enc_pack <= 7 && t->dec_mode <= 7;
+}
+
+// The selection mode a call asks for (BFSC_SEL_DEFAULT: the context's).
+static int sel_mode(const bfsc_ctx *ctx, int mode) { return mode == BFSC_SEL_DEFAULT ? ctx->cfg.selector : mode; }
+
 extern "C" {
 
-int bfsc_create(bfsc_ctx **out, int device) {
+void bfsc_config_default(bfsc_config *cfg) {
+    if (!cfg) return;
+    cfg->selector = BFSC_SEL_EXHAUSTIVE;
+    cfg->raw_below = 32;
+    cfg->resolve_literal = 0;
+    cfg->autotune = 0;
+    cfg->tune_cache = nullptr;
+}
+
+int bfsc_get_config(const bfsc_ctx *ctx, bfsc_config *cfg) {
+    if (!ctx || !cfg) return BFSC_E_INVAL;
+    *cfg = ctx->cfg;
+    return BFSC_OK;
+}
+
+int bfsc_create(bfsc_ctx **out, int device, const bfsc_config *cfg) {
     if (!out) return BFSC_E_INVAL;
     *out = nullptr;
+    bfsc_config conf;
+    bfsc_config_default(&conf);
+    if (cfg) conf = *cfg;
+    if (conf.selector < BFSC_SEL_PLAIN_BP || conf.selector > BFSC_SEL_LEARNED || conf.raw_below > kMaxRawBelow ||
+        conf.resolve_literal > 1 || conf.autotune > 1 ||
+        (conf.tune_cache && strlen(conf.tune_cache) >= sizeof(((bfsc_ctx *)0)->tune_cache)))
+        return BFSC_E_INVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BFSC_E_INVAL;
     HIP_OK(hipSetDevice(device));
@@ -100,6 +196,10 @@ int bfsc_create(bfsc_ctx **out, int device) {
     c->tune.dec_wg_per_cu = 8;
     c->tune.enc_pack = 6;
     c->tune.dec_mode = 3;
+    c->cfg = conf;
+    if (conf.tune_cache) snprintf(c->tune_cache, sizeof c->tune_cache, "%s", conf.tune_cache);
+    c->cfg.tune_cache = c->tune_cache[0] ? c->tune_cache : nullptr;
+    tune_cache_load(c);
     *out = c;
     return BFSC_OK;
 }
@@ -222,6 +322,7 @@ int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *b
 int bfsc_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes,
                 uint64_t *fallbacks_dev, void *ws, void *stream) {
     if (!ctx || !batch_ok(b) || !classes || !ws) return BFSC_E_INVAL;
+    mode = sel_mode(ctx, mode);
     if (mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     Plan p;
@@ -252,13 +353,22 @@ int bfsc_encode_bound(uint64_t n_ids, uint32_t nseg, size_t *bytes) {
 int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int mode, uint8_t *out,
                 size_t out_cap, uint64_t *seg_byte_off, void *ws, void *stream) {
     if (!ctx || !batch_ok(b) || !out || !seg_byte_off || !ws) return BFSC_E_INVAL;
+    mode = sel_mode(ctx, mode);
     if (((uintptr_t)out & 3) || mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED) return BFSC_E_INVAL;
+    if (mode == BFSC_SEL_LEARNED && !classes && !b->seg_level) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     Plan p;
     plan_layout(ws, b->max_ids, b->nseg, true, &p);
+    p.raw_below = ctx->cfg.raw_below;
     int st = launch_plan_prep(b, p, ctx->err, true, S(stream));
     if (st) return st;
-    if (mode == BFSC_SEL_LEARNED && !classes && !b->seg_level) return BFSC_E_INVAL;
+    if (mode == BFSC_SEL_LEARNED && !classes && ctx->cfg.resolve_literal) {
+        // literal widths are not a selection kind of the fused pass: select
+        // into the workspace first
+        st = launch_select(ctx, b, BFSC_SEL_LEARNED, p.cls_buf, nullptr, nullptr, p, S(stream));
+        if (st) return st;
+        classes = p.cls_buf;
+    }
     return launch_encode(ctx, b, classes, mode, out, out_cap, seg_byte_off, p, S(stream));
 }
 
@@ -272,6 +382,40 @@ int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, 
 }
 
 int bfsc_mlp_param_count(void) { return kNParams; }
+
+// Counter-based SplitMix64 draw (Steele, Lea & Flood, OOPSLA 2014): the
+// finaliser applied to seed + G (stream + 1), then to that key + G (idx + 1).
+static uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static uint64_t ctr64(uint64_t seed, uint64_t stream, uint64_t idx) {
+    const uint64_t G = 0x9E3779B97F4A7C15ull;
+    return mix64(mix64(seed + G * (stream + 1)) + G * (idx + 1));
+}
+
+int bfsc_mlp_init(bfsc_ctx *ctx, uint64_t seed) {
+    if (!ctx) return BFSC_E_INVAL;
+    static const int dims[4] = {kIn, kH, kH, kOut};
+    float *h = (float *)calloc(kNParams, sizeof(float));
+    if (!h) return BFSC_E_HIP;
+    size_t k = 0;
+    for (int l = 0; l < 3; ++l) {
+        const uint64_t nw = (uint64_t)dims[l] * dims[l + 1];
+        const float lim = (float)sqrt(6.0 / dims[l]);
+        for (uint64_t i = 0; i < nw; ++i) {
+            const double u = (double)(ctr64(seed, 100 + l, i) >> 40) * 0x1.0p-24;
+            h[k++] = (float)((double)lim * (2.0 * u - 1.0));
+        }
+        k += dims[l + 1];  // biases stay 0
+    }
+    const int st = bfsc_mlp_set_weights(ctx, h);
+    free(h);
+    return st;
+}
 
 int bfsc_mlp_set_weights(bfsc_ctx *ctx, const float *host_params) {
     if (!ctx || !host_params) return BFSC_E_INVAL;
@@ -333,14 +477,8 @@ int bfsc_get_tune(const bfsc_ctx *ctx, bfsc_tune *out) {
     return BFSC_OK;
 }
 
-static bool waves_ok(uint32_t w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
-
 int bfsc_set_tune(bfsc_ctx *ctx, const bfsc_tune *t) {
-    if (!ctx || !t) return BFSC_E_INVAL;
-    if (!waves_ok(t->enc_waves) || !waves_ok(t->dec_waves) || t->enc_wg_per_cu < 1 ||
-        t->enc_wg_per_cu > 64 || t->dec_wg_per_cu < 1 || t->dec_wg_per_cu > 64 || t->enc_pack > 7 ||
-        t->dec_mode > 7)
-        return BFSC_E_INVAL;
+    if (!ctx || !t || !tune_valid(t)) return BFSC_E_INVAL;
     ctx->tune = *t;
     return BFSC_OK;
 }

@@ -53,14 +53,18 @@ struct PlanArgs {
     uint32_t *err;
 };
 
-// One workgroup: per-segment block / group / tile bases.
+// One workgroup: per-segment block / group / tile / fixed-word bases.  A
+// segment of n IDs is empty (n = 0: no bytes), raw (n below the compression
+// threshold: its n IDs) or compressed (16-byte header, 8 bytes of directory
+// per block, the group table and the payloads).
 __global__ __launch_bounds__(1024) void k_plan_prep(PlanArgs a) {
     const uint32_t tid = threadIdx.x;
     __shared__ uint32_t s_tmp[17];
-    uint32_t cb = 0, cg = 0, ct = 0;
+    uint32_t cb = 0, cg = 0, ct = 0, cf = 0;
+    const uint32_t T = a.p.raw_below;
     for (uint32_t base = 0; base < a.nseg; base += blockDim.x) {
         const uint32_t r = base + tid;
-        uint32_t nb = 0, ng = 0, nt = 0;
+        uint32_t nb = 0, ng = 0, nt = 0, nf = 0;
         if (r < a.nseg) {
             const uint64_t s = a.seg_off[r], e = a.seg_off[r + 1];
             const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
@@ -68,22 +72,28 @@ __global__ __launch_bounds__(1024) void k_plan_prep(PlanArgs a) {
             const uint32_t n = bad ? 0u : (uint32_t)(e - s);
             if (bad) raise_err(a.err, kErrInval);
             a.p.seg_n[r] = n;
+            const bool raw = n < T;  // (an empty segment too: no groups)
             nb = cdiv32(n, kBlock);
-            ng = cdiv32(nb, kGroup);
+            ng = raw ? 0u : cdiv32(nb, kGroup);
             nt = ng ? ng : 1u;
+            nf = raw ? n : 4u + 2u * nb;
+            if (n == 0) nf = 0;
         }
-        uint32_t tb, tg, tt;
+        uint32_t tb, tg, tt, tf;
         const uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
         const uint32_t xg = wg_excl_scan(ng, s_tmp, &tg);
         const uint32_t xt = wg_excl_scan(nt, s_tmp, &tt);
+        const uint32_t xf = wg_excl_scan(nf, s_tmp, &tf);
         if (r < a.nseg) {
             a.p.blk_base[r] = cb + xb;
             a.p.grp_base[r] = cg + xg;
             a.p.tile_base[r] = ct + xt;
+            a.p.fix_base[r] = cf + xf;
         }
         cb += tb;
         cg += tg;
         ct += tt;
+        cf += tf;
     }
     if (tid == 0) {
         // inconsistent offsets (totals beyond what max_ids allows) disable
@@ -93,6 +103,7 @@ __global__ __launch_bounds__(1024) void k_plan_prep(PlanArgs a) {
         if (over) raise_err(a.err, kErrInval);
         a.p.blk_base[a.nseg] = cb;
         a.p.grp_base[a.nseg] = cg;
+        a.p.fix_base[a.nseg] = cf;
         a.p.tile_base[a.nseg] = over ? 0u : ct;
         a.p.counter[0] = 0;
     }
@@ -943,6 +954,7 @@ struct SegCursor {
     uint32_t r = 0, t_first = 0, t_next = 0;
     bool have = false;
     uint32_t bb = 0, nb = 0, n = 0, lo = 0, hi = 0;
+    uint32_t form = 0;  // decoder: 1 raw, 2 compressed
     uint64_t base = 0, S = 0, bytes = 0;
     __device__ __forceinline__ bool seek(const uint32_t *tile_base, uint32_t nseg, uint32_t t, uint32_t lane,
                                          bool jump) {
@@ -992,8 +1004,9 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
         const uint32_t t = u >> 1, h = u & 1;
         if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
             c.bb = readfirst(a.p.blk_base[c.r]);
-            c.nb = readfirst(a.p.blk_base[c.r + 1]) - c.bb;
             c.n = readfirst(a.p.seg_n[c.r]);
+            // a raw segment's IDs are copied by the place pass: no blocks
+            c.nb = c.n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[c.r + 1]) - c.bb;
             c.lo = readfirst(a.seg_lo[c.r]);
             c.hi = readfirst(a.seg_hi[c.r]);
             c.base = readfirst64(a.seg_off[c.r]);
@@ -1166,8 +1179,9 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
         const uint32_t t = u >> 1, h = u & 1;
         if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
             c.bb = readfirst(a.p.blk_base[c.r]);
-            c.nb = readfirst(a.p.blk_base[c.r + 1]) - c.bb;
             c.n = readfirst(a.p.seg_n[c.r]);
+            // a raw segment's IDs are copied by the place pass: no blocks
+            c.nb = c.n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[c.r + 1]) - c.bb;
             c.lo = readfirst(a.seg_lo[c.r]);
             c.hi = readfirst(a.seg_hi[c.r]);
             c.base = readfirst64(a.seg_off[c.r]);
@@ -1309,9 +1323,10 @@ __device__ __forceinline__ uint64_t chunk_prefix(const uint32_t *chunk_words, ui
 
 // Place pass, one wave per tile (tiles are independent, so every wave's
 // chain of dependent loads runs in parallel with all others): the segment's
-// header and start offset (written by its first tile), then the tile's
-// directory entries, group-table entry and payload words, copied from the
-// two halves of its slot to their final position.
+// start offset (written by its first tile), then for a compressed segment
+// its header (first tile), the tile's directory entries, group-table entry
+// and payload words, copied from the two halves of its slot to their final
+// position; for a raw segment its IDs, copied from the input.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1341,32 +1356,58 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
     const uint32_t dirw = lane < kSlotDirWords ? slot[lane] : 0u;
     const uint32_t r = readfirst(ts.x);
     const uint32_t t_first = readfirst(ts.y);
+    const uint32_t n = readfirst(a.p.seg_n[r]);
     const uint32_t bb = readfirst(a.p.blk_base[r]);
     const uint32_t nb = readfirst(a.p.blk_base[r + 1]) - bb;
     const uint32_t gb = readfirst(a.p.grp_base[r]);
     const uint32_t ng = readfirst(a.p.grp_base[r + 1]) - gb;
+    const uint32_t fb = readfirst(a.p.fix_base[r]);
     // payload words before the segment and before the tile (unit 2t)
     const uint32_t cf = 2 * t_first / kScanChunk, ct = 2 * t / kScanChunk;
     const uint64_t Pf = chunk_prefix(a.p.chunk_words, cf, lane);
     const uint64_t P = Pf + readfirst(a.p.unit_off[2 * t_first]);
     const uint64_t Pt = (ct == cf ? Pf : chunk_prefix(a.p.chunk_words, ct, lane)) + readfirst(a.p.unit_off[2 * t]);
-    const uint64_t sw = (16ull * r + 8ull * bb + 4ull * gb + 4ull * P) >> 2;
+    const uint64_t sw = (uint64_t)fb + gb + P;
     const uint32_t g = t - t_first;
     if (t == 0) {
         // the batch end, from the totals of all chunks
         const uint32_t units = 2 * total;
         const uint64_t words = chunk_prefix(a.p.chunk_words, (units + kScanChunk - 1) / kScanChunk, lane);
         if (lane == 0) {
-            const uint64_t end = 16ull * a.nseg + 8ull * a.p.blk_base[a.nseg] + 4ull * a.p.grp_base[a.nseg] +
-                                 4ull * words;
+            const uint64_t end = 4ull * ((uint64_t)a.p.fix_base[a.nseg] + a.p.grp_base[a.nseg] + words);
             a.seg_byte_off[a.nseg] = end;
             if (end > a.out_cap) raise_err(a.err, kErrCapacity);
         }
     }
+    if (g == 0 && lane == 0) a.seg_byte_off[r] = sw << 2;
+    if (n == 0) return;
+    if (n < a.p.raw_below) {
+        // raw form: the IDs as they are (one tile per raw segment), checked
+        // as the pack pass checks the others: strictly increasing, inside
+        // [lo, hi)
+        const uint32_t *ids = a.ids + a.seg_off[r];
+        const uint32_t lo = readfirst(a.seg_lo[r]), hi = readfirst(a.seg_hi[r]);
+        const bool fits = sw + n <= capw;
+        bool bad = false;
+        uint32_t carry = 0;
+        for (uint32_t q0 = 0; q0 < n; q0 += 64) {
+            const uint32_t q = q0 + lane;
+            const bool in = q < n;
+            const uint32_t v = in ? ids[q] : 0u;
+            const uint32_t pv = pin(lane_prev(v, carry));
+            bad |= in & ((v < lo) | (v >= hi) | ((q > 0) & (v <= pv)));
+            if (in && fits) a.out[sw + q] = v;
+            carry = readlane(v, 63);
+        }
+        if (lane == 0) {
+            if (!fits) raise_err(a.err, kErrCapacity);
+        }
+        if (ballot(bad) != 0ull && lane == 0) raise_err(a.err, kErrInval);
+        return;
+    }
     if (g == 0 && lane < 4) {
-        if (lane == 0) a.seg_byte_off[r] = sw << 2;
         if (sw + 4 <= capw) {
-            const uint32_t hv = lane == 0 ? a.p.seg_n[r] : lane == 1 ? a.seg_lo[r] : lane == 2 ? a.seg_hi[r] : kMagic;
+            const uint32_t hv = lane == 0 ? n : lane == 1 ? a.seg_hi[r] : lane == 2 ? a.seg_lo[r] : kMagic;
             a.out[sw + lane] = hv;
         }
     }
@@ -1409,6 +1450,7 @@ struct SelArgs {
     const MlpMfma *w;         // the network in MFMA operand order (learned mode)
     Plan p;
     uint32_t *err;
+    uint32_t literal;         // learned mode: keep a predicted width that holds the block
 };
 
 template <int WAVES>
@@ -1521,7 +1563,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
                         res = s_ex[bi];
                     }
                 } else if (best <= 33) {
-                    res = 1u + wmin;
+                    if (!a.literal || best - 1u >= wmin) {
+                        res = a.literal ? best : 1u + wmin;
+                    } else {
+                        fb = true;
+                        res = s_ex[bi];
+                    }
                 } else {
                     res = kClsPfor;
                 }
@@ -1544,10 +1591,16 @@ struct DecPlanArgs {
     uint64_t out_cap;
     uint64_t *out_off;
     uint32_t *seg_n;      // 0 for bad / empty
+    uint32_t *seg_form;   // 0 empty or bad, 1 raw, 2 compressed
     uint32_t *tile_base;  // [nseg+1]
     uint32_t *err;
 };
 
+// One workgroup: each segment's form, ID count and tiles (a group of 16
+// blocks of a compressed segment, or the whole of a raw one), and the
+// output offsets.  A segment of L bytes is empty if L = 0; raw if L < 16 or
+// its words 1 and 2 increase (IDs strictly increase); compressed if they
+// decrease (header n, hi, lo, magic with hi > lo).
 __global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
     __shared__ uint32_t s_tmp[17];
     __shared__ unsigned long long s_w[16];
@@ -1560,20 +1613,34 @@ __global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
         uint32_t n = 0, ng = 0;
         if (r < a.nseg) {
             const uint64_t s = a.seg_byte_off[r], e = a.seg_byte_off[r + 1];
-            bool bad = e < s || e - s < 16 || (s & 3) || (e & 3);
-            if (!bad) {
+            bool bad = e < s || (s & 3) || (e & 3);
+            uint32_t form = 0;
+            if (!bad && e > s) {
+                const uint64_t L = e - s;
                 const uint32_t *h = (const uint32_t *)(a.in + s);
-                const uint32_t hn = h[0], lo = h[1], hi = h[2], mg = h[3];
-                const uint64_t nb = cdiv32(hn, kBlock) + 0ull;
-                const uint64_t meta = 16ull + 8ull * nb + 4ull * ((nb + kGroup - 1) / kGroup);
-                bad = mg != kMagic || lo > hi || hn > hi - lo || meta > e - s;
-                if (!bad) {
+                if (L < 16 || h[1] < h[2]) {
+                    bad = L / 4 > 0xFFFFFFFFull;
+                    n = (uint32_t)(L / 4);
+                    ng = 1;
+                    form = 1;
+                } else {
+                    const uint32_t hn = h[0], hi = h[1], lo = h[2], mg = h[3];
+                    const uint64_t nb = cdiv32(hn, kBlock) + 0ull;
+                    const uint64_t meta = 16ull + 8ull * nb + 4ull * ((nb + kGroup - 1) / kGroup);
+                    bad = mg != kMagic || lo >= hi || hn == 0 || hn > hi - lo || meta > L;
                     n = hn;
                     ng = (uint32_t)((nb + kGroup - 1) / kGroup);
+                    form = 2;
                 }
             }
-            if (bad) raise_err(a.err, kErrCorrupt);
+            if (bad) {
+                raise_err(a.err, kErrCorrupt);
+                n = 0;
+                ng = 0;
+                form = 0;
+            }
             a.seg_n[r] = n;
+            a.seg_form[r] = form;
         }
         uint32_t tt;
         const uint32_t xt = wg_excl_scan(ng, s_tmp, &tt);
@@ -1616,6 +1683,7 @@ struct DecArgs {
     const uint64_t *seg_byte_off;
     uint32_t nseg;
     const uint32_t *seg_n;
+    const uint32_t *seg_form;
     const uint32_t *tile_base;
     const uint64_t *out_off;
     uint32_t *out;
@@ -1956,6 +2024,24 @@ __device__ __forceinline__ void dec_unit_r(const uint32_t *win, uint32_t *val, u
     }
 }
 
+// A raw segment: its n words are the IDs, which must strictly increase;
+// the wave copies them 64 at a time.
+__device__ __forceinline__ void dec_raw(const uint32_t *src, uint32_t n, uint32_t *out, uint64_t ob,
+                                        uint64_t out_cap, uint32_t *err, uint32_t lane) {
+    uint32_t carry = 0;
+    bool bad = false;
+    for (uint32_t q0 = 0; q0 < n; q0 += 64) {
+        const uint32_t q = q0 + lane;
+        const bool in = q < n;
+        const uint32_t v = in ? src[q] : 0xFFFFFFFFu;
+        const uint32_t pv = pin(lane_prev(v, carry));
+        bad |= in & (q > 0) & (v <= pv);
+        if (in && ob + q < out_cap) out[ob + q] = v;
+        carry = readlane(v, 63);
+    }
+    if (ballot(bad) != 0ull && lane == 0) raise_err(err, kErrCorrupt);
+}
+
 // Decode, one wave per unit (half a group: up to 8 blocks).  The wave reads
 // and checks the group's directory entries (one lane per block) and table
 // words, then decodes the unit's blocks in order.  STAGE: the unit's payload
@@ -1978,12 +2064,20 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
         const uint32_t t = u >> 1, h = u & 1;
         if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
             c.n = readfirst(a.seg_n[c.r]);
+            c.form = readfirst(a.seg_form[c.r]);
             c.S = readfirst64(a.seg_byte_off[c.r]);
             c.bytes = readfirst64(a.seg_byte_off[c.r + 1]) - c.S;
             c.base = readfirst64(a.out_off[c.r]);
-            const uint32_t *sg = (const uint32_t *)(a.in + c.S);
-            c.lo = readfirst(sg[1]);
-            c.hi = readfirst(sg[2]);
+            if (c.form == 2) {
+                const uint32_t *sg = (const uint32_t *)(a.in + c.S);
+                c.hi = readfirst(sg[1]);
+                c.lo = readfirst(sg[2]);
+            }
+        }
+        if (c.form != 2) {
+            // a raw segment's one tile (empty segments have none)
+            if (h == 0) dec_raw((const uint32_t *)(a.in + c.S), c.n, a.out, c.base, a.out_cap, a.err, lane);
+            continue;
         }
         const uint32_t g = t - c.t_first;
         const uint32_t n = c.n;
@@ -2081,7 +2175,8 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
 // The directory side of a decode unit, as read and checked by the wave.
 struct DecUnit {
     uint32_t kind;  // 0: nothing to decode (empty half, or a damaged group, reported)
-                    // 1: full unit (8 blocks of 128 IDs); 2: any other unit
+                    // 1: full unit (8 blocks of 128 IDs); 2: any other unit;
+                    // 3: a raw segment (n IDs at pay)
     uint32_t hb, k0, nb, n, gblk, nblk, lo, hi, ub, ue;
     uint64_t oo, availw;
     const uint32_t *pay;
@@ -2097,12 +2192,25 @@ __device__ __forceinline__ DecUnit dec_dir(const DecArgs &a, SegCursor &c, uint3
     const uint32_t t = u >> 1, h = u & 1;
     if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
         c.n = readfirst(a.seg_n[c.r]);
+        c.form = readfirst(a.seg_form[c.r]);
         c.S = readfirst64(a.seg_byte_off[c.r]);
         c.bytes = readfirst64(a.seg_byte_off[c.r + 1]) - c.S;
         c.base = readfirst64(a.out_off[c.r]);
-        const uint32_t *sg = (const uint32_t *)(a.in + c.S);
-        c.lo = readfirst(sg[1]);
-        c.hi = readfirst(sg[2]);
+        if (c.form == 2) {
+            const uint32_t *sg = (const uint32_t *)(a.in + c.S);
+            c.hi = readfirst(sg[1]);
+            c.lo = readfirst(sg[2]);
+        }
+    }
+    if (c.form != 2) {
+        // a raw segment's one tile: its first unit copies the IDs
+        if (h == 0) {
+            U.kind = 3;
+            U.n = c.n;
+            U.pay = (const uint32_t *)(a.in + c.S);
+            U.oo = c.base;
+        }
+        return U;
     }
     const uint32_t g = t - c.t_first;
     const uint32_t n = c.n;
@@ -2236,6 +2344,8 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_decode_r(DecArgs a) {
                        a.out_cap, a.err, lane);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
+        } else if (U.kind == 3) {
+            dec_raw(U.pay, U.n, a.out, U.oo, a.out_cap, a.err, lane);
         } else if (U.kind == 2) {
             uint32_t pa = 0, pb = 0;
             load_payload(U.pay, U.ub, readlane(U.words, U.hb), lane, pa, pb);
@@ -2401,6 +2511,7 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
     a.w = (const MlpMfma *)ctx->mlp_mfma;
     a.p = p;
     a.err = ctx->err;
+    a.literal = ctx->cfg.resolve_literal;
     const uint32_t grid = persistent_grid(ctx, 4, p.max_tiles);
     const int slot = timing_begin(ctx, feat ? BFSC_OP_FEATURES : BFSC_OP_SELECT, s);
     hipLaunchKernelGGL(k_select<4>, dim3(grid), dim3(256), 0, s, a);
@@ -2410,15 +2521,17 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
 
 size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg) {
     (void)max_ids;
-    return align256(((size_t)nseg + 1) * 4) * 2 + 256;
+    return align256(((size_t)nseg + 1) * 4) * 3 + 256;
 }
 
 int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                   uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
                   void *ws, hipStream_t s) {
     char *wb = (char *)ws;
+    const size_t arr = align256(((size_t)nseg + 1) * 4);
     uint32_t *seg_n = (uint32_t *)wb;
-    uint32_t *tile_base = (uint32_t *)(wb + align256(((size_t)nseg + 1) * 4));
+    uint32_t *tile_base = (uint32_t *)(wb + arr);
+    uint32_t *seg_form = (uint32_t *)(wb + 2 * arr);
     DecPlanArgs pa;
     pa.in = in;
     pa.seg_byte_off = seg_byte_off;
@@ -2426,6 +2539,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     pa.out_cap = out_cap;
     pa.out_off = out_off;
     pa.seg_n = seg_n;
+    pa.seg_form = seg_form;
     pa.tile_base = tile_base;
     pa.err = ctx->err;
     hipLaunchKernelGGL(k_dec_prep, dim3(1), dim3(1024), 0, s, pa);
@@ -2434,6 +2548,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     a.seg_byte_off = seg_byte_off;
     a.nseg = nseg;
     a.seg_n = seg_n;
+    a.seg_form = seg_form;
     a.tile_base = tile_base;
     a.out_off = out_off;
     a.out = out_ids;

@@ -147,8 +147,10 @@ __device__ __forceinline__ uint32_t upper_bound_m1(const uint32_t *base, uint32_
 // ------------------------------------------------------------------ batch plan
 
 // Per-batch tiling computed by the prep kernel into the workspace.  A tile is
-// one group of up to 16 blocks of one segment; an empty segment gets one
-// tile without blocks (so that someone writes its header).  The pack pass
+// one group of up to 16 blocks of one compressed segment; an empty or a raw
+// segment (fewer IDs than the compression threshold) gets one tile without
+// blocks, whose place wave writes the segment's offset and copies a raw
+// segment's IDs.  The pack pass
 // works on units, the two halves of a tile (8 blocks each), and puts each
 // unit's payload into its own half of the tile's private slot; one
 // workgroup then turns the unit sizes into output offsets, and the slots are
@@ -163,8 +165,11 @@ constexpr uint32_t kSlotWords = kSlotDirWords + 2 * kSlotHalfWords;
 constexpr uint32_t kScanChunk = 4096;
 
 struct Plan {
-    uint32_t *blk_base;   // [nseg+1] first global block of each segment
-    uint32_t *grp_base;   // [nseg+1] first global group
+    uint32_t *blk_base;   // [nseg+1] first global block of each segment (raw segments'
+                          // blocks included: the index into a class vector)
+    uint32_t *grp_base;   // [nseg+1] first global group (compressed segments only)
+    uint32_t *fix_base;   // [nseg+1] output words before the segment taken by the headers
+                          // and directories of compressed segments and the IDs of raw ones
     uint32_t *tile_base;  // [nseg+1] first tile
     uint32_t *seg_n;      // [nseg]   IDs per segment (0 for a rejected segment)
     uint32_t *counter;    // [4]      [0]: workgroups done with the pack pass
@@ -174,8 +179,15 @@ struct Plan {
     uint2 *tile_seg;      // [max_tiles] segment of each tile and the segment's first tile,
                           // written by the pack pass (encode only)
     uint32_t *slots;      // [max_tiles][kSlotWords] (encode only)
+    uint8_t *cls_buf;     // [max blocks] a class vector (encode only: the learned choice
+                          // with literal widths runs as a separate pass into it)
     uint32_t max_tiles;
+    uint32_t raw_below;   // compression threshold: segments of 1 .. raw_below-1 IDs are raw
 };
+
+// Largest compression threshold: a raw segment's blocks then fit the one
+// tile it gets (the selection pass covers them tile by tile).
+constexpr uint32_t kMaxRawBelow = kBlock * kGroup;
 
 __host__ __device__ inline uint64_t plan_max_tiles(uint64_t max_ids, uint32_t nseg) {
     return max_ids / (kBlock * kGroup) + 2ull * nseg + 2;
@@ -195,6 +207,8 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     off = align256(off + n1 * 4);
     if (p) p->grp_base = (uint32_t *)(b + off);
     off = align256(off + n1 * 4);
+    if (p) p->fix_base = (uint32_t *)(b + off);
+    off = align256(off + n1 * 4);
     if (p) p->tile_base = (uint32_t *)(b + off);
     off = align256(off + n1 * 4);
     if (p) p->seg_n = (uint32_t *)(b + off);
@@ -211,7 +225,10 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     if (slots) off = align256(off + mt * 8);
     if (p) p->slots = slots ? (uint32_t *)(b + off) : nullptr;
     if (slots) off = align256(off + mt * (size_t)kSlotWords * 4);
+    if (p) p->cls_buf = slots ? (uint8_t *)(b + off) : nullptr;
+    if (slots) off = align256(off + (max_ids + kBlock - 1) / kBlock + nseg);
     if (p) p->max_tiles = (uint32_t)mt;
+    if (p) p->raw_below = 0;
     return off;
 }
 
@@ -230,6 +247,8 @@ struct bfsc_ctx {
     void *mlp_mfma;         // device: the fp16 weights in MFMA operand order + biases
     uint32_t adam_t;
     bfsc_tune tune;
+    bfsc_config cfg;          // settings from bfsc_create (cfg.tune_cache -> tune_cache)
+    char tune_cache[1024];
     // per-kernel event timing (bfsc_timing_enable / bfsc_timing_read)
     int timing;
     uint32_t n_timed;
@@ -241,6 +260,8 @@ struct bfsc_ctx {
 };
 
 namespace bfsc {
+// Stores the context's launch shapes in its tune cache file (if configured).
+void tune_cache_store(const bfsc_ctx *c);
 // Brackets one kernel launch with an event pair on stream s when timing is
 // on; returns the slot (or -1).
 int timing_begin(bfsc_ctx *ctx, int op, hipStream_t s);

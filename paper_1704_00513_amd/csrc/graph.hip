@@ -81,17 +81,19 @@ int enqueue_step(bfsc_pipeline *P, int p, hipStream_t s) {
     b.max_ids = V;
     Plan plan;
     plan_layout(P->enc_ws, V, P->nseg, true, &plan);
+    plan.raw_below = ctx->cfg.raw_below;
     st = launch_plan_prep(&b, plan, ctx->err, false, s);
     if (st) return st;
     const uint8_t *cls = nullptr;
-    int mode = P->mode;
-    if (P->mode == BFSC_SEL_LEARNED) {
+    if (P->mode == BFSC_SEL_LEARNED && ctx->cfg.resolve_literal) {
+        // literal widths: a separate selection pass (the fused pack pass
+        // snaps widths to the minimal one)
         st = launch_select(ctx, &b, BFSC_SEL_LEARNED, P->classes, nullptr, nullptr, plan, s);
         if (st) return st;
         cls = P->classes;
-        mode = BFSC_SEL_EXHAUSTIVE;
     }
-    st = launch_encode(ctx, &b, cls, mode, P->out, P->out_cap, P->sbo, plan, s);
+    // learned choice otherwise inside the pack pass, on the matrix cores
+    st = launch_encode(ctx, &b, cls, P->mode, P->out, P->out_cap, P->sbo, plan, s);
     if (st) return st;
     st = launch_decode(ctx, P->out, P->sbo, P->nseg, V, P->dec, V, P->doff, P->dec_ws, s);
     if (st) return st;
@@ -136,6 +138,7 @@ extern "C" {
 
 int bfsc_pipeline_create(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *bounds_host, uint32_t nseg,
                          int mode, int use_graph, bfsc_pipeline **out) {
+    if (ctx && mode == BFSC_SEL_DEFAULT) mode = ctx->cfg.selector;
     if (!ctx || !g || !bounds_host || !out || nseg == 0 || g->n_vertices == 0 ||
         g->n_vertices > 0x7FFFFFFFu || mode < BFSC_SEL_PLAIN_BP || mode > BFSC_SEL_LEARNED)
         return BFSC_E_INVAL;
@@ -364,6 +367,7 @@ int bfsc_autotune(bfsc_ctx *ctx, const bfsc_batch *sample, void *ws, void *strea
     }
     ctx->timing = timing;
     ctx->tune = st ? keep : best;
+    if (!st) tune_cache_store(ctx);
     hipStreamSynchronize(s);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);

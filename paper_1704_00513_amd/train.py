@@ -100,7 +100,7 @@ def train(ctx, P, torch, X, y, epochs=8, batch=8192, lr=1e-3, seed=1):
     X, y = X[perm], y[perm]
     Xd = torch.from_numpy(np.ascontiguousarray(X).view(np.int16)).cuda()
     yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
-    ctx.mlp_set_weights(inputs.mlp_init(seed))
+    ctx.mlp_init(seed)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     ws = ctx.workspace(P.OP_MLP, batch, 0, key="mlp")
     N = X.shape[0]

@@ -87,3 +87,21 @@ def shifted_batch(b, shift):
         buf[shift:shift + ids.size] = t.from_numpy(ids.view(np.int32)).to("cuda")
     view = buf[shift:shift + max(ids.size, 1)]
     return DeviceBatch(view, dev.seg_off, dev.seg_lo, dev.seg_hi, dev.seg_level, max_ids=dev.max_ids), buf
+
+
+def stream_classes(stream, sbo, seg_off):
+    """The class of every block of a batch as its compressed stream records
+    it (directory entries); blocks of raw and empty segments get 0, which an
+    encoder skips."""
+    stream = np.ascontiguousarray(stream, np.uint8)
+    sizes = np.diff(np.asarray(seg_off, np.int64))
+    out = []
+    for r, n in enumerate(sizes):
+        nb = (int(n) + 127) // 128
+        s0, s1 = int(sbo[r]), int(sbo[r + 1])
+        w = stream[s0:s1].view(np.uint32) if s1 > s0 else np.zeros(0, np.uint32)
+        if w.size >= 4 and w[1] > w[2]:
+            out.extend(int(w[4 + 2 * k + 1]) & 0xFF for k in range(nb))
+        else:
+            out.extend([0] * nb)
+    return np.array(out, np.uint8)

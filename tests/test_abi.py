@@ -52,10 +52,10 @@ def test_encode_bound_matches_oracle_bound_and_holds(lib):
 def test_status_strings_and_host_errors(lib):
     lib.bfsc_status_string.restype = ctypes.c_char_p
     assert lib.bfsc_status_string(3) == b"corrupt compressed stream"
-    lib.bfsc_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+    from paper_1704_00513_amd import _lib
     h = ctypes.c_void_p()
-    assert lib.bfsc_create(None, 0) == 1          # NULL out -> INVAL
-    assert lib.bfsc_create(ctypes.byref(h), -1) == 1
+    assert lib.bfsc_create(None, 0, None) == 1          # NULL out -> INVAL
+    assert lib.bfsc_create(ctypes.byref(h), -1, None) == 1
     lib.bfsc_mlp_param_count.restype = ctypes.c_int
     assert lib.bfsc_mlp_param_count() == 7011
 
@@ -81,3 +81,21 @@ def test_exchange_key_space_limit_is_checked_on_the_host(lib):
     bfs = ctypes.c_size_t()
     assert lib.bfsc_bfs_workspace_size(ctypes.byref(csr), ctypes.byref(bfs)) == 0
     assert bfs.value >= 3 * ((1 << 26) - 32) // 8  # visited, next-level and frontier bitmaps
+
+
+def test_config_defaults_and_range_checks(lib):
+    """bfsc_config: the defaults, and settings out of range refused on the
+    host before any device is touched."""
+    from paper_1704_00513_amd import _lib
+    c = _lib.default_config()
+    assert (c.selector, c.raw_below, c.resolve_literal, c.autotune, c.tune_cache) == (1, 32, 0, 0, None)
+    assert c.raw_below == _lib.RAW_BELOW == oracle.RAW_BELOW
+    h = ctypes.c_void_p()
+    for field, bad in (("selector", 3), ("selector", -1), ("raw_below", 2049), ("resolve_literal", 2),
+                       ("autotune", 5)):
+        c = _lib.default_config()
+        setattr(c, field, bad)
+        assert lib.bfsc_create(ctypes.byref(h), 0, ctypes.byref(c)) == 1, field
+    c = _lib.default_config()
+    c.tune_cache = b"x" * 2000  # longer than the context keeps
+    assert lib.bfsc_create(ctypes.byref(h), 0, ctypes.byref(c)) == 1

@@ -9,7 +9,7 @@ import pytest
 import inputs
 import oracle
 
-from gpu_util import gpu_encode
+from gpu_util import gpu_encode, stream_classes
 
 pytestmark = pytest.mark.gpu
 
@@ -22,11 +22,17 @@ def ctx():
     c.close()
 
 
-def run_pipeline(ctx, g, root, bounds, use_graph, mode=1):
+def run_pipeline(ctx, g, root, bounds, use_graph, mode=1, theta=None):
+    """theta: the network's weights in learned mode (mode 2): each level's
+    stream must then be the oracle's encoding of the classes its directory
+    records, and those must be the oracle's resolved prediction wherever its
+    top two logits are clearly apart."""
     import paper_1704_00513_amd as P
+    from oracle import mlp
     dg = P.DeviceGraph.from_host(g)
     pipe = P.Pipeline(ctx, dg, bounds, mode=mode, use_graph=use_graph)
     olevel, _, depth = oracle.bfs(g, root)
+    checked = 0
     pipe.start(root)
     L = 0
     n = 1
@@ -38,7 +44,20 @@ def run_pipeline(ctx, g, root, bounds, use_graph, mode=1):
         np.testing.assert_array_equal(got["frontier"], front)
         ob = oracle.batch_from_frontier(front, bounds, L)
         np.testing.assert_array_equal(got["seg_off"], ob.seg_off)
-        want, want_off = oracle.encode(ob, mode=mode)
+        if mode == 2:
+            cls = stream_classes(got["stream"], got["seg_byte_off"], ob.seg_off)
+            want, want_off = oracle.encode(ob, classes=cls)
+            X = mlp.features_to_f64(oracle.features(ob))
+            z, _ = mlp.forward(theta, X)
+            res, _ = oracle.resolve(ob, mlp.predict(theta, X))
+            top2 = np.sort(z, axis=1)[:, -2:]
+            clear = (top2[:, 1] - top2[:, 0]) > 2e-3 * (1 + np.abs(top2[:, 1]))
+            sizes = np.diff(ob.seg_off.astype(np.int64))
+            comp = np.repeat(sizes >= oracle.RAW_BELOW, (sizes + 127) // 128)
+            np.testing.assert_array_equal(cls[clear & comp], res[clear & comp])
+            checked += int((clear & comp).sum())
+        else:
+            want, want_off = oracle.encode(ob, mode=mode)
         np.testing.assert_array_equal(got["seg_byte_off"], want_off)
         np.testing.assert_array_equal(got["stream"], want)
         np.testing.assert_array_equal(got["decoded"], front)
@@ -50,6 +69,8 @@ def run_pipeline(ctx, g, root, bounds, use_graph, mode=1):
     np.testing.assert_array_equal(lv, olevel)
     assert oracle.bfs_check(g, root, lv, par) == 0
     pipe.close()
+    if mode == 2:
+        assert checked > 0
     return L
 
 
@@ -79,6 +100,22 @@ def test_pipeline_direction_optimizing(ctx, use_graph, alpha, beta):
             run_pipeline(ctx, g, int(root), inputs.bounds_equal(g.n_vertices, 16), use_graph)
     finally:
         ctx.bfs_set_direction(0.0, 0.0)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_pipeline_learned_mode(ctx, use_graph):
+    """The learned choice inside the captured level (fused into the pack
+    pass), with the trained selector."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1704_00513_amd", "selector_weights.npy")
+    theta = np.load(path, allow_pickle=False)
+    ctx.mlp_set_weights(theta)
+    g = inputs.graph(inputs.RMAT, 16, 16, 1)
+    bounds = inputs.bounds_zipf(g.n_vertices, 64, 1)[0]
+    for root in inputs.roots(g, 2, 1):
+        print("pipeline learned graph=%s root=%d" % (use_graph, root), flush=True)
+        run_pipeline(ctx, g, int(root), bounds, use_graph, mode=2, theta=theta.astype(np.float64))
 
 
 def test_pipeline_plain_mode(ctx):
