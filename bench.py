@@ -126,6 +126,29 @@ def build_batch(ctx, P, torch, g, roots, nseg, bounds_kind, seed):
     return b, host, dict(bfs_ms=bfs_ms, bfs_levels=bfs_levels, edges=edges, n_ids=base)
 
 
+def save_batch(b, host, bfs, path):
+    """The frontier batch (host copies) and its BFS figures, as .npy files."""
+    os.makedirs(path, exist_ok=True)
+    np.save(os.path.join(path, "ids.npy"), b.ids[:max(1, b.max_ids)].cpu().numpy().view(np.uint32))
+    for k in ("seg_off", "seg_lo", "seg_hi", "seg_level"):
+        np.save(os.path.join(path, k + ".npy"), host[k])
+    with open(os.path.join(path, "meta.json"), "w") as f:
+        json.dump(bfs, f)
+
+
+def load_batch(P, torch, path):
+    ld = lambda k: np.load(os.path.join(path, k + ".npy"), allow_pickle=False)
+    host = {k: ld(k) for k in ("seg_off", "seg_lo", "seg_hi", "seg_level")}
+    bfs = json.load(open(os.path.join(path, "meta.json")))
+    ids = np.load(os.path.join(path, "ids.npy"), mmap_mode="r", allow_pickle=False)
+    ids_t = torch.from_numpy(np.ascontiguousarray(ids).view(np.int32)).cuda()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    b = P.DeviceBatch(ids_t, t(host["seg_off"].view(np.int64)), t(host["seg_lo"].view(np.int32)),
+                      t(host["seg_hi"].view(np.int32)), t(host["seg_level"].astype(np.int32)),
+                      max_ids=bfs["n_ids"])
+    return b, host, bfs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +173,9 @@ def main():
     ap.add_argument("--tune", action="append", default=[],
                     help="launch shape override, e.g. --tune enc_waves=8 --tune enc_pack=1")
     ap.add_argument("--autotune", action="store_true", help="measure launch shapes on the batch first")
+    ap.add_argument("--batch-cache", default=None,
+                    help="directory keeping the frontier batch between runs (written on the first run, "
+                         "loaded by later ones: profiler passes skip graph generation and BFS)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -162,15 +188,36 @@ def main():
 
     mode = {"exhaustive": P.SEL_EXHAUSTIVE, "plain": P.SEL_PLAIN_BP, "learned": P.SEL_LEARNED}[args.mode]
     kind = inputs.RMAT if args.graph == "rmat" else inputs.UNIFORM
-    t0 = time.time()
-    g = inputs.graph(kind, args.scale, 16, args.seed)
-    log("graph %s scale %d: V=%d arcs=%d (%.1fs)" % (args.graph, args.scale, g.n_vertices, g.n_arcs,
-                                                    time.time() - t0))
-    roots = inputs.roots(g, args.roots, args.seed)
+    workload = "rmat-s%d" % args.scale if args.graph == "rmat" else "uniform-s%d" % args.scale
+    workload += "-%droots-%s%d-%s" % (args.roots, args.bounds, args.nseg, args.mode)
+    graph_state = {}
+
+    def get_graph():
+        if "g" not in graph_state:
+            t0 = time.time()
+            g = inputs.graph(kind, args.scale, 16, args.seed)
+            log("graph %s scale %d: V=%d arcs=%d (%.1fs)" % (args.graph, args.scale, g.n_vertices,
+                                                            g.n_arcs, time.time() - t0))
+            graph_state["g"] = g
+            graph_state["roots"] = inputs.roots(g, args.roots, args.seed)
+        return graph_state["g"], graph_state["roots"]
+
     ctx = P.Context(0)
     if args.bfs == "do":
         ctx.bfs_set_direction(14.0, 24.0)
-    b, host, bfs = build_batch(ctx, P, torch, g, roots, args.nseg, args.bounds, args.seed)
+    # the batch does not depend on the selector: one cache entry per graph,
+    # roots and segment split
+    cache_dir = None
+    if args.batch_cache:
+        cache_dir = os.path.join(args.batch_cache, workload.rsplit("-", 1)[0] + "-" + args.bfs)
+    if cache_dir and os.path.exists(os.path.join(cache_dir, "meta.json")):
+        b, host, bfs = load_batch(P, torch, cache_dir)
+        log("batch loaded from %s" % cache_dir)
+    else:
+        g, roots = get_graph()
+        b, host, bfs = build_batch(ctx, P, torch, g, roots, args.nseg, args.bounds, args.seed)
+        if cache_dir:
+            save_batch(b, host, bfs, cache_dir)
     N = bfs["n_ids"]
     log("batch: %d IDs in %d segments, %d levels; BFS %.2f ms total" % (N, b.nseg, bfs["bfs_levels"],
                                                                        bfs["bfs_ms"]))
@@ -246,8 +293,6 @@ def main():
     pack_kernel = "k_enc_pack_l" if mode == P.SEL_LEARNED else "k_enc_pack_u"
     dom = (pack_kernel, enc_avg) if enc_avg >= dec_avg else ("k_decode_u", dec_avg)
     achieved = alg_bytes / (dom[1] * 1e-3) / 1e9
-    workload = "rmat-s%d" % args.scale if args.graph == "rmat" else "uniform-s%d" % args.scale
-    workload += "-%droots-%s%d-%s" % (args.roots, args.bounds, args.nseg, args.mode)
     traffic = read_traffic(dom[0], workload)
 
     res = {
@@ -298,6 +343,7 @@ def main():
             torch.add(x, 1, out=y)
         torch.cuda.synchronize()
     if not args.no_extra:
+        g, roots = get_graph()
         res["extra"] = extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(b, host, args.cpu_seconds, mode)

@@ -18,29 +18,6 @@ namespace bfsc {
 
 // ------------------------------------------------------------------ scans
 
-// Exclusive prefix sum over a workgroup of up to 1024 threads.
-__device__ uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tmp /*[17]*/, uint32_t *total) {
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t nw = blockDim.x >> 6;
-    const uint32_t incl = wave_incl_scan(v);
-    if (lane == 63) s_tmp[w] = incl;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (uint32_t i = 0; i < nw; ++i) {
-            const uint32_t x = s_tmp[i];
-            s_tmp[i] = acc;
-            acc += x;
-        }
-        s_tmp[16] = acc;
-    }
-    __syncthreads();
-    const uint32_t r = s_tmp[w] + incl - v;
-    *total = s_tmp[16];
-    __syncthreads();
-    return r;
-}
-
 // ------------------------------------------------------------------ plan
 
 struct PlanArgs {
@@ -53,49 +30,85 @@ struct PlanArgs {
     uint32_t *err;
 };
 
-// One workgroup: per-segment block / group / tile / fixed-word bases.  A
-// segment of n IDs is empty (n = 0: no bytes), raw (n below the compression
-// threshold: its n IDs) or compressed (16-byte header, 8 bytes of directory
-// per block, the group table and the payloads).
-__global__ __launch_bounds__(1024) void k_plan_prep(PlanArgs a) {
-    const uint32_t tid = threadIdx.x;
+// Per-segment block / group / tile / fixed-word counts.  A segment of n IDs
+// is empty (n = 0: no bytes), raw (n below the compression threshold: its n
+// IDs) or compressed (16-byte header, 8 bytes of directory per block, the
+// group table and the payloads).  Pass 1, one workgroup per kPrepChunk
+// segments: the counts, their exclusive scans inside the chunk, and the
+// chunk's totals.
+__global__ __launch_bounds__(1024) void k_plan_local(PlanArgs a) {
+    const uint32_t tid = threadIdx.x, c = blockIdx.x;
     __shared__ uint32_t s_tmp[17];
-    uint32_t cb = 0, cg = 0, ct = 0, cf = 0;
     const uint32_t T = a.p.raw_below;
-    for (uint32_t base = 0; base < a.nseg; base += blockDim.x) {
-        const uint32_t r = base + tid;
-        uint32_t nb = 0, ng = 0, nt = 0, nf = 0;
-        if (r < a.nseg) {
-            const uint64_t s = a.seg_off[r], e = a.seg_off[r + 1];
-            const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
-            const bool bad = e < s || e > a.max_ids || lo > hi || (e - s) > (uint64_t)(hi - lo);
-            const uint32_t n = bad ? 0u : (uint32_t)(e - s);
-            if (bad) raise_err(a.err, kErrInval);
-            a.p.seg_n[r] = n;
-            const bool raw = n < T;  // (an empty segment too: no groups)
-            nb = cdiv32(n, kBlock);
-            ng = raw ? 0u : cdiv32(nb, kGroup);
-            nt = ng ? ng : 1u;
-            nf = raw ? n : 4u + 2u * nb;
-            if (n == 0) nf = 0;
-        }
-        uint32_t tb, tg, tt, tf;
-        const uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
-        const uint32_t xg = wg_excl_scan(ng, s_tmp, &tg);
-        const uint32_t xt = wg_excl_scan(nt, s_tmp, &tt);
-        const uint32_t xf = wg_excl_scan(nf, s_tmp, &tf);
-        if (r < a.nseg) {
-            a.p.blk_base[r] = cb + xb;
-            a.p.grp_base[r] = cg + xg;
-            a.p.tile_base[r] = ct + xt;
-            a.p.fix_base[r] = cf + xf;
-        }
-        cb += tb;
-        cg += tg;
-        ct += tt;
-        cf += tf;
+    const uint32_t r = c * kPrepChunk + tid;
+    uint32_t nb = 0, ng = 0, nt = 0, nf = 0;
+    if (r < a.nseg) {
+        const uint64_t s = a.seg_off[r], e = a.seg_off[r + 1];
+        const uint32_t lo = a.seg_lo[r], hi = a.seg_hi[r];
+        const bool bad = e < s || e > a.max_ids || lo > hi || (e - s) > (uint64_t)(hi - lo);
+        const uint32_t n = bad ? 0u : (uint32_t)(e - s);
+        if (bad) raise_err(a.err, kErrInval);
+        a.p.seg_n[r] = n;
+        const bool raw = n < T;  // (an empty segment too: no groups)
+        nb = cdiv32(n, kBlock);
+        ng = raw ? 0u : cdiv32(nb, kGroup);
+        nt = ng ? ng : 1u;
+        nf = raw ? n : 4u + 2u * nb;
+        if (n == 0) nf = 0;
     }
-    if (tid == 0) {
+    uint32_t tb, tg, tt, tf;
+    const uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
+    const uint32_t xg = wg_excl_scan(ng, s_tmp, &tg);
+    const uint32_t xt = wg_excl_scan(nt, s_tmp, &tt);
+    const uint32_t xf = wg_excl_scan(nf, s_tmp, &tf);
+    if (r < a.nseg) {
+        a.p.blk_base[r] = xb;
+        a.p.grp_base[r] = xg;
+        a.p.tile_base[r] = xt;
+        a.p.fix_base[r] = xf;
+    }
+    if (tid == 0) *(uint4 *)(a.p.chunk_sums + 4 * c) = make_uint4(tb, tg, tt, tf);
+}
+
+// Sum over workgroup threads of four values (up to 1024 threads).
+__device__ __forceinline__ uint4 wg_sum4(uint4 v, uint4 *s_red /*[16]*/) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    v.x = wave_sum(v.x);
+    v.y = wave_sum(v.y);
+    v.z = wave_sum(v.z);
+    v.w = wave_sum(v.w);
+    if (lane == 0) s_red[w] = v;
+    __syncthreads();
+    uint4 t = make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t i = 0; i < (blockDim.x >> 6); ++i) {
+        const uint4 x = s_red[i];
+        t.x += x.x, t.y += x.y, t.z += x.z, t.w += x.w;
+    }
+    return t;
+}
+
+// Pass 2, one workgroup per chunk: adds the totals of the chunks before it;
+// the last workgroup writes the batch totals at index nseg.
+__global__ __launch_bounds__(1024) void k_plan_fix(PlanArgs a) {
+    const uint32_t tid = threadIdx.x, c = blockIdx.x;
+    __shared__ uint4 s_red[16];
+    uint4 q = make_uint4(0u, 0u, 0u, 0u);
+    const uint4 *cs = (const uint4 *)a.p.chunk_sums;
+    for (uint32_t i = tid; i < c; i += blockDim.x) {
+        const uint4 x = cs[i];
+        q.x += x.x, q.y += x.y, q.z += x.z, q.w += x.w;
+    }
+    const uint4 pre = wg_sum4(q, s_red);
+    const uint32_t r = c * kPrepChunk + tid;
+    if (r < a.nseg) {
+        a.p.blk_base[r] += pre.x;
+        a.p.grp_base[r] += pre.y;
+        a.p.tile_base[r] += pre.z;
+        a.p.fix_base[r] += pre.w;
+    }
+    if (c + 1 == gridDim.x && tid == 0) {
+        const uint4 own = cs[c];
+        const uint32_t cb = pre.x + own.x, cg = pre.y + own.y, ct = pre.z + own.z, cf = pre.w + own.w;
         // inconsistent offsets (totals beyond what max_ids allows) disable
         // the batch: no tile runs, so nothing is indexed past the workspace
         const uint64_t max_blocks = (a.max_ids + kBlock - 1) / kBlock + a.nseg;
@@ -909,24 +922,6 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
     return total;
 }
 
-// Last r < n with base[r] <= t (base non-decreasing, base[0] <= t), found by
-// the whole wave: 64 probes per round, so 2 dependent loads for up to 4096
-// entries and 3 for up to 262144.
-__device__ __forceinline__ uint32_t wave_find(const uint32_t *base, uint32_t n, uint32_t t,
-                                              uint32_t lane) {
-    uint32_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const uint32_t step = (hi - lo + 63) >> 6;
-        const uint32_t idx = lo + lane * step;
-        const bool ok = idx < hi && base[idx] <= t;
-        const uint64_t mk = ballot(ok);
-        const uint32_t k = 63u - (uint32_t)__builtin_clzll(mk | 1ull);
-        lo = lo + k * step;
-        hi = min(hi, lo + step);
-    }
-    return readfirst(lo);
-}
-
 // Units a wave handles: a contiguous run (consecutive units mostly share a
 // segment, so the segment is found once and then walked forward) or every
 // NW-th unit.
@@ -1593,86 +1588,119 @@ struct DecPlanArgs {
     uint32_t *seg_n;      // 0 for bad / empty
     uint32_t *seg_form;   // 0 empty or bad, 1 raw, 2 compressed
     uint32_t *tile_base;  // [nseg+1]
+    uint64_t *chunk_n;    // [prep chunks] IDs of every kPrepChunk segments
+    uint32_t *chunk_t;    // [prep chunks] tiles of every kPrepChunk segments
     uint32_t *err;
 };
 
-// One workgroup: each segment's form, ID count and tiles (a group of 16
-// blocks of a compressed segment, or the whole of a raw one), and the
-// output offsets.  A segment of L bytes is empty if L = 0; raw if L < 16 or
-// its words 1 and 2 increase (IDs strictly increase); compressed if they
-// decrease (header n, hi, lo, magic with hi > lo).
-__global__ __launch_bounds__(1024) void k_dec_prep(DecPlanArgs a) {
+// Pass 1 of the decoder's plan, one workgroup per kPrepChunk segments: each
+// segment's form, ID count and tiles (a group of 16 blocks of a compressed
+// segment, or the whole of a raw one), their exclusive scans inside the
+// chunk, and the chunk's totals.  A segment of L bytes is empty if L = 0;
+// raw if L < 16 or its words 1 and 2 increase (IDs strictly increase);
+// compressed if they decrease (header n, hi, lo, magic with hi > lo).
+__global__ __launch_bounds__(1024) void k_dec_local(DecPlanArgs a) {
     __shared__ uint32_t s_tmp[17];
     __shared__ unsigned long long s_w[16];
     __shared__ unsigned long long s_c;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t ct = 0;
-    uint64_t co = 0;
-    for (uint32_t base = 0; base < a.nseg; base += blockDim.x) {
-        const uint32_t r = base + tid;
-        uint32_t n = 0, ng = 0;
-        if (r < a.nseg) {
-            const uint64_t s = a.seg_byte_off[r], e = a.seg_byte_off[r + 1];
-            bool bad = e < s || (s & 3) || (e & 3);
-            uint32_t form = 0;
-            if (!bad && e > s) {
-                const uint64_t L = e - s;
-                const uint32_t *h = (const uint32_t *)(a.in + s);
-                if (L < 16 || h[1] < h[2]) {
-                    bad = L / 4 > 0xFFFFFFFFull;
-                    n = (uint32_t)(L / 4);
-                    ng = 1;
-                    form = 1;
-                } else {
-                    const uint32_t hn = h[0], hi = h[1], lo = h[2], mg = h[3];
-                    const uint64_t nb = cdiv32(hn, kBlock) + 0ull;
-                    const uint64_t meta = 16ull + 8ull * nb + 4ull * ((nb + kGroup - 1) / kGroup);
-                    bad = mg != kMagic || lo >= hi || hn == 0 || hn > hi - lo || meta > L;
-                    n = hn;
-                    ng = (uint32_t)((nb + kGroup - 1) / kGroup);
-                    form = 2;
-                }
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6, c = blockIdx.x;
+    const uint32_t r = c * kPrepChunk + tid;
+    uint32_t n = 0, ng = 0;
+    if (r < a.nseg) {
+        const uint64_t s = a.seg_byte_off[r], e = a.seg_byte_off[r + 1];
+        bool bad = e < s || (s & 3) || (e & 3);
+        uint32_t form = 0;
+        if (!bad && e > s) {
+            const uint64_t L = e - s;
+            const uint32_t *h = (const uint32_t *)(a.in + s);
+            if (L < 16 || h[1] < h[2]) {
+                bad = L / 4 > 0xFFFFFFFFull;
+                n = (uint32_t)(L / 4);
+                ng = 1;
+                form = 1;
+            } else {
+                const uint32_t hn = h[0], hi = h[1], lo = h[2], mg = h[3];
+                const uint64_t nb = cdiv32(hn, kBlock) + 0ull;
+                const uint64_t meta = 16ull + 8ull * nb + 4ull * ((nb + kGroup - 1) / kGroup);
+                bad = mg != kMagic || lo >= hi || hn == 0 || hn > hi - lo || meta > L;
+                n = hn;
+                ng = (uint32_t)((nb + kGroup - 1) / kGroup);
+                form = 2;
             }
-            if (bad) {
-                raise_err(a.err, kErrCorrupt);
-                n = 0;
-                ng = 0;
-                form = 0;
-            }
-            a.seg_n[r] = n;
-            a.seg_form[r] = form;
         }
-        uint32_t tt;
-        const uint32_t xt = wg_excl_scan(ng, s_tmp, &tt);
-        // 64-bit exclusive scan of n (waves, then the workgroup)
-        uint64_t incl = n;
+        if (bad) {
+            raise_err(a.err, kErrCorrupt);
+            n = 0;
+            ng = 0;
+            form = 0;
+        }
+        a.seg_n[r] = n;
+        a.seg_form[r] = form;
+    }
+    uint32_t tt;
+    const uint32_t xt = wg_excl_scan(ng, s_tmp, &tt);
+    // 64-bit exclusive scan of n (waves, then the workgroup)
+    uint64_t incl = n;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t l2 = shfl_up((uint32_t)incl, d), h2 = shfl_up((uint32_t)(incl >> 32), d);
-            if (lane >= (uint32_t)d) incl += ((uint64_t)h2 << 32) | l2;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t l2 = shfl_up((uint32_t)incl, d), h2 = shfl_up((uint32_t)(incl >> 32), d);
+        if (lane >= (uint32_t)d) incl += ((uint64_t)h2 << 32) | l2;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long acc = 0;
+        for (uint32_t i = 0; i < (blockDim.x >> 6); ++i) {
+            const unsigned long long x = s_w[i];
+            s_w[i] = acc;
+            acc += x;
         }
-        if (lane == 63) s_w[w] = incl;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long acc = 0;
-            for (uint32_t i = 0; i < (blockDim.x >> 6); ++i) {
-                const unsigned long long x = s_w[i];
-                s_w[i] = acc;
-                acc += x;
-            }
-            s_c = acc;
-        }
-        __syncthreads();
-        if (r < a.nseg) {
-            a.tile_base[r] = ct + xt;
-            a.out_off[r] = co + s_w[w] + incl - n;
-        }
-        ct += tt;
-        co += s_c;
-        __syncthreads();
+        s_c = acc;
+    }
+    __syncthreads();
+    if (r < a.nseg) {
+        a.tile_base[r] = xt;
+        a.out_off[r] = s_w[w] + incl - n;
     }
     if (tid == 0) {
-        a.tile_base[a.nseg] = ct;
+        a.chunk_t[c] = tt;
+        a.chunk_n[c] = s_c;
+    }
+}
+
+// Pass 2: adds the totals of the chunks before each chunk; the last
+// workgroup writes the batch totals at index nseg and checks the capacity.
+__global__ __launch_bounds__(1024) void k_dec_fix(DecPlanArgs a) {
+    __shared__ unsigned long long s_n[16];
+    __shared__ uint32_t s_t[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6, c = blockIdx.x;
+    uint64_t qn = 0;
+    uint32_t qt = 0;
+    for (uint32_t i = tid; i < c; i += blockDim.x) {
+        qn += a.chunk_n[i];
+        qt += a.chunk_t[i];
+    }
+    qn = wave_sum64(qn);
+    qt = wave_sum(qt);
+    if (lane == 0) {
+        s_n[w] = qn;
+        s_t[w] = qt;
+    }
+    __syncthreads();
+    uint64_t pn = 0;
+    uint32_t pt = 0;
+    for (uint32_t i = 0; i < (blockDim.x >> 6); ++i) {
+        pn += s_n[i];
+        pt += s_t[i];
+    }
+    const uint32_t r = c * kPrepChunk + tid;
+    if (r < a.nseg) {
+        a.tile_base[r] += pt;
+        a.out_off[r] += pn;
+    }
+    if (c + 1 == gridDim.x && tid == 0) {
+        const uint64_t co = pn + a.chunk_n[c];
+        a.tile_base[a.nseg] = pt + a.chunk_t[c];
         a.out_off[a.nseg] = co;
         if (co > a.out_cap) raise_err(a.err, kErrCapacity);
     }
@@ -1846,6 +1874,95 @@ __device__ __forceinline__ void decode_block(const uint32_t *buf, uint32_t bw, u
     else
         decode_one_block<false>(buf, bw, val, cls, param, aux, v0, nk, hi, has_next, nxt, out, ob, out_cap,
                                 err, lane);
+}
+
+// ds_write_b32 of v to LDS byte address addr on the lanes of mask only: exec
+// is narrowed for the one store and restored inside the same asm block, so
+// the compiler never sees a changed exec (no per-lane test of the bit is
+// needed).  The store has no result register.
+__device__ __forceinline__ void lds_store_lanes(uint32_t addr, uint32_t v, uint64_t mask) {
+    uint64_t save;
+    asm volatile(
+        "s_and_saveexec_b64 %0, %3\n\t"
+        "ds_write_b32 %1, %2\n\t"
+        "s_mov_b64 exec, %0"
+        : "=&s"(save)
+        : "v"(addr), "v"(v), "s"(mask)
+        : "memory");
+}
+
+// LDS byte address of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// Chunk c (64 bits: words wi, wi + 1 of a bitmap held one word per lane in
+// src) of a full bitmap block: every lane whose bit is set writes its ID
+// (vl + 64 c, vl = v0 + 1 + lane) at its rank, cnt + the set bits below it.
+// The chunk's two words come to scalar registers, so the mask, the count
+// and the loop are scalar work; each lane spends two mbcnt, an address and a
+// value on it.  vbase: LDS byte address of the wave's val array (uniform).
+// A damaged block may hold more than 127 bits: the rank base is clamped at
+// 128, so such chunks land in val[128 .. 191] and the block is rejected by
+// its count.
+__device__ __forceinline__ void bitmap_chunk(uint32_t src, uint32_t wi, uint32_t vl, uint32_t &cnt,
+                                             uint32_t vbase) {
+    const uint32_t lo = readlane(src, wi), hi = readlane(src, wi + 1);
+    const uint64_t mk = ((uint64_t)hi << 32) | lo;
+    const uint32_t rk = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+    uint32_t b4 = vbase + 4 * min(cnt, kBlock);
+    asm("" : "+s"(b4));  // kept scalar: one v_lshl_add per lane for the address
+    lds_store_lanes(b4 + 4 * rk, vl, mk);
+    cnt += popc64(mk);
+}
+
+// A full bitmap block (128 IDs) decoded from its payload words in registers
+// (lane i: word i in px, word 64 + i in py, zero past the block's words), so
+// it is never staged in LDS.  Checks as for every block: the set bits number
+// m = 127, none lies past the span (aux), the last ID is below hi and below
+// the next block's first.  val: 192 words of the wave's LDS.  Returns false
+// (nothing written) for a damaged block.
+__device__ __forceinline__ bool dec_bitmap_full(uint32_t px, uint32_t py, uint32_t aux, uint32_t v0, uint32_t hi,
+                                                bool has_next, uint32_t nxt, uint32_t *val, uint32_t *out,
+                                                uint64_t ob, uint64_t out_cap, uint32_t lane) {
+    const uint32_t nch = (aux + 63) >> 6;  // 64-bit chunks
+    const uint32_t vbase = readfirst(lds_addr(val));
+    if (lane == 0) val[0] = v0;
+    uint32_t cnt = 1;
+    const uint32_t n1 = min(nch, 32u);
+    const uint32_t vl = v0 + 1 + lane;
+    for (uint32_t c = 0; c < n1; c += 2) {
+        bitmap_chunk(px, 2 * c, vl + 64 * c, cnt, vbase);
+        bitmap_chunk(px, (2 * c + 2) & 63, vl + 64 * c + 64, cnt, vbase);
+    }
+    for (uint32_t c = 32; c < nch; c += 2) {
+        bitmap_chunk(py, 2 * c - 64, vl + 64 * c, cnt, vbase);
+        bitmap_chunk(py, (2 * c - 62) & 63, vl + 64 * c + 64, cnt, vbase);
+    }
+    // (the second chunk of a pair past the span reads words that are zero:
+    // words past the block's own are not loaded, and chunk pairs never pass
+    // word 127 because 2 nch <= 128)
+    const uint32_t tailw = aux >> 5, tailb = aux & 31;
+    const uint32_t tw = readlane(tailw < 64 ? px : py, tailw & 63);
+    bool bad = cnt != kBlock || (tailb != 0 && (tw >> tailb) != 0u);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t xa = val[lane], xb = val[lane + 64];
+    if (!bad) {
+        const uint32_t last = readlane(xb, 63);
+        bad = (uint64_t)v0 + (last - v0) >= (uint64_t)hi || (has_next && last >= nxt);
+    }
+    if (!bad) {
+        if (ob + kBlock <= out_cap) {
+            out[ob + lane] = xa;
+            out[ob + 64 + lane] = xb;
+        } else {
+            if (ob + lane < out_cap) out[ob + lane] = xa;
+            if (ob + 64 + lane < out_cap) out[ob + 64 + lane] = xb;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    return !bad;
 }
 
 // A block's payload words (wc of them, at word o of the segment's payload
@@ -2152,12 +2269,24 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
             const uint32_t j = hb + kk, k = k0 + j;
             const bool has_next = k + 1 < nb;
             const uint32_t nxt = has_next ? lo + readlane(first, j + 1) : 0u;
+            const uint32_t nk = min(kBlock, n - k * kBlock);
+            const uint32_t cj = readlane(cls, j);
             const uint32_t *buf = win;
             if constexpr (STAGE) {
                 buf = win + (readlane(off, j) - ub);
             } else {
                 uint32_t na = 0, nbw = 0;
                 if (kk + 1 < nblk) load_payload(pay, readlane(off, j + 1), readlane(words, j + 1), lane, na, nbw);
+                if ((cj == kClsBitmap) & (nk == kBlock)) {
+                    // full bitmap: decoded from the registers
+                    if (!dec_bitmap_full(pa, pb, readlane(aux, j), lo + readlane(first, j), hi, has_next, nxt, val,
+                                         a.out, oo + (uint64_t)k * kBlock, a.out_cap, lane)) {
+                        if (lane == 0) raise_err(a.err, kErrCorrupt);
+                    }
+                    pa = na;
+                    pb = nbw;
+                    continue;
+                }
                 win[lane] = pa;
                 win[lane + 64] = pb;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2165,8 +2294,8 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
                 pa = na;
                 pb = nbw;
             }
-            decode_block(buf, readlane(words, j), val, readlane(cls, j), readlane(param, j), readlane(aux, j),
-                         lo + readlane(first, j), min(kBlock, n - k * kBlock), hi, has_next, nxt, a.out,
+            decode_block(buf, readlane(words, j), val, cj, readlane(param, j), readlane(aux, j),
+                         lo + readlane(first, j), nk, hi, has_next, nxt, a.out,
                          oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
         }
     }
@@ -2429,7 +2558,9 @@ int launch_plan_prep(const bfsc_batch *b, const Plan &p, uint32_t *err, bool zer
     a.max_ids = b->max_ids;
     a.p = p;
     a.err = err;
-    hipLaunchKernelGGL(k_plan_prep, dim3(1), dim3(1024), 0, s, a);
+    const uint32_t chunks = prep_chunks(b->nseg);
+    hipLaunchKernelGGL(k_plan_local, dim3(chunks), dim3(kPrepChunk), 0, s, a);
+    hipLaunchKernelGGL(k_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -2521,7 +2652,7 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
 
 size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg) {
     (void)max_ids;
-    return align256(((size_t)nseg + 1) * 4) * 3 + 256;
+    return dec_ws_bytes(nseg);
 }
 
 int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
@@ -2532,6 +2663,9 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     uint32_t *seg_n = (uint32_t *)wb;
     uint32_t *tile_base = (uint32_t *)(wb + arr);
     uint32_t *seg_form = (uint32_t *)(wb + 2 * arr);
+    const uint32_t chunks = prep_chunks(nseg);
+    uint64_t *chunk_n = (uint64_t *)(wb + 3 * arr);
+    uint32_t *chunk_t = (uint32_t *)(wb + 3 * arr + align256((size_t)chunks * 8));
     DecPlanArgs pa;
     pa.in = in;
     pa.seg_byte_off = seg_byte_off;
@@ -2541,8 +2675,11 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     pa.seg_n = seg_n;
     pa.seg_form = seg_form;
     pa.tile_base = tile_base;
+    pa.chunk_n = chunk_n;
+    pa.chunk_t = chunk_t;
     pa.err = ctx->err;
-    hipLaunchKernelGGL(k_dec_prep, dim3(1), dim3(1024), 0, s, pa);
+    hipLaunchKernelGGL(k_dec_local, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
+    hipLaunchKernelGGL(k_dec_fix, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
     DecArgs a;
     a.in = in;
     a.seg_byte_off = seg_byte_off;

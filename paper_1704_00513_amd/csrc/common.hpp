@@ -134,6 +134,47 @@ __device__ __forceinline__ void raise_err(uint32_t *err, uint32_t bit) {
     __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Last r < n with base[r] <= t (base non-decreasing, base[0] <= t), found by
+// the whole wave: 64 probes per round, so 2 dependent loads for up to 4096
+// entries and 3 for up to 262144.
+__device__ __forceinline__ uint32_t wave_find(const uint32_t *base, uint32_t n, uint32_t t,
+                                              uint32_t lane) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) >> 6;
+        const uint32_t idx = lo + lane * step;
+        const bool ok = idx < hi && base[idx] <= t;
+        const uint64_t mk = ballot(ok);
+        const uint32_t k = 63u - (uint32_t)__builtin_clzll(mk | 1ull);
+        lo = lo + k * step;
+        hi = min(hi, lo + step);
+    }
+    return readfirst(lo);
+}
+
+// Exclusive prefix sum over a workgroup of up to 1024 threads.
+__device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tmp /*[17]*/, uint32_t *total) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) s_tmp[w] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t i = 0; i < nw; ++i) {
+            const uint32_t x = s_tmp[i];
+            s_tmp[i] = acc;
+            acc += x;
+        }
+        s_tmp[16] = acc;
+    }
+    __syncthreads();
+    const uint32_t r = s_tmp[w] + incl - v;
+    *total = s_tmp[16];
+    __syncthreads();
+    return r;
+}
+
 // Index of the last entry of base[0..n] (non-decreasing) that is <= t.
 __device__ __forceinline__ uint32_t upper_bound_m1(const uint32_t *base, uint32_t n, uint32_t t) {
     uint32_t lo = 0, hi = n;  // answer in [0, n-1]
@@ -173,6 +214,8 @@ struct Plan {
     uint32_t *tile_base;  // [nseg+1] first tile
     uint32_t *seg_n;      // [nseg]   IDs per segment (0 for a rejected segment)
     uint32_t *counter;    // [4]      [0]: workgroups done with the pack pass
+    uint32_t *chunk_sums; // [4 x prep chunks] blocks, groups, tiles and fixed words of
+                          // every kPrepChunk segments (the plan passes' carries)
     uint32_t *unit_words; // [2 max_tiles] payload words per unit (unit 2t + h: half h of tile t)
     uint32_t *unit_off;   // [2 max_tiles] exclusive prefix of unit_words within the unit's chunk
     uint32_t *chunk_words;  // [chunks] payload words of every chunk of kScanChunk units
@@ -193,7 +236,20 @@ __host__ __device__ inline uint64_t plan_max_tiles(uint64_t max_ids, uint32_t ns
     return max_ids / (kBlock * kGroup) + 2ull * nseg + 2;
 }
 
-__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Segments per workgroup of the plan passes (encode and decode): one
+// workgroup scans its chunk, a second pass adds the totals of the chunks
+// before it.
+constexpr uint32_t kPrepChunk = 1024;
+__host__ __device__ constexpr uint32_t prep_chunks(uint32_t nseg) { return (nseg + kPrepChunk - 1) / kPrepChunk; }
+
+// Decoder workspace: seg_n, tile_base, seg_form (u32[nseg+1] each), the
+// chunk carries (u64 IDs, u32 tiles per chunk of segments), 256 spare bytes.
+__host__ __device__ constexpr size_t dec_ws_bytes(uint32_t nseg) {
+    return align256(((size_t)nseg + 1) * 4) * 3 + align256((size_t)prep_chunks(nseg) * 8) +
+           align256((size_t)prep_chunks(nseg) * 4) + 256;
+}
 
 // Carves a Plan out of a workspace; returns the bytes used.  Slots are only
 // laid out (and only counted) for the encoder.
@@ -215,6 +271,8 @@ __host__ __device__ inline size_t plan_layout(void *ws, uint64_t max_ids, uint32
     off = align256(off + n1 * 4);
     if (p) p->counter = (uint32_t *)(b + off);
     off = align256(off + 16);
+    if (p) p->chunk_sums = (uint32_t *)(b + off);
+    off = align256(off + (size_t)prep_chunks(nseg) * 16);
     if (p) p->unit_words = (uint32_t *)(b + off);
     off = align256(off + 2 * mt * 4);
     if (p) p->unit_off = (uint32_t *)(b + off);

@@ -195,7 +195,7 @@ def _round_trip_and_samples(ctx, full, P, t, b, N, R):
 
 
 def test_full_size_fused_learned_pass(ctx, full):
-    """The trained selector inside the pack pass, on the 1024-range batch:
+    """The trained selector inside the pack pass, on each full-size batch:
     the stream is the oracle's encoding (per sampled segment) of the class
     vector that the separate selection pass writes, and those classes are the
     oracle's resolved prediction wherever its top two logits are clearly
@@ -203,8 +203,6 @@ def test_full_size_fused_learned_pass(ctx, full):
     import os
     import paper_1704_00513_amd as P
     from oracle import mlp
-    if full["nseg"] != 1024:
-        pytest.skip("the learned pass is checked on the 1024-range batch")
     t = torch()
     b, N = full["b"], full["n"]
     R = b.nseg
