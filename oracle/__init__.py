@@ -22,6 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "bitmap.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -40,11 +41,12 @@ RAW_BELOW = 32
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c (plain C, no fast-math) into liboracle.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oracle.c and bitmap.c (plain C, no fast-math) into liboracle.so."""
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-fno-fast-math",
-                               "-ffp-contract=off", "-o", tmp, _SRC])
+                               "-ffp-contract=off", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -72,6 +74,10 @@ def _load():
                 "ref_f32_to_f16": (ctypes.c_uint16, [ctypes.c_float]),
                 "ref_features": (i32, [vp, vp, u32, vp, vp]),
                 "ref_resolve": (u64, [vp, vp, u32, vp, i32, vp]),
+                "ref_bmc_bound": (u64, [u64, u32]),
+                "ref_bmc_classes": (u64, [vp, vp, u32, vp]),
+                "ref_bmc_encode": (i32, [vp, vp, u32, vp, u64, vp]),
+                "ref_bmc_decode": (i32, [vp, vp, u32, vp, u64, vp]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(lib, name)
@@ -347,3 +353,59 @@ def merge_filter(ids, level: np.ndarray, cur_level: int):
     new = u[lv[u] < 0]
     lv[new] = cur_level + 1
     return new.astype(np.uint32), lv
+
+
+# ---------------------------------------------------------------- bitmap codec
+
+BMC_ZERO, BMC_ONES, BMC_SET, BMC_CLEAR, BMC_LITERAL = 0, 1, 2, 3, 4
+BMC_BLOCK_WORDS = 128
+
+
+def bmc_bound(n_words: int, nseg: int) -> int:
+    return int(_load().ref_bmc_bound(int(n_words), int(nseg)))
+
+
+def bmc_encode(bits: np.ndarray, seg_w: np.ndarray):
+    """Bitmap codec: words bits u32, segments seg_w u64[R+1] (word ranges)
+    -> (stream u8, seg_byte_off u64[R+1])."""
+    bits, seg_w = _u32(bits), _u64(seg_w)
+    if bits.size == 0:
+        bits = np.zeros(1, np.uint32)
+    nseg = seg_w.size - 1
+    cap = bmc_bound(int(seg_w[-1] - seg_w[0]) if nseg else 0, nseg)
+    out = np.zeros(max(4, cap), np.uint8)
+    sbo = np.zeros(nseg + 1, np.uint64)
+    st = _load().ref_bmc_encode(_p(bits), _p(seg_w), nseg, _p(out), cap, _p(sbo))
+    if st != ST_OK:
+        raise ValueError("bitmap encode status %d" % st)
+    return out[:int(sbo[-1])].copy(), sbo
+
+
+def bmc_classes(bits: np.ndarray, seg_w: np.ndarray) -> np.ndarray:
+    bits, seg_w = _u32(bits), _u64(seg_w)
+    if bits.size == 0:
+        bits = np.zeros(1, np.uint32)
+    nseg = seg_w.size - 1
+    nblk = int(sum((int(seg_w[r + 1] - seg_w[r]) + BMC_BLOCK_WORDS - 1) // BMC_BLOCK_WORDS
+                   for r in range(nseg)))
+    cls = np.zeros(max(1, nblk), np.uint8)
+    k = _load().ref_bmc_classes(_p(bits), _p(seg_w), nseg, _p(cls))
+    return cls[:k]
+
+
+def bmc_decode(stream: np.ndarray, seg_byte_off: np.ndarray, out_cap: int | None = None):
+    """-> (status, words u32[n], out_off u64[R+1])."""
+    stream = np.ascontiguousarray(stream, np.uint8)
+    if stream.size == 0:
+        stream = np.zeros(4, np.uint8)
+    sbo = _u64(seg_byte_off)
+    nseg = sbo.size - 1
+    if out_cap is None:
+        # a segment of nw words takes at least 16 + 12 ceil(nw / 128) bytes
+        out_cap = 11 * (int(sbo[-1]) if nseg else 0) + 1
+    out = np.zeros(max(1, out_cap), np.uint32)
+    off = np.zeros(nseg + 1, np.uint64)
+    st = _load().ref_bmc_decode(_p(stream), _p(sbo), nseg, _p(out), out_cap, _p(off))
+    if st != ST_OK:
+        return st, None, None
+    return st, out[:int(off[-1])].copy(), off
