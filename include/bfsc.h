@@ -91,7 +91,9 @@ enum {
     BFSC_OP_FEATURES = 4,
     BFSC_OP_MLP = 5,
     BFSC_OP_ENCODE_PLACE = 6, /* timing only: the encoder's placement pass */
-    BFSC_OP_PIPELINE = 7      /* timing only: one bfsc_pipeline_step */
+    BFSC_OP_PIPELINE = 7,     /* timing only: one bfsc_pipeline_step */
+    BFSC_OP_BITMAP_ENCODE = 8,
+    BFSC_OP_BITMAP_DECODE = 9
 };
 
 /* One GPU's CSR partition: a row range with global column IDs; on one GPU
@@ -332,6 +334,47 @@ int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int 
 int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                 uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
                 void *ws, void *stream);
+
+/* ---- Bitmap codec: one owner's share of a vertex bitmap (the visited
+ * list, or a frontier kept as a bitmap).  The paper leaves the compression
+ * of the visited bitmap as future work ("Future work" chapter), after the
+ * work of Huiwei et al. that it reviews (related work: the BFS's sparse
+ * vectors as bitmaps, compressed with a bitmap index); its guidance on
+ * compression techniques names bitmap indexes for low-cardinality data.
+ *
+ * A batch: bitmap words bits u32 (device), segment r = words
+ * [seg_w[r], seg_w[r+1]) (u64[nseg+1], device, non-decreasing,
+ * seg_w[nseg] <= max_words, fewer than 2^27 words per segment).  Bit i of a
+ * segment is bit (i mod 32) of its word i / 32.  Stream of a segment of nw
+ * words (little-endian 32-bit words):
+ *   nw = 0      no bytes
+ *   otherwise   header 16 B: nw, pop (set bits), nb = ceil(nw / 128), magic 0x31434D42
+ *               directory 12 B per block of 128 words: off (payload word
+ *                 offset of the block in the segment's payload area),
+ *                 count u16 | first u16 << 16, class u8 | width u8 << 8
+ *                 (upper 16 bits zero)
+ *               payloads, whole words per block, in block order
+ * Block classes: 0 ZERO (every bit clear) and 1 ONES (every bit set), no
+ * payload; 2 SET / 3 CLEAR: the positions p_0 < ... of the set / clear
+ * bits, count of them, first = p_0, the gaps p_j - p_{j-1} bit-packed at
+ * width = bitlen(largest gap) (field j-1 at stream bits [(j-1) w, j w),
+ * LSB first); 4 LITERAL: the block's words.  The encoder takes ZERO or ONES
+ * when they apply, else the fewest payload words among SET, CLEAR, LITERAL
+ * (ties in that order).  Segments are back to back, word aligned, their
+ * byte offsets out of band (seg_byte_off u64[nseg+1], device).
+ * Workspace: bfsc_workspace_size(BFSC_OP_BITMAP_ENCODE / _DECODE, max_words,
+ * nseg).  Errors latch as for the frontier codec: bad segments or sizes
+ * BFSC_E_INVAL, output overflow BFSC_E_CAPACITY, a damaged stream
+ * BFSC_E_CORRUPT (nothing is read or written outside the buffers). */
+int bfsc_bitmap_encode_bound(uint64_t n_words, uint32_t nseg, size_t *bytes);
+int bfsc_bitmap_encode(bfsc_ctx *ctx, const uint32_t *bits, const uint64_t *seg_w, uint32_t nseg, uint64_t max_words,
+                       uint8_t *out, size_t out_cap, uint64_t *seg_byte_off, void *ws, void *stream);
+/* Writes segment r's words to out[out_off[r] .. out_off[r+1]) (out_off
+ * u64[nseg+1], device; out capacity out_cap words); max_words bounds the
+ * total. */
+int bfsc_bitmap_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                       uint64_t max_words, uint32_t *out, uint64_t out_cap, uint64_t *out_off, void *ws,
+                       void *stream);
 
 /* Selector features: 8 fp16 values per block (bit patterns as u16, row
  * major [block][8]): n/128, bitlen(min delta)/32, bitlen(max delta)/32,

@@ -296,6 +296,31 @@ class Context:
                                       ptr(out_ids), cap, ptr(out_off), ptr(ws), _stream(stream)),
               "bfsc_decode")
 
+    # ---------------------------------------------------------- bitmap codec
+
+    @staticmethod
+    def bitmap_encode_bound(n_words: int, nseg: int) -> int:
+        n = ctypes.c_size_t()
+        check(_lib.load().bfsc_bitmap_encode_bound(n_words, nseg, ctypes.byref(n)), "bfsc_bitmap_encode_bound")
+        return n.value
+
+    def bitmap_encode(self, bits, seg_w, nseg, max_words, out, seg_byte_off, ws=None, stream=None, out_cap=None):
+        """Bitmap codec: words bits (u32 tensor), segments seg_w (u64 word
+        ranges, nseg + 1) -> out bytes, seg_byte_off (nseg + 1)."""
+        ws = ws if ws is not None else self.workspace(_lib.OP_BITMAP_ENCODE, max_words, nseg)
+        cap = out.numel() * out.element_size() if out_cap is None else out_cap
+        check(_lib.load().bfsc_bitmap_encode(self.h, ptr(bits), ptr(seg_w), int(nseg), int(max_words), ptr(out),
+                                             cap, ptr(seg_byte_off), ptr(ws), _stream(stream)),
+              "bfsc_bitmap_encode")
+
+    def bitmap_decode(self, data, seg_byte_off, nseg, max_words, out, out_off, ws=None, stream=None,
+                      out_cap=None):
+        ws = ws if ws is not None else self.workspace(_lib.OP_BITMAP_DECODE, max_words, nseg)
+        cap = out.numel() if out_cap is None else out_cap
+        check(_lib.load().bfsc_bitmap_decode(self.h, ptr(data), ptr(seg_byte_off), int(nseg), int(max_words),
+                                             ptr(out), cap, ptr(out_off), ptr(ws), _stream(stream)),
+              "bfsc_bitmap_decode")
+
     def sync_status(self, stream=None) -> int:
         return _lib.load().bfsc_sync_status(self.h, _stream(stream))
 

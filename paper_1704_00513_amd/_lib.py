@@ -20,6 +20,7 @@ SEL_DEFAULT, SEL_PLAIN_BP, SEL_EXHAUSTIVE, SEL_LEARNED = -1, 0, 1, 2
 RAW_BELOW = 32  # the library's default compression threshold
 OP_BFS, OP_SELECT, OP_ENCODE, OP_DECODE, OP_FEATURES, OP_MLP = 0, 1, 2, 3, 4, 5
 OP_ENCODE_PLACE, OP_PIPELINE = 6, 7
+OP_BITMAP_ENCODE, OP_BITMAP_DECODE = 8, 9
 N_PARAMS = 7011
 
 vp = ctypes.c_void_p
@@ -82,6 +83,9 @@ _SIGS = {
     "bfsc_encode_bound": [u64, u32, P(sz)],
     "bfsc_encode": [vp, P(BatchDesc), vp, ctypes.c_int, vp, sz, vp, vp, vp],
     "bfsc_decode": [vp, vp, vp, u32, u64, vp, u64, vp, vp, vp],
+    "bfsc_bitmap_encode_bound": [u64, u32, P(sz)],
+    "bfsc_bitmap_encode": [vp, vp, vp, u32, u64, vp, sz, vp, vp, vp],
+    "bfsc_bitmap_decode": [vp, vp, vp, u32, u64, vp, u64, vp, vp, vp],
     "bfsc_features": [vp, P(BatchDesc), vp, vp, vp],
     "bfsc_mlp_param_count": [],
     "bfsc_mlp_init": [vp, u64],

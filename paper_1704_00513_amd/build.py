@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbfsc.so")
 ARCH = "gfx950"
-SOURCES = ["codec.hip", "bfs.hip", "mlp.hip", "graph.hip", "capi.hip"]
+SOURCES = ["codec.hip", "bfs.hip", "mlp.hip", "graph.hip", "bitmap.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -236,6 +236,10 @@ int bfsc_workspace_size(const bfsc_ctx *ctx, int op, uint64_t max_ids, uint32_t 
         case BFSC_OP_MLP:
             *bytes = mlp_ws_bytes((uint32_t)(max_ids ? max_ids : 1));
             return BFSC_OK;
+        case BFSC_OP_BITMAP_ENCODE:
+        case BFSC_OP_BITMAP_DECODE:
+            *bytes = bitmap_ws_bytes(max_ids, nseg);
+            return BFSC_OK;
         default:
             return BFSC_E_INVAL;
     }
@@ -379,6 +383,31 @@ int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, 
     if ((uintptr_t)in & 3) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     return launch_decode(ctx, in, seg_byte_off, nseg, max_ids, out_ids, out_cap, out_off, ws, S(stream));
+}
+
+int bfsc_bitmap_encode_bound(uint64_t n_words, uint32_t nseg, size_t *bytes) {
+    if (!bytes) return BFSC_E_INVAL;
+    *bytes = (size_t)bitmap_encode_bound(n_words, nseg);
+    return BFSC_OK;
+}
+
+int bfsc_bitmap_encode(bfsc_ctx *ctx, const uint32_t *bits, const uint64_t *seg_w, uint32_t nseg, uint64_t max_words,
+                       uint8_t *out, size_t out_cap, uint64_t *seg_byte_off, void *ws, void *stream) {
+    if (!ctx || !bits || !seg_w || !out || !seg_byte_off || !ws || nseg == 0 || max_words >= (1ull << 40))
+        return BFSC_E_INVAL;
+    if ((uintptr_t)out & 3) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_bitmap_encode(ctx, bits, seg_w, nseg, max_words, out, out_cap, seg_byte_off, ws, S(stream));
+}
+
+int bfsc_bitmap_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                       uint64_t max_words, uint32_t *out, uint64_t out_cap, uint64_t *out_off, void *ws,
+                       void *stream) {
+    if (!ctx || !in || !seg_byte_off || !out || !out_off || !ws || nseg == 0 || max_words >= (1ull << 40))
+        return BFSC_E_INVAL;
+    if ((uintptr_t)in & 3) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    return launch_bitmap_decode(ctx, in, seg_byte_off, nseg, max_words, out, out_cap, out_off, ws, S(stream));
 }
 
 int bfsc_mlp_param_count(void) { return kNParams; }

@@ -350,6 +350,13 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
                      const int32_t *cur_level_dev = nullptr);
 int launch_level_inc(int32_t *level_dev, hipStream_t s);
 size_t mlp_ws_bytes(uint32_t n);
+size_t bitmap_ws_bytes(uint64_t max_words, uint32_t nseg);
+uint64_t bitmap_encode_bound(uint64_t n_words, uint32_t nseg);
+int launch_bitmap_encode(bfsc_ctx *ctx, const uint32_t *bits, const uint64_t *seg_w, uint32_t nseg, uint64_t max_words,
+                         uint8_t *out, uint64_t out_cap, uint64_t *seg_byte_off, void *ws, hipStream_t s);
+int launch_bitmap_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                         uint64_t max_words, uint32_t *out, uint64_t out_cap, uint64_t *out_off, void *ws,
+                         hipStream_t s);
 int launch_mlp_forward(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, hipStream_t s);
 int launch_mlp_infer(bfsc_ctx *ctx, const uint16_t *X, uint32_t n, float *logits, uint8_t *cls,
                      hipStream_t s);
