@@ -335,6 +335,21 @@ int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, 
                 uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
                 void *ws, void *stream);
 
+/* bfsc_decode without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, output and error
+ * behaviour as bfsc_decode.  The decoder's per-segment plan lives in a
+ * fixed array of the library (about 0.8 MB per GPU, held until the process
+ * ends), so nseg is limited to BFSC_DECODE_NOALLOC_MAX_SEGS (BFSC_E_INVAL
+ * beyond it).  The call allocates nothing and records no timing events.
+ * All calls on one GPU share that array: calls that overlap on one GPU (two
+ * streams, or two contexts of the same device) race and must be serialised
+ * by the caller. */
+#define BFSC_DECODE_NOALLOC_MAX_SEGS 65536u
+int bfsc_decode_noalloc(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                        uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
+                        void *stream);
+
 /* ---- Bitmap codec: one owner's share of a vertex bitmap (the visited
  * list, or a frontier kept as a bitmap).  The paper leaves the compression
  * of the visited bitmap as future work ("Future work" chapter), after the

@@ -14,12 +14,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (E_CAPACITY, E_CORRUPT, E_HIP, E_INVAL, N_PARAMS, OK, OP_DECODE, OP_ENCODE,
+from ._lib import (DECODE_NOALLOC_MAX_SEGS, E_CAPACITY, E_CORRUPT, E_HIP, E_INVAL, N_PARAMS, OK, OP_DECODE, OP_ENCODE,
                    OP_FEATURES, OP_MLP, OP_SELECT, RAW_BELOW, SEL_DEFAULT, SEL_EXHAUSTIVE, SEL_LEARNED,
                    SEL_PLAIN_BP, BfscError, check, ptr)
 
 __all__ = ["Context", "DeviceGraph", "DeviceBatch", "SEL_DEFAULT", "SEL_PLAIN_BP", "SEL_EXHAUSTIVE",
-           "SEL_LEARNED", "RAW_BELOW", "BfscError", "OK", "E_INVAL", "E_CAPACITY", "E_CORRUPT", "E_HIP"]
+           "SEL_LEARNED", "RAW_BELOW", "DECODE_NOALLOC_MAX_SEGS", "BfscError", "OK", "E_INVAL", "E_CAPACITY", "E_CORRUPT", "E_HIP"]
 
 
 def _torch():
@@ -295,6 +295,15 @@ class Context:
         check(_lib.load().bfsc_decode(self.h, ptr(data), ptr(seg_byte_off), int(nseg), int(max_ids),
                                       ptr(out_ids), cap, ptr(out_off), ptr(ws), _stream(stream)),
               "bfsc_decode")
+
+    def decode_noalloc(self, data, seg_byte_off, nseg, max_ids, out_ids, out_off, stream=None,
+                       out_cap=None):
+        """bfsc_decode with the library's fixed scratch array instead of a
+        workspace (at most DECODE_NOALLOC_MAX_SEGS segments)."""
+        cap = out_ids.numel() if out_cap is None else out_cap
+        check(_lib.load().bfsc_decode_noalloc(self.h, ptr(data), ptr(seg_byte_off), int(nseg), int(max_ids),
+                                              ptr(out_ids), cap, ptr(out_off), _stream(stream)),
+              "bfsc_decode_noalloc")
 
     # ---------------------------------------------------------- bitmap codec
 

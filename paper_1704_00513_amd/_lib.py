@@ -22,6 +22,7 @@ OP_BFS, OP_SELECT, OP_ENCODE, OP_DECODE, OP_FEATURES, OP_MLP = 0, 1, 2, 3, 4, 5
 OP_ENCODE_PLACE, OP_PIPELINE = 6, 7
 OP_BITMAP_ENCODE, OP_BITMAP_DECODE = 8, 9
 N_PARAMS = 7011
+DECODE_NOALLOC_MAX_SEGS = 65536  # BFSC_DECODE_NOALLOC_MAX_SEGS
 
 vp = ctypes.c_void_p
 u32, u64, i32, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
@@ -83,6 +84,7 @@ _SIGS = {
     "bfsc_encode_bound": [u64, u32, P(sz)],
     "bfsc_encode": [vp, P(BatchDesc), vp, ctypes.c_int, vp, sz, vp, vp, vp],
     "bfsc_decode": [vp, vp, vp, u32, u64, vp, u64, vp, vp, vp],
+    "bfsc_decode_noalloc": [vp, vp, vp, u32, u64, vp, u64, vp, vp],
     "bfsc_bitmap_encode_bound": [u64, u32, P(sz)],
     "bfsc_bitmap_encode": [vp, vp, vp, u32, u64, vp, sz, vp, vp, vp],
     "bfsc_bitmap_decode": [vp, vp, vp, u32, u64, vp, u64, vp, vp, vp],

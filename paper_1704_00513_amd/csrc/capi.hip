@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "common.hpp"
@@ -50,6 +51,35 @@ void timing_end(bfsc_ctx *ctx, int slot, hipStream_t s) {
 }
 
 }  // namespace bfsc
+
+// ------------------------------------------------------------------ decode scratch without allocation
+// bfsc_decode_noalloc keeps the decoder's per-segment plan (three u32 arrays
+// of nseg + 1 entries and the carries of its chunks of segments, each
+// 256-byte aligned, plus 256 bytes) in this file-scope array instead of a
+// caller workspace.  Every GPU the library
+// runs on holds its own copy until the process ends.  In host code `scratch`
+// only names the symbol: its device address on the current GPU comes from
+// hipGetSymbolAddress, resolved once per device at bfsc_create.
+static constexpr size_t kNoAllocScratchBytes = dec_ws_bytes(BFSC_DECODE_NOALLOC_MAX_SEGS);
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+// The device address of `scratch` on `device`, which must be current.
+static int noalloc_scratch_addr(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return BFSC_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BFSC_E_HIP;
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return BFSC_OK;
+}
 
 static int set_device(const bfsc_ctx *ctx) {
     return hipSetDevice(ctx->device) == hipSuccess ? BFSC_OK : BFSC_E_HIP;
@@ -170,6 +200,7 @@ int bfsc_create(bfsc_ctx **out, int device, const bfsc_config *cfg) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return BFSC_E_HIP; }
     c->n_cu = prop.multiProcessorCount;
+    if (noalloc_scratch_addr(device, &c->noalloc_scratch) != BFSC_OK) { delete c; return BFSC_E_HIP; }
     const size_t np = kNParams;
     if (hipMalloc((void **)&c->err, 256) != hipSuccess ||
         hipMalloc((void **)&c->mlp_params, np * 4) != hipSuccess ||
@@ -383,6 +414,20 @@ int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, 
     if ((uintptr_t)in & 3) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     return launch_decode(ctx, in, seg_byte_off, nseg, max_ids, out_ids, out_cap, out_off, ws, S(stream));
+}
+
+int bfsc_decode_noalloc(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
+                        uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
+                        void *stream) {
+    if (!ctx || !in || !seg_byte_off || !out_ids || !out_off || nseg == 0) return BFSC_E_INVAL;
+    if (nseg > BFSC_DECODE_NOALLOC_MAX_SEGS || (uintptr_t)in & 3) return BFSC_E_INVAL;
+    if (decode_ws_bytes(max_ids, nseg) > kNoAllocScratchBytes || !ctx->noalloc_scratch) return BFSC_E_INVAL;
+    if (set_device(ctx)) return BFSC_E_HIP;
+    // every word of the plan that the decoder reads is written by its first
+    // kernel, so the array needs no clearing between calls; no timing events
+    // either (creating one may allocate)
+    return launch_decode(ctx, in, seg_byte_off, nseg, max_ids, out_ids, out_cap, out_off, ctx->noalloc_scratch,
+                         S(stream), false);
 }
 
 int bfsc_bitmap_encode_bound(uint64_t n_words, uint32_t nseg, size_t *bytes) {

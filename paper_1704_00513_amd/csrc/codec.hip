@@ -2657,7 +2657,7 @@ size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg) {
 
 int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                   uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
-                  void *ws, hipStream_t s) {
+                  void *ws, hipStream_t s, bool timed) {
     char *wb = (char *)ws;
     const size_t arr = align256(((size_t)nseg + 1) * 4);
     uint32_t *seg_n = (uint32_t *)wb;
@@ -2695,7 +2695,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     const uint64_t mt = plan_max_tiles(max_ids, nseg);
     const uint64_t units = 2 * mt;
     const uint32_t per_cu = ctx->tune.dec_wg_per_cu;
-    const int slot = timing_begin(ctx, BFSC_OP_DECODE, s);
+    const int slot = timed ? timing_begin(ctx, BFSC_OP_DECODE, s) : -1;
 #define BFSC_DEC_LAUNCH(K, W)                                                                \
     hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \
                        dim3(W * 64), 0, s, a)

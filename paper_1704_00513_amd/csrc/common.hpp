@@ -315,6 +315,9 @@ struct bfsc_ctx {
     uint32_t ev_created;
     // direction-optimizing BFS (bfsc_bfs_set_direction); alpha 0: top-down only
     float bfs_alpha, bfs_beta;
+    // this device's copy of the decoder scratch array of bfsc_decode_noalloc
+    // (its device address, from hipGetSymbolAddress at create)
+    void *noalloc_scratch;
 };
 
 namespace bfsc {
@@ -337,7 +340,7 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
                   uint64_t *fallbacks, uint16_t *feat, const Plan &p, hipStream_t s);
 int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                   uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
-                  void *ws, hipStream_t s);
+                  void *ws, hipStream_t s, bool timed = true);
 size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg);
 int launch_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds,
                      uint32_t nseg, uint64_t *seg_off, hipStream_t s);
