@@ -486,6 +486,7 @@ def extras(ctx, P, torch, g, roots, b, host, N, comp, ms_step, args, mode):
         out["bfs_top_down_only"] = bfs_top_down(ctx, P, torch, g, roots, host)
     out["exchange_root0"] = exchange_leg(ctx, P, torch, g, int(roots[0]), host, args.nseg, mode)
     out["mall_cold"] = mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps)
+    out["bitmap_root0"] = bitmap_leg(ctx, P, torch, g, int(roots[0]))
 
     # per-level pipeline for the first root: graph replay vs eager launches
     dg = P.DeviceGraph.from_host(g)
@@ -599,11 +600,10 @@ def exchange_leg(ctx, P, torch, g, root, host, nseg, mode, reps=3):
     events), the best of `reps` traversals; the levels are checked against a
     plain GPU BFS."""
     V = g.n_vertices
-    S = (V + 31) // 32 * 32
     bounds_h = np.concatenate([[host["seg_lo"][0]], host["seg_hi"][:nseg]]).astype(np.uint32)
-    if nseg * S >= 1 << 32:  # candidate keys are u32: fall back to 16 equal owners
+    if nseg > 256:  # 256 equal owners (65,536 segments per level) at most
         import inputs
-        nseg = 16
+        nseg = 256
         bounds_h = inputs.bounds_equal(V, nseg)
     RR = nseg * nseg
     dg = P.DeviceGraph.from_host(g)
@@ -697,6 +697,74 @@ def exchange_leg(ctx, P, torch, g, root, host, nseg, mode, reps=3):
                            "us_candidates": round(r["us_candidates"], 1), "us_codec": round(r["us_codec"], 1),
                            "us_merge": round(r["us_merge"], 1), "us_bfs_level": round(u, 1)}
                           for r, u in zip(rows, bfs_us)]}
+
+
+def bitmap_leg(ctx, P, torch, g, root, owners=(16, 64), reps=3):
+    """The bitmap codec on the first root's traversal: at every level the
+    frontier and the visited list as bitmaps, split into `owners` equal word
+    ranges (one owner's share each), compressed and decompressed on the GPU
+    and checked word for word; the final visited bitmap is the one a
+    predecessor reduction would exchange.  Ratio = raw bitmap bytes over
+    compressed bytes; GB/s of raw bitmap bytes over encode + decode (stream
+    events, best of `reps`)."""
+    V = g.n_vertices
+    nw = (V + 31) // 32
+    dg = P.DeviceGraph.from_host(g)
+    i32 = dict(dtype=torch.int32, device="cuda")
+    level, parent = torch.empty(V, **i32), torch.empty(V, **i32)
+    fa, fb = torch.empty(V, **i32), torch.empty(V, **i32)
+    la, lb = torch.zeros(1, **i32), torch.zeros(1, **i32)
+    ws = ctx.bfs_workspace(dg, key="bm_bfs")
+    ctx.bfs_init(dg, root, level, parent, fa, la, ws)
+    L = 0
+    while int(la.item()):
+        ctx.bfs_level(dg, L, fa, la, level, parent, fb, lb, ws)
+        fa, fb, la, lb = fb, fa, lb, la
+        L += 1
+    depth = L - 1
+    shifts = torch.arange(32, device="cuda", dtype=torch.int64)
+
+    def pack(mask):
+        m = torch.zeros(nw * 32, dtype=torch.int64, device="cuda")
+        m[:V] = mask.to(torch.int64)
+        w = (m.view(nw, 32) << shifts).sum(dim=1)
+        return torch.where(w >= 1 << 31, w - (1 << 32), w).to(torch.int32).contiguous()
+
+    res = {"levels": depth + 1}
+    for R in owners:
+        seg_w = torch.from_numpy(((np.arange(R + 1, dtype=np.uint64) * nw) // R).view(np.int64)).cuda()
+        cap = P.Context.bitmap_encode_bound(nw, R)
+        out = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+        sbo = torch.zeros(R + 1, dtype=torch.int64, device="cuda")
+        back = torch.empty(nw, **i32)
+        boff = torch.zeros(R + 1, dtype=torch.int64, device="cuda")
+        wse = ctx.workspace(P._lib.OP_BITMAP_ENCODE, nw, R, key="bm_e")
+        wsd = ctx.workspace(P._lib.OP_BITMAP_DECODE, nw, R, key="bm_d")
+        row = {}
+        for kind in ("frontier", "visited"):
+            raw, comp, us = 0, 0, 0.0
+            for Lv in range(depth + 1):
+                bits = pack(level == Lv) if kind == "frontier" else pack((level >= 0) & (level <= Lv))
+                best = None
+                for _ in range(reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    ctx.bitmap_encode(bits, seg_w, R, nw, out, sbo, ws=wse)
+                    ctx.bitmap_decode(out, sbo, R, nw, back, boff, ws=wsd)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    t = e0.elapsed_time(e1) * 1e3
+                    best = t if best is None else min(best, t)
+                assert ctx.sync_status() == 0, "bitmap codec reported an error"
+                assert torch.equal(back, bits), "bitmap round trip differs"
+                raw += 4 * nw
+                comp += int(sbo[-1].item())
+                us += best
+            row[kind] = {"raw_bytes": raw, "compressed_bytes": comp, "ratio": round(raw / max(1, comp), 3),
+                         "GBps": round(raw / max(1e-9, us * 1e-6) / 1e9, 2)}
+        row["final_visited_ratio"] = round(4 * nw / max(1, int(sbo[-1].item())), 3)
+        res["owners_%d" % R] = row
+    return res
 
 
 def mall_cold(ctx, P, torch, b, buf, sbo, dec, doff, N, mode, steps):

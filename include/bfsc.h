@@ -252,7 +252,9 @@ int bfsc_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *b
  * T_p is every neighbour of them, visited or not.  T_p restricted to owner
  * d's range is segment p*nseg + d of a batch (sorted, without repeats), so a
  * vertex that several owners reach is sent once by each: the exchanged
- * volume.  Requires nseg * 32 * ceil(n_vertices / 32) < 2^32.
+ * volume.  Requires nseg <= 65535 and nseg * ceil(n_vertices / 32) below
+ * 2^32 - 2^16 (the owners' bitmaps are indexed by 32-bit word numbers): at
+ * scale 26 up to 2047 owners.
  *
  * Workspace: bfsc_exchange_workspace_size bytes (nseg + 1 bitmaps of
  * n_vertices bits, a queue of high-degree vertices, counters), caller-owned, cleared once by

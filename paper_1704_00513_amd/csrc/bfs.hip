@@ -490,17 +490,16 @@ int launch_bfs_level(bfsc_ctx *ctx, const bfsc_csr *g, int32_t cur_level, const 
 // owners.  Owner p's frontier vertices (those in [bounds[p], bounds[p+1]))
 // expand into owner p's candidate bitmap, visited or not (the expansion
 // kernels of a BFS level, with the candidate visitor); the R bitmaps are
-// compacted as one, in key order p*V + w, which is the order of the
-// segments (p, d) of the batch; the receiver ORs every decoded candidate
+// compacted as one, owner after owner, which is the order of the segments
+// (p, d) of the batch; the receiver ORs every decoded candidate
 // into one bitmap and keeps what is not yet visited.
 
 // Workspace: the merge bitmap (first, so that its place does not depend on
-// R), R candidate bitmaps of S = 32 * ceil(V/32) bits (compacted through a BfsWs view), the
-// segment bounds in key space, the candidate count.
+// R), R candidate bitmaps of ceil(V/32) words (compacted through a BfsWs
+// view), the candidate count.
 struct ExWs {
     uint32_t *merged;
     BfsWs cb;        // next_bm: the R bitmaps back to back (words = R * V/32)
-    uint32_t *keyb;  // [R*R + 1] first key of segment p*R + d
     uint32_t *count; // [4] [0]: candidates found, [1]: kept (capacity)
     uint32_t words;  // V/32 (rounded up)
 };
@@ -528,8 +527,6 @@ static inline ExWs ex_ws_layout(void *ws, uint32_t V, uint64_t n_arcs, uint32_t 
     w.cb.front_bm = nullptr;  // the candidate compaction uses k_ex_emit, which has no frontier bitmap
     w.cb.stat = nullptr;
     w.cb.part = nullptr;
-    w.keyb = (uint32_t *)(b + off);
-    off = align256(off + ((size_t)nseg * nseg + 1) * 4);
     w.count = (uint32_t *)(b + off);
     off = align256(off + 16);
     if (bytes) *bytes = off;
@@ -547,26 +544,43 @@ __global__ void k_ex_zero(uint32_t *a, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0u;
 }
 
-// Keys: owner p's bitmap starts at bit p*S, S = 32 * ceil(V/32), so vertex w
-// of owner p has key p*S + w.  Segment p*R + d holds the keys
-// [p*S + bounds[d], p*S + bounds[d+1]); the owners must cover [0, V) in order
-// (else the batch is flagged invalid).
-__global__ void k_ex_keyb(const uint32_t *bounds, uint32_t R, uint32_t V, uint32_t S, uint32_t *keyb,
-                          uint32_t *err) {
-    const uint32_t RR = R * R;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < RR; i += gridDim.x * blockDim.x)
-        keyb[i] = (i / R) * S + bounds[i % R];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        keyb[RR] = (uint32_t)((uint64_t)R * S);
-        bool ok = bounds[0] == 0 && bounds[R] == V;
-        for (uint32_t r = 0; r < R; ++r) ok = ok && bounds[r] <= bounds[r + 1];
-        if (!ok) raise_err(err, kErrInval);
+// The owners must cover [0, V) in order (else the batch is flagged invalid).
+__global__ void k_ex_check(const uint32_t *bounds, uint32_t R, uint32_t V, uint32_t *err) {
+    bool ok = bounds[0] == 0 && bounds[R] == V;
+    for (uint32_t r = 0; r < R; ++r) ok = ok && bounds[r] <= bounds[r + 1];
+    if (!ok) raise_err(err, kErrInval);
+}
+
+// Owner p's bitmap is words [p W, (p + 1) W) of the concatenation (W =
+// ceil(V/32)), so segment p R + d, owner p's candidates in receiver d's range,
+// starts at bit p 32 W + bounds[d]: its offset in the batch is the number of
+// candidates before that bit, the chunk's prefix (k_bfs_scan) plus the set
+// bits of the chunk's words before it.  One wave per boundary (i = R R is the
+// end); offsets past the capacity are clamped to it.  Runs before the
+// compaction clears the bitmaps.
+__global__ __launch_bounds__(256) void k_ex_segoff(BfsWs ws, const uint32_t *bounds, uint32_t R, uint32_t W,
+                                                   uint64_t cap, uint64_t *seg_off) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t RR = (uint64_t)R * R;
+    const uint64_t NW = (uint64_t)gridDim.x * 4;
+    for (uint64_t i = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i <= RR; i += NW) {
+        const uint64_t p = i / R, d = i % R;
+        const uint64_t bit = i == RR ? 32ull * W * R : p * 32ull * W + bounds[d];
+        const uint64_t word = bit >> 5;
+        const uint64_t c = word / kCompactWords;
+        uint32_t cnt = 0;
+        for (uint64_t q = c * kCompactWords + lane; q < word; q += 64) cnt += __popc(ws.next_bm[q]);
+        if (lane == 0 && (bit & 31)) cnt += __popc(ws.next_bm[word] & ((1u << (bit & 31)) - 1u));
+        cnt = wave_sum(cnt);
+        const uint64_t before = (uint64_t)ws.chunk[c] + cnt;  // chunk[nchunks] holds the total
+        if (lane == 0) seg_off[i] = before < cap ? before : cap;
     }
 }
 
-// The candidates' keys in order (k_bfs_emit with a capacity: keys past cap
-// are dropped), the bitmap cleared for the next call.
-__global__ __launch_bounds__(256) void k_ex_emit(BfsWs ws, uint32_t *keys, uint64_t cap) {
+// The candidates' vertex IDs in order (k_bfs_emit with a capacity: IDs past
+// cap are dropped), the bitmaps cleared for the next call.  Word q of the
+// concatenation is word q mod W of owner q / W.
+__global__ __launch_bounds__(256) void k_ex_emit(BfsWs ws, uint32_t W, uint32_t *ids, uint64_t cap) {
     __shared__ uint32_t s_wt[4];
     const uint32_t c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const uint32_t w0 = c * kCompactWords + tid * 4;
@@ -585,10 +599,11 @@ __global__ __launch_bounds__(256) void k_ex_emit(BfsWs ws, uint32_t *keys, uint6
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         uint32_t v = x[k];
+        const uint32_t vbase = ((w0 + k) % W) * 32u;
         while (v) {
             const uint32_t b = __builtin_ctz(v);
             v &= v - 1;
-            if (pos < cap) keys[pos] = (w0 + k) * 32 + b;
+            if (pos < cap) ids[pos] = vbase + b;
             ++pos;
         }
         if (x[k]) ws.next_bm[w0 + k] = 0u;
@@ -601,13 +616,11 @@ __global__ void k_ex_clamp(uint32_t *count, uint64_t cap, uint32_t *err) {
     if ((uint64_t)n > cap) raise_err(err, kErrCapacity);
 }
 
-// Keys back to vertex IDs; each segment's range.
-__global__ void k_ex_finish(uint32_t *ids, const uint32_t *count, uint32_t S, const uint32_t *bounds, uint32_t R,
-                            uint32_t *seg_lo, uint32_t *seg_hi) {
-    const uint32_t n = count[1];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) ids[i] = ids[i] % S;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R * R; i += stride) {
+// Each segment's range: receiver d's [bounds[d], bounds[d+1]).
+__global__ void k_ex_finish(const uint32_t *bounds, uint32_t R, uint32_t *seg_lo, uint32_t *seg_hi) {
+    const uint64_t RR = (uint64_t)R * R;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < RR; i += stride) {
         seg_lo[i] = bounds[i % R];
         seg_hi[i] = bounds[i % R + 1];
     }
@@ -680,21 +693,20 @@ int launch_candidates(bfsc_ctx *ctx, const bfsc_csr *g, const uint32_t *frontier
     const uint32_t V = g->n_vertices;
     ExWs ws = ex_ws_layout(wsp, V, g->n_arcs, nseg, nullptr);
     const uint32_t grid = (uint32_t)ctx->n_cu * 8;
-    const uint32_t S = ws.words * 32;
-    hipLaunchKernelGGL(k_ex_keyb, dim3((nseg * nseg + 255) / 256), dim3(256), 0, s, bounds, nseg, V, S, ws.keyb,
-                       ctx->err);
+    const uint64_t RR = (uint64_t)nseg * nseg;
+    hipLaunchKernelGGL(k_ex_check, dim3(1), dim3(1), 0, s, bounds, nseg, V, ctx->err);
     const CandVisit vis{bounds, nseg, ws.words, ws.cb.next_bm};
     hipLaunchKernelGGL(k_bfs_expand<CandVisit>, dim3(grid), dim3(kExpandThreads), 0, s, g->row_ptr, g->col_idx,
                        frontier, frontier_len, vis, ws.cb);
     hipLaunchKernelGGL(k_bfs_huge<CandVisit>, dim3((uint32_t)ctx->n_cu * 4), dim3(256), 0, s, g->col_idx, vis, ws.cb);
     hipLaunchKernelGGL(k_bfs_count, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb);
     hipLaunchKernelGGL(k_bfs_scan, dim3(1), dim3(1024), 0, s, ws.cb, ws.count);
-    hipLaunchKernelGGL(k_ex_emit, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb, ids, cap);
+    const uint64_t sw = (RR + 1 + 3) / 4;
+    hipLaunchKernelGGL(k_ex_segoff, dim3((uint32_t)(sw < (uint64_t)grid * 4 ? sw : (uint64_t)grid * 4)), dim3(256), 0,
+                       s, ws.cb, bounds, nseg, ws.words, cap, seg_off);
+    hipLaunchKernelGGL(k_ex_emit, dim3(ws.cb.nchunks), dim3(256), 0, s, ws.cb, ws.words, ids, cap);
     hipLaunchKernelGGL(k_ex_clamp, dim3(1), dim3(1), 0, s, ws.count, cap, ctx->err);
-    if (hipGetLastError() != hipSuccess) return BFSC_E_HIP;
-    const int st = launch_partition(ids, ws.count + 1, ws.keyb, nseg * nseg, seg_off, s);
-    if (st) return st;
-    hipLaunchKernelGGL(k_ex_finish, dim3(grid), dim3(256), 0, s, ids, ws.count, S, bounds, nseg, seg_lo, seg_hi);
+    hipLaunchKernelGGL(k_ex_finish, dim3(grid), dim3(256), 0, s, bounds, nseg, seg_lo, seg_hi);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 

@@ -309,10 +309,12 @@ int bfsc_bfs_set_direction(bfsc_ctx *ctx, float alpha, float beta) {
     return BFSC_OK;
 }
 
-// keys p*V + w of the candidate exchange must fit 32 bits
+// the candidate exchange: the owners' bitmaps together are indexed by 32-bit
+// word numbers (nseg * ceil(V/32) words, with room for the last compaction
+// chunk), and the nseg * nseg segments form one batch
 static bool ex_ok(const bfsc_csr *g, uint32_t nseg) {
-    return g && g->n_vertices > 0 && g->n_vertices <= 0x7FFFFFFFu && nseg > 0 &&
-           (uint64_t)nseg * ((g->n_vertices + 31ull) & ~31ull) <= 0xFFFFFFFFull;
+    return g && g->n_vertices > 0 && g->n_vertices <= 0x7FFFFFFFu && nseg > 0 && nseg <= 65535u &&
+           (uint64_t)nseg * ((g->n_vertices + 31ull) / 32ull) <= 0xFFFFFFFFull - 65536ull;
 }
 
 int bfsc_exchange_workspace_size(const bfsc_csr *g, uint32_t nseg, size_t *bytes) {

@@ -60,24 +60,32 @@ def test_status_strings_and_host_errors(lib):
     assert lib.bfsc_mlp_param_count() == 7011
 
 
-def test_exchange_key_space_limit_is_checked_on_the_host(lib):
-    """Candidate keys are p * 32*ceil(V/32) + w in 32 bits: nseg * 32*ceil(V/32)
-    must stay below 2^32; the BFS and exchange workspaces need no GPU."""
+def test_exchange_owner_limit_is_checked_on_the_host(lib):
+    """The owners' candidate bitmaps are indexed by 32-bit word numbers:
+    nseg * ceil(V/32) must not pass 2^32 - 1 - 2^16, and nseg * nseg segments
+    form one batch (nseg <= 65535); at scale 26 that is 2047 owners.  The BFS
+    and exchange workspaces need no GPU."""
     from paper_1704_00513_amd import _lib
     csr = _lib.CSR()
     csr.n_vertices = 1 << 26
     csr.n_arcs = 1 << 30
     out = ctypes.c_size_t()
     size = lib.bfsc_exchange_workspace_size
-    assert size(ctypes.byref(csr), 63, ctypes.byref(out)) == 0
-    # 63 candidate bitmaps + the merge and frontier bitmaps, V/8 bytes each at least
-    assert out.value >= 64 * (1 << 26) // 8
-    assert size(ctypes.byref(csr), 64, ctypes.byref(out)) == 1
+    for R in (63, 64, 256, 1024, 2047):
+        assert size(ctypes.byref(csr), R, ctypes.byref(out)) == 0, R
+    # R candidate bitmaps + the merge bitmap, V/8 bytes each at least
+    assert out.value >= 2048 * (1 << 26) // 8
+    assert size(ctypes.byref(csr), 2048, ctypes.byref(out)) == 1
     assert size(ctypes.byref(csr), 0, ctypes.byref(out)) == 1
-    csr.n_vertices = (1 << 26) - 31  # rounds up to the same 32-bit stride
-    assert size(ctypes.byref(csr), 64, ctypes.byref(out)) == 1
+    words = (1 << 32) - 1 - (1 << 16)
+    csr.n_vertices = 32 * (words // 4096)
+    assert size(ctypes.byref(csr), 4096, ctypes.byref(out)) == 0
+    csr.n_vertices += 32
+    assert size(ctypes.byref(csr), 4096, ctypes.byref(out)) == 1
+    csr.n_vertices = 1024
+    assert size(ctypes.byref(csr), 65535, ctypes.byref(out)) == 0
+    assert size(ctypes.byref(csr), 65536, ctypes.byref(out)) == 1
     csr.n_vertices = (1 << 26) - 32
-    assert size(ctypes.byref(csr), 64, ctypes.byref(out)) == 0
     bfs = ctypes.c_size_t()
     assert lib.bfsc_bfs_workspace_size(ctypes.byref(csr), ctypes.byref(bfs)) == 0
     assert bfs.value >= 3 * ((1 << 26) - 32) // 8  # visited, next-level and frontier bitmaps

@@ -96,7 +96,9 @@ def exchange_traversal(ctx, g, root, bounds):
 
 
 @pytest.mark.parametrize("kind,scale,seed,nseg", [(inputs.RMAT, 14, 1, 16), (inputs.RMAT, 16, 2, 5),
-                                                  (inputs.UNIFORM, 14, 3, 8), (inputs.RMAT, 12, 4, 1)])
+                                                  (inputs.UNIFORM, 14, 3, 8), (inputs.RMAT, 12, 4, 1),
+                                                  (inputs.RMAT, 14, 7, 100), (inputs.RMAT, 16, 8, 200),
+                                                  (inputs.UNIFORM, 16, 9, 333)])
 def test_exchange_traversal_matches_bfs(ctx, kind, scale, seed, nseg):
     g = inputs.graph(kind, scale, 16, seed)
     root = int(inputs.roots(g, 1, seed)[0])
