@@ -1579,6 +1579,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_select(SelArgs a) {
 
 // ------------------------------------------------------------------ decode
 
+// Workgroups of the block decoder per SIMD that its registers allow.
+#ifndef DEC_OCC
+#define DEC_OCC 6
+#endif
+
 struct DecPlanArgs {
     const uint8_t *in;
     const uint64_t *seg_byte_off;
@@ -1734,18 +1739,14 @@ __device__ __forceinline__ uint32_t block_words(uint32_t cls, uint32_t param, ui
     return cdiv32(m * param, 32) + cdiv32(E, 4) + cdiv32(E * (aux >> 8), 32);
 }
 
-// Decodes and validates one block whose bw payload words start at buf (LDS;
-// words past bw may hold anything and are never taken as payload); writes
-// its IDs to out[ob ..] unless it is damaged.  val: 192 words of LDS (the
-// block's IDs, then a spare slot per lane).
-// FULL: a block of exactly 128 IDs, where every per-lane validity test folds
-// away at compile time.
+// The IDs of one block (lane: xa = ID lane, xb = ID 64 + lane) and whether
+// it passed every check; stores nothing.  FULL: a block of exactly 128 IDs,
+// where every per-lane validity test folds away at compile time.
 template <bool FULL>
-__device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t bw, uint32_t *val,
-                                                 uint32_t cls, uint32_t param, uint32_t aux,
-                                                 uint32_t v0, uint32_t nk, uint32_t hi, bool has_next,
-                                                 uint32_t nxt, uint32_t *out, uint64_t ob,
-                                                 uint64_t out_cap, uint32_t *err, uint32_t lane) {
+__device__ __forceinline__ bool decode_vals(const uint32_t *buf, uint32_t bw, uint32_t *val, uint32_t cls,
+                                            uint32_t param, uint32_t aux, uint32_t v0, uint32_t nk, uint32_t hi,
+                                            bool has_next, uint32_t nxt, uint32_t lane, uint32_t &xa_out,
+                                            uint32_t &xb_out) {
     if constexpr (FULL) {
         nk = kBlock;
         if (cls >= 2 && cls <= 25) {
@@ -1759,17 +1760,9 @@ __device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t b
             const uint32_t sa = wave_incl_scan(da);
             const uint32_t sb = wave_incl_scan(db) + readlane(sa, 63);
             const uint64_t last = (uint64_t)v0 + readlane(sb, 63);
-            if ((zero != 0ull) | (last >= hi) | (has_next & (last >= nxt))) {
-                if (lane == 0) raise_err(err, kErrCorrupt);
-            } else if (ob + kBlock <= out_cap) {
-                out[ob + lane] = v0 + sa;
-                out[ob + 64 + lane] = v0 + sb;
-            } else {
-                if (ob + lane < out_cap) out[ob + lane] = v0 + sa;
-                if (ob + 64 + lane < out_cap) out[ob + 64 + lane] = v0 + sb;
-            }
-            __builtin_amdgcn_wave_barrier();
-            return;
+            xa_out = v0 + sa;
+            xb_out = v0 + sb;
+            return !((zero != 0ull) | (last >= hi) | (has_next & (last >= nxt)));
         }
     } else {
         nk = readfirst(nk);
@@ -1850,16 +1843,31 @@ __device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t b
     }
     const uint32_t last = nk <= 64 ? readlane(xa, nk - 1) : readlane(xb, nk - 65);
     bad |= last >= hi || (has_next && last >= nxt);
-    if (ballot(bad) != 0ull) {
+    xa_out = xa;
+    xb_out = xb;
+    return ballot(bad) == 0ull;
+}
+
+// Decodes and validates one block whose bw payload words start at buf (LDS;
+// words past bw may hold anything and are never taken as payload); writes
+// its IDs to out[ob ..] unless it is damaged.  val: 192 words of LDS (the
+// block's IDs, then a spare slot per lane).
+template <bool FULL>
+__device__ __forceinline__ void decode_one_block(const uint32_t *buf, uint32_t bw, uint32_t *val,
+                                                 uint32_t cls, uint32_t param, uint32_t aux,
+                                                 uint32_t v0, uint32_t nk, uint32_t hi, bool has_next,
+                                                 uint32_t nxt, uint32_t *out, uint64_t ob,
+                                                 uint64_t out_cap, uint32_t *err, uint32_t lane) {
+    uint32_t xa, xb;
+    if (!decode_vals<FULL>(buf, bw, val, cls, param, aux, v0, nk, hi, has_next, nxt, lane, xa, xb)) {
         if (lane == 0) raise_err(err, kErrCorrupt);
+    } else if (FULL && ob + kBlock <= out_cap) {  // uniform: unmasked stores
+        out[ob + lane] = xa;
+        out[ob + 64 + lane] = xb;
     } else {
-        if (FULL && ob + kBlock <= out_cap) {  // uniform: unmasked stores
-            out[ob + lane] = xa;
-            out[ob + 64 + lane] = xb;
-        } else {
-            if (ina && ob + lane < out_cap) out[ob + lane] = xa;
-            if (inb && ob + 64 + lane < out_cap) out[ob + 64 + lane] = xb;
-        }
+        const uint32_t n = FULL ? kBlock : readfirst(nk);
+        if (lane < n && ob + lane < out_cap) out[ob + lane] = xa;
+        if (lane + 64 < n && ob + 64 + lane < out_cap) out[ob + 64 + lane] = xb;
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -1963,6 +1971,95 @@ __device__ __forceinline__ bool dec_bitmap_full(uint32_t px, uint32_t py, uint32
     }
     __builtin_amdgcn_wave_barrier();
     return !bad;
+}
+
+// Chunk c of a full bitmap block whose words sit in LDS at bm (wc of them;
+// the words after them belong to the next block): the pair of words comes to
+// scalar registers by one broadcast read, the second word counting as zero
+// past the block.  Then as bitmap_chunk: each lane with its bit set writes
+// its ID at its rank.
+__device__ __forceinline__ void bitmap_chunk_lds(const uint32_t *bm, uint32_t c, uint32_t wc, uint32_t vl,
+                                                 uint32_t &cnt, uint32_t vbase) {
+    const uint32_t lo = readfirst(bm[2 * c]);
+    const uint32_t h0 = readfirst(bm[2 * c + 1]);
+    const uint32_t hi = 2 * c + 1 < wc ? h0 : 0u;
+    const uint64_t mk = ((uint64_t)hi << 32) | lo;
+    const uint32_t rk = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+    uint32_t b4 = vbase + 4 * min(cnt, kBlock);
+    asm("" : "+s"(b4));  // kept scalar: one v_lshl_add per lane for the address
+    lds_store_lanes(b4 + 4 * rk, vl + 64 * c, mk);
+    cnt += popc64(mk);
+}
+
+// The full-unit path of the decoder: 8 blocks of 128 IDs whose output lies
+// inside the buffer and whose payload (Au words from pu, at most 1,021) fits
+// the wave's LDS window.  The payload is copied into LDS by the memory unit
+// (global_load_lds, 16 bytes per lane, starting at the 16-byte boundary at
+// or below pu, so no load touches a page the payload does not: the words
+// of the unit start at win + delta) with every load in flight at once.  Each
+// block's directory fields come to scalar registers (lane j of e1v / firstv
+// / offv: block j of the group, offsets relative to the unit's first payload
+// word; lane hb + 8 of firstv: the next block's first, when has_last_next).
+// Full bitmap blocks are expanded from the staged words with scalar chunk
+// masks, the other classes by decode_vals; the IDs are stored through a
+// buffer resource over the unit's 1,024 output IDs, so the stores need no
+// per-lane address arithmetic.
+__device__ __forceinline__ void dec_full_unit(const uint32_t *pu, uint32_t Au, uint32_t *win, uint32_t *val,
+                                              uint32_t e1v, uint32_t firstv, uint32_t offv, uint32_t hb,
+                                              uint32_t lo, uint32_t hi, bool has_last_next, uint32_t *dst,
+                                              uint32_t *err, uint32_t lane) {
+    const uint32_t delta = (uint32_t)(((uintptr_t)pu & 15) >> 2);
+    const uint32_t last = (delta + Au - 1) >> 2;  // last 16-byte chunk holding payload (Au >= 1)
+    const uint32_t *base = pu - delta;
+    asm volatile("" ::: "memory");  // earlier LDS reads of win are done before it is overwritten
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i)
+        if (64 * i <= last)
+            __builtin_amdgcn_global_load_lds((const void *)(base + 4 * min(lane + 64 * i, last)),
+                                             (__attribute__((address_space(3))) void *)(win + 256 * i), 16, 0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t *pw = win + delta;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, kHalf * kBlock * 4, 0x00020000);
+    const uint32_t lo4 = 4 * lane;
+    const uint32_t vbase = readfirst(lds_addr(val));
+    for (uint32_t kk = 0; kk < kHalf; ++kk) {
+        const uint32_t j = hb + kk;
+        const uint32_t e1 = readlane(e1v, j), v0 = lo + readlane(firstv, j), o = readlane(offv, j);
+        const bool has_next = kk + 1 < kHalf || has_last_next;
+        const uint32_t nxt = lo + readlane(firstv, j + 1);
+        const uint32_t cls = e1 & 0xFFu, aux = e1 >> 16;
+        const uint32_t *bm = pw + o;
+        uint32_t xa = 0, xb = 0;
+        bool ok;
+        if (cls == kClsBitmap) {
+            const uint32_t nch = (aux + 63) >> 6, wc = (aux + 31) >> 5;
+            if (lane == 0) val[0] = v0;
+            uint32_t cnt = 1;
+            const uint32_t vl = v0 + 1 + lane;
+            for (uint32_t c = 0; c < nch; ++c) bitmap_chunk_lds(bm, c, wc, vl, cnt, vbase);
+            const uint32_t tailw = aux >> 5, tailb = aux & 31;
+            ok = cnt == kBlock && (tailb == 0 || (readfirst(bm[tailw]) >> tailb) == 0u);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            xa = val[lane];
+            xb = val[lane + 64];
+            if (ok) {
+                const uint32_t lst = readlane(xb, 63);
+                ok = !((uint64_t)v0 + (lst - v0) >= (uint64_t)hi || (has_next && lst >= nxt));
+            }
+        } else {
+            ok = decode_vals<true>(bm, 0u, val, cls, (e1 >> 8) & 0xFFu, aux, v0, kBlock, hi, has_next, nxt, lane,
+                                   xa, xb);
+        }
+        if (ok) {
+            __builtin_amdgcn_raw_buffer_store_b32(xa, rs, lo4, kk * kBlock * 4, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(xb, rs, lo4 + 256, kk * kBlock * 4, 0);
+        } else if (lane == 0) {
+            raise_err(err, kErrCorrupt);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 // A block's payload words (wc of them, at word o of the segment's payload
@@ -2166,10 +2263,10 @@ __device__ __forceinline__ void dec_raw(const uint32_t *src, uint32_t n, uint32_
 // in LDS with every load in flight at once; otherwise they are loaded block
 // by block, the next block's words in flight while the current one decodes.
 template <int WAVES, bool STAGE>
-__global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
+__global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
     constexpr uint32_t kWin = kHalf * kBlock;
     constexpr uint32_t kPerLane = kWin / 64;
-    __shared__ uint32_t s_win[WAVES][STAGE ? kWin + 4 : 132];
+    __shared__ uint32_t s_win[WAVES][kWin + 4];
     __shared__ uint32_t s_val[WAVES][192];  // 128 IDs, 64 spare slots
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t units = 2 * readfirst(a.tile_base[a.nseg]);
@@ -2212,10 +2309,11 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
         const uint64_t oo = c.base;
         // lane i < gblk: block k0+i of the group; lane gblk: the next block's first value
         bool bad = false;
-        uint32_t words = 0, cls = 0, param = 0, aux = 0, first = 0;
+        uint32_t words = 0, cls = 0, param = 0, aux = 0, first = 0, e1v = 0;
         if (lane <= gblk && k0 + lane < nb) {
             first = seg[4 + 2 * (k0 + lane)];
             const uint32_t e1 = seg[4 + 2 * (k0 + lane) + 1];
+            e1v = e1;
             if (lane < gblk) {
                 cls = e1 & 0xFFu;
                 param = (e1 >> 8) & 0xFFu;
@@ -2250,6 +2348,16 @@ __global__ __launch_bounds__(WAVES * 64, 8) void k_decode_u(DecArgs a) {
         }
         const uint32_t ub = readlane(off, hb);
         const uint32_t *pay = seg + metaw;
+        if constexpr (!STAGE) {
+            const uint64_t ou = oo + (uint64_t)(k0 + hb) * kBlock;
+            const uint32_t ue = hb + kHalf < gblk ? readlane(off, hb + kHalf) : gt + A;
+            if ((nblk == kHalf) & ((uint64_t)(k0 + hb + kHalf) * kBlock <= n) & (ou + kHalf * kBlock <= a.out_cap) &
+                (ue > ub) & (ue - ub + 3 <= kWin)) {
+                dec_full_unit(pay + ub, ue - ub, win, val, e1v, first, off - ub, hb, lo, hi, k0 + hb + kHalf < nb,
+                              a.out + ou, a.err, lane);
+                continue;
+            }
+        }
         uint32_t pa = 0, pb = 0;
         if constexpr (STAGE) {
             const uint32_t ue = hb + nblk < gblk ? readlane(off, hb + nblk) : gt + A;
