@@ -93,16 +93,27 @@ __device__ __forceinline__ uint32_t ffbl(uint32_t x) { return (uint32_t)__builti
 
 // Largest distance between consecutive set bits of one word (0 if it has
 // fewer than two): one more than the longest run of clear bits strictly
-// between its lowest and highest set bit.
+// between its lowest and highest set bit.  The run is found in five steps
+// with no data-dependent loop: p_k marks the bits that start a run of at
+// least k (p_1 = z, p_2k = p_k & p_k >> k), and the length is built from the
+// largest step down, keeping a step when some run still reaches that far.
 __device__ __forceinline__ uint32_t inner_gap(uint32_t x) {
     if (__popc(x) < 2) return 0u;
     const uint32_t lo = ffbl(x), hi = 31u - (uint32_t)__clz(x);
-    uint32_t z = ~x & ((1u << hi) - 1u) & ~((2u << lo) - 1u);
-    uint32_t run = 0;
-    while (z) {
-        z &= z >> 1;
-        ++run;
-    }
+    const uint32_t z = ~x & ((1u << hi) - 1u) & ~((2u << lo) - 1u);
+    const uint32_t p1 = z, p2 = p1 & (p1 >> 1), p4 = p2 & (p2 >> 2), p8 = p4 & (p4 >> 4), p16 = p8 & (p8 >> 8);
+    // q: bits starting a run of at least `run` (all bits for run = 0)
+    uint32_t q = 0xFFFFFFFFu, run = 0;
+    uint32_t t = q & p16;  // run >= 16 (z has at most 29 bits, so at most one step of 16)
+    if (t) { q = t; run = 16; }
+    t = q & (p8 >> run);
+    if (t) { q = t; run += 8; }
+    t = q & (p4 >> run);
+    if (t) { q = t; run += 4; }
+    t = q & (p2 >> run);
+    if (t) { q = t; run += 2; }
+    t = q & (p1 >> run);
+    if (t) { run += 1; }
     return run + 1u;
 }
 

@@ -2017,7 +2017,10 @@ __device__ __forceinline__ void dec_full_unit(const uint32_t *pu, uint32_t Au, u
         if (64 * i <= last)
             __builtin_amdgcn_global_load_lds((const void *)(base + 4 * min(lane + 64 * i, last)),
                                              (__attribute__((address_space(3))) void *)(win + 256 * i), 16, 0, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // vmcnt(0) (expcnt and lgkmcnt left at their maxima), as a builtin so that
+    // the compiler's wait bookkeeping knows the copy into LDS has landed and
+    // puts no further waits for it before the LDS reads below
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     __builtin_amdgcn_wave_barrier();
     const uint32_t *pw = win + delta;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, kHalf * kBlock * 4, 0x00020000);
