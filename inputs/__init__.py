@@ -91,6 +91,8 @@ class Graph:
         if not h:
             raise MemoryError("graph generation failed (scale=%d)" % scale)
         self._h = h
+        # kept for __del__: module globals may already be gone at interpreter exit
+        self._free = lib.bfsgen_graph_free
         nv, na = ctypes.c_uint32(), ctypes.c_uint64()
         rp, ci = ctypes.POINTER(ctypes.c_uint64)(), ctypes.POINTER(ctypes.c_uint32)()
         lib.bfsgen_graph_info(h, ctypes.byref(nv), ctypes.byref(na), ctypes.byref(rp), ctypes.byref(ci))
@@ -110,7 +112,7 @@ class Graph:
             self._h = None
             self.row_ptr = None
             self.col_idx = None
-            _load().bfsgen_graph_free(h)
+            self._free(h)
 
     @property
     def name(self) -> str:
