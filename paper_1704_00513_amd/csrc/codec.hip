@@ -774,7 +774,7 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
             // that cannot win; a block resolved to PFOR tries every b < wmin
             // (and keeps b = wmin, no exceptions, if none is smaller)
             uint32_t best = bpw, pfb = wmin, pfe = 0;
-            const uint32_t bcap = pf ? wmin : exh & (words >= 3) ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
+            const uint32_t bcap = pf ? wmin : (exh & (words >= 3)) ? min(wmin, (32 * (words - 3)) / m + 1) : 0u;
             uint32_t b = bcap;
             bool live = b > 0;
             while (ballot(live) != 0ull) {
@@ -884,10 +884,10 @@ __device__ __forceinline__ uint32_t enc_unit_r(const uint32_t *src, bool al16, u
             for (uint32_t k = 0; k < 8; ++k) {
                 const uint32_t dk = BFSC_D(k);
                 const bool x = ispf & (dk > mask);
-                k1x = x & (xc == 1) ? k : k1x;
-                d1x = x & (xc == 1) ? dk : d1x;
-                k0x = x & (xc == 0) ? k : k0x;
-                d0x = x & (xc == 0) ? dk : d0x;
+                k1x = (x & (xc == 1)) ? k : k1x;
+                d1x = (x & (xc == 1)) ? dk : d1x;
+                k0x = (x & (xc == 0)) ? k : k0x;
+                d0x = (x & (xc == 0)) ? dk : d0x;
                 xc += x;
             }
             const uint32_t e0 = row_excl_scan(xc);
@@ -929,7 +929,12 @@ struct UnitRange {
     uint32_t begin, end, step;
 };
 __device__ __forceinline__ UnitRange unit_range(uint32_t units, uint32_t waves, uint32_t w, bool strided) {
-    const uint64_t W = (uint64_t)blockIdx.x * waves + w, NW = (uint64_t)gridDim.x * waves;
+    // workgroup b runs on XCD b mod 8: the workgroups are numbered XCD by
+    // XCD, so that neighbouring units (which share lines at their ends) go to
+    // waves behind one L2
+    const uint32_t G = gridDim.x, b = blockIdx.x, x = b & 7u, q = G >> 3, r = G & 7u;
+    const uint32_t vb = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
+    const uint64_t W = (uint64_t)vb * waves + w, NW = (uint64_t)G * waves;
     UnitRange ur;
     if (strided) {
         ur.begin = (uint32_t)W;
@@ -1973,22 +1978,49 @@ __device__ __forceinline__ bool dec_bitmap_full(uint32_t px, uint32_t py, uint32
     return !bad;
 }
 
-// Chunk c of a full bitmap block whose words sit in LDS at bm (wc of them;
-// the words after them belong to the next block): the pair of words comes to
-// scalar registers by one broadcast read, the second word counting as zero
-// past the block.  Then as bitmap_chunk: each lane with its bit set writes
-// its ID at its rank.
-__device__ __forceinline__ void bitmap_chunk_lds(const uint32_t *bm, uint32_t c, uint32_t wc, uint32_t vl,
-                                                 uint32_t &cnt, uint32_t vbase) {
-    const uint32_t lo = readfirst(bm[2 * c]);
-    const uint32_t h0 = readfirst(bm[2 * c + 1]);
-    const uint32_t hi = 2 * c + 1 < wc ? h0 : 0u;
+// One 64-bit chunk (words lo, hi) of a full bitmap block: every lane whose
+// bit is set writes its ID idv at its rank, the set bits below it plus the
+// rank base.  cb is the base as an LDS byte address (one word per rank) and
+// is advanced by the chunk's bits; writes are clamped at cap (rank 128), so
+// a damaged block holding more bits lands in the 64 spare slots after it and
+// is rejected by its count.  The mask, the count and the base stay scalar;
+// each lane spends two mbcnt, an address and the store.
+__device__ __forceinline__ void bitmap_chunk_s(uint32_t lo, uint32_t hi, uint32_t idv, uint32_t &cb,
+                                               uint32_t cap) {
     const uint64_t mk = ((uint64_t)hi << 32) | lo;
     const uint32_t rk = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-    uint32_t b4 = vbase + 4 * min(cnt, kBlock);
+    uint32_t b4 = min(cb, cap);
     asm("" : "+s"(b4));  // kept scalar: one v_lshl_add per lane for the address
-    lds_store_lanes(b4 + 4 * rk, vl + 64 * c, mk);
-    cnt += popc64(mk);
+    lds_store_lanes(b4 + 4 * rk, idv, mk);
+    cb += 4 * popc64(mk);
+}
+
+// A full bitmap block's IDs into val[0 .. 127] from its wc payload words at
+// bm (LDS; the words after them belong to the next block and are not read):
+// two chunks per step from four words, then the one or two chunks left.
+// vbase: LDS byte address of val.  Returns the number of IDs (128 when the
+// block is sound).
+__device__ __forceinline__ uint32_t bitmap_expand_lds(const uint32_t *bm, uint32_t wc, uint32_t v0,
+                                                      uint32_t vbase, uint32_t lane) {
+    uint32_t cb = vbase + 4;  // val[0] is the first ID
+    const uint32_t cap = vbase + 4 * kBlock;
+    uint32_t idv = v0 + 1 + lane;
+    uint32_t q = wc;
+    const uint32_t *bp = bm;
+    for (; q >= 4; q -= 4, bp += 4, idv += 128) {
+        const uint32_t w0 = readfirst(bp[0]), w1 = readfirst(bp[1]);
+        const uint32_t w2 = readfirst(bp[2]), w3 = readfirst(bp[3]);
+        bitmap_chunk_s(w0, w1, idv, cb, cap);
+        bitmap_chunk_s(w2, w3, idv + 64, cb, cap);
+    }
+    if (q >= 2) {
+        bitmap_chunk_s(readfirst(bp[0]), readfirst(bp[1]), idv, cb, cap);
+        q -= 2;
+        bp += 2;
+        idv += 64;
+    }
+    if (q) bitmap_chunk_s(readfirst(bp[0]), 0u, idv, cb, cap);
+    return (cb - vbase) >> 2;
 }
 
 // The full-unit path of the decoder: 8 blocks of 128 IDs whose output lies
@@ -2015,7 +2047,7 @@ __device__ __forceinline__ void dec_full_unit(const uint32_t *pu, uint32_t Au, u
 #pragma unroll
     for (uint32_t i = 0; i < 4; ++i)
         if (64 * i <= last)
-            __builtin_amdgcn_global_load_lds((const void *)(base + 4 * min(lane + 64 * i, last)),
+            __builtin_amdgcn_global_load_lds((const void *)(base + 4 * (min(lane, last - 64 * i) + 64 * i)),
                                              (__attribute__((address_space(3))) void *)(win + 256 * i), 16, 0, 0);
     // vmcnt(0) (expcnt and lgkmcnt left at their maxima), as a builtin so that
     // the compiler's wait bookkeeping knows the copy into LDS has landed and
@@ -2036,11 +2068,8 @@ __device__ __forceinline__ void dec_full_unit(const uint32_t *pu, uint32_t Au, u
         uint32_t xa = 0, xb = 0;
         bool ok;
         if (cls == kClsBitmap) {
-            const uint32_t nch = (aux + 63) >> 6, wc = (aux + 31) >> 5;
             if (lane == 0) val[0] = v0;
-            uint32_t cnt = 1;
-            const uint32_t vl = v0 + 1 + lane;
-            for (uint32_t c = 0; c < nch; ++c) bitmap_chunk_lds(bm, c, wc, vl, cnt, vbase);
+            const uint32_t cnt = bitmap_expand_lds(bm, (aux + 31) >> 5, v0, vbase, lane);
             const uint32_t tailw = aux >> 5, tailb = aux & 31;
             ok = cnt == kBlock && (tailb == 0 || (readfirst(bm[tailw]) >> tailb) == 0u);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2555,7 +2584,7 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_decode_r(DecArgs a) {
                 asm volatile("" ::: "memory");
 #pragma unroll
                 for (uint32_t i = 0; i < 2; ++i)
-                    __builtin_amdgcn_global_load_lds((const void *)(base + 4 * min(lane + 64 * i, last)),
+                    __builtin_amdgcn_global_load_lds((const void *)(base + 4 * (min(lane, last - 64 * i) + 64 * i)),
                                                      (__attribute__((address_space(3))) void *)(dst + 256 * i),
                                                      16, 0, 0);
             }
