@@ -82,35 +82,37 @@ __device__ __forceinline__ void mlp16(const MlpMfma &W, half4_t x, uint32_t lane
 
 // Predicted class of sample lane mod 16: the largest logit, the lowest class
 // on ties, 255 when any of its logits is NaN.  All four lanes of a sample
-// return the same value.
+// return the same value.  A lane visits its classes in increasing order, so
+// inside the lane a later class wins only by a strictly larger logit; the
+// first one (class 4(l/16) < 35) starts the scan, so a lane whose logits
+// are all -inf still names its lowest class.  Written without branches:
+// short-circuit tests would put exec-mask handling around every logit.
 __device__ __forceinline__ uint32_t mlp16_argmax(const float4_t z[3], uint32_t lane) {
     const uint32_t q4 = (lane >> 4) * 4;
-    float best = -__builtin_inff();
-    uint32_t bi = 63, nan = 0;
+    float best = z[0][0];
+    uint32_t bi = q4;
+    bool nan = best != best;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = (t == 0 ? 1 : 0); j < 4; ++j) {
             const uint32_t c = 16u * t + q4 + j;
             const float v = z[t][j];
-            if (c < (uint32_t)kOut) {
-                nan |= v != v;
-                if (v > best || (v == best && c < bi)) {
-                    best = v;
-                    bi = c;
-                }
-            }
+            const bool valid = c < (uint32_t)kOut;
+            nan |= valid & (v != v);
+            const bool take = valid & (v > best);
+            best = take ? v : best;
+            bi = take ? c : bi;
         }
     }
 #pragma unroll
     for (int d = 16; d <= 32; d <<= 1) {
         const float ob = __builtin_bit_cast(float, shfl_xor(__builtin_bit_cast(uint32_t, best), d));
         const uint32_t oi = shfl_xor(bi, d);
-        nan |= shfl_xor(nan, d);
-        if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-        }
+        nan |= shfl_xor((uint32_t)nan, d) != 0u;
+        const bool take = (ob > best) | ((ob == best) & (oi < bi));
+        best = take ? ob : best;
+        bi = take ? oi : bi;
     }
     return nan ? 255u : bi;
 }
