@@ -2023,21 +2023,21 @@ __device__ __forceinline__ uint32_t bitmap_expand_lds(const uint32_t *bm, uint32
     return (cb - vbase) >> 2;
 }
 
-// The full-unit path of the decoder: 8 blocks of 128 IDs whose output lies
-// inside the buffer and whose payload (Au words from pu, at most 1,021) fits
-// the wave's LDS window.  The payload is copied into LDS by the memory unit
-// (global_load_lds, 16 bytes per lane, starting at the 16-byte boundary at
-// or below pu, so no load touches a page the payload does not: the words
-// of the unit start at win + delta) with every load in flight at once.  Each
-// block's directory fields come to scalar registers (lane j of e1v / firstv
-// / offv: block j of the group, offsets relative to the unit's first payload
-// word; lane hb + 8 of firstv: the next block's first, when has_last_next).
-// Full bitmap blocks are expanded from the staged words with scalar chunk
-// masks, the other classes by decode_vals; the IDs are stored through a
-// buffer resource over the unit's 1,024 output IDs, so the stores need no
-// per-lane address arithmetic.
-__device__ __forceinline__ void dec_full_unit(const uint32_t *pu, uint32_t Au, uint32_t *win, uint32_t *val,
-                                              uint32_t e1v, uint32_t firstv, uint32_t offv, uint32_t hb,
+// The full-unit path of the decoder: NB blocks of 128 IDs (a whole group
+// of 16, or half of one) whose output lies inside the buffer and whose
+// payload (Au words from pu, at most 1,021) fits the wave's LDS window.  The
+// payload is copied into LDS by the memory unit (global_load_lds, 16 bytes
+// per lane, starting at the 16-byte boundary at or below pu, so no load
+// touches a page the payload does not: the words of the unit start at win +
+// delta) with every load in flight at once.  Each block's directory fields
+// come to scalar registers (lane j of e1v / firstv / offv: block j of the
+// group, offsets relative to the unit's first payload word; lane hb + NB of
+// firstv: the next block's first, when has_last_next).  Full bitmap blocks
+// are expanded from the staged words with scalar chunk masks, the other
+// classes by decode_vals; the IDs are stored through a buffer resource over
+// the unit's output IDs, so the stores need no per-lane address arithmetic.
+__device__ __forceinline__ void dec_full_unit(uint32_t NB, const uint32_t *pu, uint32_t Au, uint32_t *win,
+                                              uint32_t *val, uint32_t e1v, uint32_t firstv, uint32_t offv, uint32_t hb,
                                               uint32_t lo, uint32_t hi, bool has_last_next, uint32_t *dst,
                                               uint32_t *err, uint32_t lane) {
     const uint32_t delta = (uint32_t)(((uintptr_t)pu & 15) >> 2);
@@ -2055,13 +2055,13 @@ __device__ __forceinline__ void dec_full_unit(const uint32_t *pu, uint32_t Au, u
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __builtin_amdgcn_wave_barrier();
     const uint32_t *pw = win + delta;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, kHalf * kBlock * 4, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, NB * kBlock * 4, 0x00020000);
     const uint32_t lo4 = 4 * lane;
     const uint32_t vbase = readfirst(lds_addr(val));
-    for (uint32_t kk = 0; kk < kHalf; ++kk) {
+    for (uint32_t kk = 0; kk < NB; ++kk) {
         const uint32_t j = hb + kk;
         const uint32_t e1 = readlane(e1v, j), v0 = lo + readlane(firstv, j), o = readlane(offv, j);
-        const bool has_next = kk + 1 < kHalf || has_last_next;
+        const bool has_next = kk + 1 < NB || has_last_next;
         const uint32_t nxt = lo + readlane(firstv, j + 1);
         const uint32_t cls = e1 & 0xFFu, aux = e1 >> 16;
         const uint32_t *bm = pw + o;
@@ -2288,26 +2288,32 @@ __device__ __forceinline__ void dec_raw(const uint32_t *src, uint32_t n, uint32_
     if (ballot(bad) != 0ull && lane == 0) raise_err(err, kErrCorrupt);
 }
 
-// Decode, one wave per unit (half a group: up to 8 blocks).  The wave reads
-// and checks the group's directory entries (one lane per block) and table
-// words, then decodes the unit's blocks in order.  STAGE: the unit's payload
-// words (at most 1024, since every block holds at most 128) are first staged
-// in LDS with every load in flight at once; otherwise they are loaded block
-// by block, the next block's words in flight while the current one decodes.
+// Decode, one wave per unit.  The wave reads and checks the group's
+// directory entries (one lane per block) and table words, then decodes the
+// unit's blocks in order.  STAGE: a unit is half a group (up to 8 blocks)
+// whose payload words (at most 1024, since every block holds at most 128)
+// are first staged in LDS with every load in flight at once.  Otherwise a
+// unit is a whole group: sixteen full blocks whose payload fits the LDS
+// window are decoded in one go (dec_full_unit), any other group half by half
+// (the same for a full half; else block by block, the next block's words in
+// flight while the current one decodes).  Whole groups read and check each
+// directory entry once.
 template <int WAVES, bool STAGE>
 __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
     constexpr uint32_t kWin = kHalf * kBlock;
     constexpr uint32_t kPerLane = kWin / 64;
+    constexpr uint32_t kUnitsPerTile = STAGE ? 2 : 1;
     __shared__ uint32_t s_win[WAVES][kWin + 4];
     __shared__ uint32_t s_val[WAVES][192];  // 128 IDs, 64 spare slots
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t units = 2 * readfirst(a.tile_base[a.nseg]);
+    const uint32_t units = kUnitsPerTile * readfirst(a.tile_base[a.nseg]);
     uint32_t *win = s_win[w];
     uint32_t *val = s_val[w];
     UnitRange ur = unit_range(units, WAVES, w, a.strided);
     SegCursor c;
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
-        const uint32_t t = u >> 1, h = u & 1;
+        const uint32_t t = STAGE ? u >> 1 : u;
+        const uint32_t h0 = STAGE ? (u & 1) : 0u, h1 = STAGE ? h0 + 1 : 2u;  // the halves to decode
         if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
             c.n = readfirst(a.seg_n[c.r]);
             c.form = readfirst(a.seg_form[c.r]);
@@ -2322,7 +2328,7 @@ __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
         }
         if (c.form != 2) {
             // a raw segment's one tile (empty segments have none)
-            if (h == 0) dec_raw((const uint32_t *)(a.in + c.S), c.n, a.out, c.base, a.out_cap, a.err, lane);
+            if (h0 == 0) dec_raw((const uint32_t *)(a.in + c.S), c.n, a.out, c.base, a.out_cap, a.err, lane);
             continue;
         }
         const uint32_t g = t - c.t_first;
@@ -2330,9 +2336,7 @@ __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
         const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
         const uint32_t k0 = g * kGroup;
         const uint32_t gblk = min(kGroup, nb - k0);
-        const uint32_t hb = h * kHalf;
-        if (hb >= gblk) continue;
-        const uint32_t nblk = min(kHalf, gblk - hb);
+        if (h0 * kHalf >= gblk) continue;
         const uint64_t bytes = c.bytes;
         const uint32_t *seg = (const uint32_t *)(a.in + c.S);
         const uint32_t lo = c.lo, hi = c.hi;
@@ -2378,65 +2382,80 @@ __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
             if (lane == 0) raise_err(a.err, kErrCorrupt);
             continue;
         }
-        const uint32_t ub = readlane(off, hb);
         const uint32_t *pay = seg + metaw;
+        uint32_t full_nb = 0;  // a whole group decoded in one go
         if constexpr (!STAGE) {
-            const uint64_t ou = oo + (uint64_t)(k0 + hb) * kBlock;
-            const uint32_t ue = hb + kHalf < gblk ? readlane(off, hb + kHalf) : gt + A;
-            if ((nblk == kHalf) & ((uint64_t)(k0 + hb + kHalf) * kBlock <= n) & (ou + kHalf * kBlock <= a.out_cap) &
-                (ue > ub) & (ue - ub + 3 <= kWin)) {
-                dec_full_unit(pay + ub, ue - ub, win, val, e1v, first, off - ub, hb, lo, hi, k0 + hb + kHalf < nb,
-                              a.out + ou, a.err, lane);
-                continue;
+            const uint64_t og = oo + (uint64_t)k0 * kBlock;
+            if ((gblk == kGroup) & ((uint64_t)(k0 + kGroup) * kBlock <= n) & (og + kGroup * kBlock <= a.out_cap) &
+                (A > 0) & (A + 3 <= kWin)) {
+                full_nb = kGroup;
             }
         }
-        uint32_t pa = 0, pb = 0;
-        if constexpr (STAGE) {
-            const uint32_t ue = hb + nblk < gblk ? readlane(off, hb + nblk) : gt + A;
-            const uint32_t Au = ue - ub;
-            uint32_t v[kPerLane];
-#pragma unroll
-            for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < Au ? pay[ub + lane + 64 * i] : 0u;
-#pragma unroll
-            for (uint32_t i = 0; i < kPerLane; ++i) win[lane + 64 * i] = v[i];
-            if (lane < 4) win[kWin + lane] = 0u;
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        } else {
-            load_payload(pay, ub, readlane(words, hb), lane, pa, pb);
-        }
-        for (uint32_t kk = 0; kk < nblk; ++kk) {
-            const uint32_t j = hb + kk, k = k0 + j;
-            const bool has_next = k + 1 < nb;
-            const uint32_t nxt = has_next ? lo + readlane(first, j + 1) : 0u;
-            const uint32_t nk = min(kBlock, n - k * kBlock);
-            const uint32_t cj = readlane(cls, j);
-            const uint32_t *buf = win;
-            if constexpr (STAGE) {
-                buf = win + (readlane(off, j) - ub);
-            } else {
-                uint32_t na = 0, nbw = 0;
-                if (kk + 1 < nblk) load_payload(pay, readlane(off, j + 1), readlane(words, j + 1), lane, na, nbw);
-                if ((cj == kClsBitmap) & (nk == kBlock)) {
-                    // full bitmap: decoded from the registers
-                    if (!dec_bitmap_full(pa, pb, readlane(aux, j), lo + readlane(first, j), hi, has_next, nxt, val,
-                                         a.out, oo + (uint64_t)k * kBlock, a.out_cap, lane)) {
-                        if (lane == 0) raise_err(a.err, kErrCorrupt);
-                    }
-                    pa = na;
-                    pb = nbw;
+        for (uint32_t h = h0; h < h1; ++h) {
+            const uint32_t hb = h * kHalf;
+            if (hb >= gblk) break;
+            const uint32_t nblk = min(kHalf, gblk - hb);
+            const uint32_t ub = readlane(off, hb);
+            if constexpr (!STAGE) {
+                const uint32_t fb = full_nb ? full_nb : kHalf;
+                const uint64_t ou = oo + (uint64_t)(k0 + hb) * kBlock;
+                const uint32_t ue = full_nb ? gt + A : hb + kHalf < gblk ? readlane(off, hb + kHalf) : gt + A;
+                if (full_nb || ((nblk == kHalf) & ((uint64_t)(k0 + hb + kHalf) * kBlock <= n) &
+                                (ou + kHalf * kBlock <= a.out_cap) & (ue > ub) & (ue - ub + 3 <= kWin))) {
+                    dec_full_unit(fb, pay + ub, ue - ub, win, val, e1v, first, off - ub, hb, lo, hi,
+                                  k0 + hb + fb < nb, a.out + ou, a.err, lane);
+                    if (full_nb) break;
                     continue;
                 }
-                win[lane] = pa;
-                win[lane + 64] = pb;
+            }
+            uint32_t pa = 0, pb = 0;
+            if constexpr (STAGE) {
+                const uint32_t ue = hb + nblk < gblk ? readlane(off, hb + nblk) : gt + A;
+                const uint32_t Au = ue - ub;
+                uint32_t v[kPerLane];
+#pragma unroll
+                for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < Au ? pay[ub + lane + 64 * i] : 0u;
+#pragma unroll
+                for (uint32_t i = 0; i < kPerLane; ++i) win[lane + 64 * i] = v[i];
+                if (lane < 4) win[kWin + lane] = 0u;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                pa = na;
-                pb = nbw;
+            } else {
+                load_payload(pay, ub, readlane(words, hb), lane, pa, pb);
             }
-            decode_block(buf, readlane(words, j), val, cj, readlane(param, j), readlane(aux, j),
-                         lo + readlane(first, j), nk, hi, has_next, nxt, a.out,
-                         oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
+            for (uint32_t kk = 0; kk < nblk; ++kk) {
+                const uint32_t j = hb + kk, k = k0 + j;
+                const bool has_next = k + 1 < nb;
+                const uint32_t nxt = has_next ? lo + readlane(first, j + 1) : 0u;
+                const uint32_t nk = min(kBlock, n - k * kBlock);
+                const uint32_t cj = readlane(cls, j);
+                const uint32_t *buf = win;
+                if constexpr (STAGE) {
+                    buf = win + (readlane(off, j) - ub);
+                } else {
+                    uint32_t na = 0, nbw = 0;
+                    if (kk + 1 < nblk) load_payload(pay, readlane(off, j + 1), readlane(words, j + 1), lane, na, nbw);
+                    if ((cj == kClsBitmap) & (nk == kBlock)) {
+                        // full bitmap: decoded from the registers
+                        if (!dec_bitmap_full(pa, pb, readlane(aux, j), lo + readlane(first, j), hi, has_next, nxt,
+                                             val, a.out, oo + (uint64_t)k * kBlock, a.out_cap, lane)) {
+                            if (lane == 0) raise_err(a.err, kErrCorrupt);
+                        }
+                        pa = na;
+                        pb = nbw;
+                        continue;
+                    }
+                    win[lane] = pa;
+                    win[lane + 64] = pb;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    pa = na;
+                    pb = nbw;
+                }
+                decode_block(buf, readlane(words, j), val, cj, readlane(param, j), readlane(aux, j),
+                             lo + readlane(first, j), nk, hi, has_next, nxt, a.out,
+                             oo + (uint64_t)k * kBlock, a.out_cap, a.err, lane);
+            }
         }
     }
 }
@@ -2833,7 +2852,8 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     a.err = ctx->err;
     a.strided = (ctx->tune.dec_mode >> 1) & 1u;
     const uint64_t mt = plan_max_tiles(max_ids, nseg);
-    const uint64_t units = 2 * mt;
+    // decode units: whole groups in the default variant, halves in the others
+    const uint64_t units = (ctx->tune.dec_mode & 5u) == 1u ? mt : 2 * mt;
     const uint32_t per_cu = ctx->tune.dec_wg_per_cu;
     const int slot = timed ? timing_begin(ctx, BFSC_OP_DECODE, s) : -1;
 #define BFSC_DEC_LAUNCH(K, W)                                                                \
