@@ -1148,13 +1148,16 @@ __device__ __forceinline__ uint32_t unit_predict(const MlpMfma &W, const uint16_
 }
 
 // Pack pass with the learned choice fused in, one wave per unit.  The wave
-// stages the unit's IDs in LDS, computes every block's eight fp16 features,
-// evaluates the network for the unit's blocks at once on the matrix cores
-// (block k is sample k, the other rows zero), resolves each prediction
-// (bitmap if it is valid, bit-pack at the minimal width, PFOR at its best b,
-// the exhaustive choice when the bitmap is invalid or a logit is NaN) and
-// packs the blocks from LDS.  The logits of a sample depend only on its own
-// features, so the classes equal those of the separate selection pass.
+// computes every block's eight fp16 features, evaluates the network for the
+// unit's blocks at once on the matrix cores (block k is sample k, the other
+// columns zero), resolves each prediction (bitmap if it is valid, bit-pack
+// at the minimal width, PFOR at its best b, the exhaustive choice when the
+// bitmap is invalid or a logit is NaN) and packs the blocks.  When there are
+// enough tiles for every wave to get many, a unit is a whole tile and a tile
+// of sixteen full blocks takes one evaluation for both halves (16 samples);
+// otherwise a unit is half a tile.  The logits of a sample depend only on
+// its own features, so the classes equal those of the separate selection
+// pass.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
     constexpr uint32_t kIds = kHalf * kBlock;
@@ -1163,20 +1166,22 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
     // staged IDs (partial units) or the row encoder's payload area (full units)
     __shared__ __align__(16) uint32_t s_ids[WAVES][kUnitStage];
     __shared__ uint32_t s_buf[WAVES][132];
-    __shared__ uint16_t s_x[WAVES][kHalf][kIn];
-    __shared__ uint32_t s_span[WAVES][kHalf];
+    __shared__ uint16_t s_x[WAVES][kGroup][kIn];
+    __shared__ uint32_t s_span[WAVES][kGroup];
     __shared__ uint32_t s_wmin[WAVES][kHalf];
-    __shared__ uint8_t s_sel[WAVES][kHalf];
+    __shared__ uint8_t s_sel[WAVES][kGroup];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     mlp_mfma_stage(&s_w, a.w, tid, WAVES * 64);
     __syncthreads();
-    const uint32_t units = 2 * readfirst(a.p.tile_base[a.nseg]);
+    const uint32_t tiles = readfirst(a.p.tile_base[a.nseg]);
+    const bool by_tile = (uint64_t)tiles >= 8ull * gridDim.x * WAVES;
     uint32_t *sid = s_ids[w];
-    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    UnitRange ur = unit_range(by_tile ? tiles : 2 * tiles, WAVES, w, a.strided);
     SegCursor c;
     int32_t level = 0;
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
-        const uint32_t t = u >> 1, h = u & 1;
+        const uint32_t t = by_tile ? u : u >> 1;
+        const uint32_t h0 = by_tile ? 0u : (u & 1), h1 = by_tile ? 2u : h0 + 1;  // the halves to pack
         if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
             c.bb = readfirst(a.p.blk_base[c.r]);
             c.n = readfirst(a.p.seg_n[c.r]);
@@ -1188,99 +1193,131 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             level = a.seg_level ? (int32_t)readfirst((uint32_t)a.seg_level[c.r]) : 0;
         }
         // the tile's segment, for the place pass
-        if (h == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
+        if (h0 == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
         const uint32_t g = t - c.t_first;
         const uint32_t nb = c.nb;
-        const uint32_t k0 = g * kGroup + h * kHalf;
-        const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
-        uint32_t run = 0;
-        if (nblk) {
+        if (by_tile && nb >= (g + 1) * kGroup && (uint64_t)(g + 1) * kGroup * kBlock <= c.n) {
+            // sixteen full blocks: features of both halves, one evaluation of
+            // the network, then the row packer on each half
             const uint32_t n = c.n, lo = c.lo, hi = c.hi;
-            const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
-            const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
-            if (cnt == kIds) {
-                // full unit: features and packing one block per 16-lane row
-                const bool al16 = ((uintptr_t)src & 15) == 0;
-                unit_features_r(src, al16, lo, hi, n, level, s_x[w], s_span[w], lane, a.err);
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                const uint32_t pred = unit_predict(s_w, s_x[w], kHalf, lane);
-                // resolved selection of block lane (bitmap only when valid; NaN
-                // or an invalid bitmap: the exhaustive choice)
-                if (lane < kHalf) {
-                    const uint32_t sel = pred == 255u ? kSelExhaustive
-                                         : pred == kClsBitmap ? (s_span[w][lane] <= kBitmapMaxSpan ? kSelBitmap
-                                                                                                  : kSelExhaustive)
-                                         : pred <= 33u ? kSelPlain : kSelPfor;
-                    s_sel[w][lane] = (uint8_t)sel;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-                run = enc_unit_r(src, al16, lo, hi, kSelExhaustive, s_sel[w], slot + kSlotDirWords + h * kSlotHalfWords,
-                                 slot + 2 * h * kHalf, sid, lane, a.err);
-                if (lane == 0) a.p.unit_words[u] = run;
-                continue;
-            }
-            uint32_t v[kPerLane];
-#pragma unroll
-            for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
-#pragma unroll
-            for (uint32_t i = 0; i < kPerLane; ++i) sid[lane + 64 * i] = v[i];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            const uint32_t *src = a.ids + c.base + (uint64_t)g * kGroup * kBlock;
+            const bool al16 = ((uintptr_t)src & 15) == 0;
+            for (uint32_t h = 0; h < 2; ++h)
+                unit_features_r(src + h * kIds, al16, lo, hi, n, level, s_x[w] + kHalf * h,
+                                s_span[w] + kHalf * h, lane, a.err);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // features of every block
-            for (uint32_t kk = 0; kk < nblk; ++kk) {
-                const uint32_t nk = readfirst(min(kBlock, cnt - kk * kBlock));
-                const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
-                BlockRegs R;
-                BlockStats S;
-                if (nk == kBlock)
-                    analyze_block(va, vb, kBlock, lo, hi, lane, true, R, S, a.err);
-                else
-                    analyze_block(va, vb, nk, lo, hi, lane, true, R, S, a.err);
-                if (lane == 0) s_wmin[w][kk] = S.wmin;
-                float f[8];
-                block_features(S, n, level, f);
-                float fv = f[0];
-#pragma unroll
-                for (int q = 1; q < 8; ++q) fv = lane == (uint32_t)q ? f[q] : fv;
-                if (lane < 8) s_x[w][kk][lane] = f16bits(fv);
-                if (lane == 0) s_span[w][kk] = S.span;
+            const uint32_t pred = unit_predict(s_w, s_x[w], kGroup, lane);
+            if (lane < kGroup) {
+                const uint32_t sel = pred == 255u ? kSelExhaustive
+                                     : pred == kClsBitmap ? (s_span[w][lane] <= kBitmapMaxSpan ? kSelBitmap
+                                                                                              : kSelExhaustive)
+                                     : pred <= 33u ? kSelPlain : kSelPfor;
+                s_sel[w][lane] = (uint8_t)sel;
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // the network on the unit's blocks
-            const uint32_t pred = unit_predict(s_w, s_x[w], nblk, lane);
-            // resolve and pack
             uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-            uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
-            uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
-            for (uint32_t kk = 0; kk < nblk; ++kk) {
-                const uint32_t nk = min(kBlock, cnt - kk * kBlock);
-                const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
-                const uint32_t p = readlane(pred, kk);
-                const bool bitmap_ok = s_span[w][kk] <= kBitmapMaxSpan;
-                // resolved selection: -1 exhaustive, else the class to use
-                const int sel = p == 255u ? kSelExhaustive
-                                : p == kClsBitmap ? (bitmap_ok ? kSelBitmap : kSelExhaustive)
-                                : p <= 33u ? kSelPlain : kSelPfor;
-                uint32_t *dst = pay + run, d0, d1;
-                if (nk == kBlock) {
-                    run += enc_full(va, vb, lo, hi, sel, d0, d1, dst, s_buf[w], lane, a.err, (int)s_wmin[w][kk]);
-                } else {
-                    // the last block of a segment: the general routine with the
-                    // resolved class (BP at the minimal width is what plain picks)
-                    const int given = sel == kSelBitmap ? (int)kClsBitmap : sel == kSelPfor ? (int)kClsPfor : -1;
-                    const int mode = sel == kSelPlain ? BFSC_SEL_PLAIN_BP : BFSC_SEL_EXHAUSTIVE;
-                    run += enc_block<false, false>(va, vb, nk, lo, hi, mode, given, d0, d1, dst, s_buf[w], nullptr,
-                                                   nullptr, lane, a.err);
-                }
-                dirv = lane == 2 * kk ? d0 : lane == 2 * kk + 1 ? d1 : dirv;
+            for (uint32_t h = 0; h < 2; ++h) {
+                const uint32_t run = enc_unit_r(src + h * kIds, al16, lo, hi, kSelExhaustive, s_sel[w] + kHalf * h,
+                                                slot + kSlotDirWords + h * kSlotHalfWords, slot + 2 * h * kHalf, sid,
+                                                lane, a.err);
+                if (lane == 0) a.p.unit_words[2 * t + h] = run;
             }
-            if (lane < 2 * nblk) slot[2 * h * kHalf + lane] = dirv;
+            continue;
         }
-        if (lane == 0) a.p.unit_words[u] = run;
+        for (uint32_t h = h0; h < h1; ++h) {
+            const uint32_t k0 = g * kGroup + h * kHalf;
+            const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
+            uint32_t run = 0;
+            if (nblk) {
+                const uint32_t n = c.n, lo = c.lo, hi = c.hi;
+                const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
+                const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+                if (cnt == kIds) {
+                    // full unit: features and packing one block per 16-lane row
+                    const bool al16 = ((uintptr_t)src & 15) == 0;
+                    unit_features_r(src, al16, lo, hi, n, level, s_x[w], s_span[w], lane, a.err);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    const uint32_t pred = unit_predict(s_w, s_x[w], kHalf, lane);
+                    // resolved selection of block lane (bitmap only when valid; NaN
+                    // or an invalid bitmap: the exhaustive choice)
+                    if (lane < kHalf) {
+                        const uint32_t sel = pred == 255u ? kSelExhaustive
+                                             : pred == kClsBitmap ? (s_span[w][lane] <= kBitmapMaxSpan ? kSelBitmap
+                                                                                                      : kSelExhaustive)
+                                             : pred <= 33u ? kSelPlain : kSelPfor;
+                        s_sel[w][lane] = (uint8_t)sel;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+                    run = enc_unit_r(src, al16, lo, hi, kSelExhaustive, s_sel[w], slot + kSlotDirWords + h * kSlotHalfWords,
+                                     slot + 2 * h * kHalf, sid, lane, a.err);
+                    if (lane == 0) a.p.unit_words[2 * t + h] = run;
+                    continue;
+                }
+                uint32_t v[kPerLane];
+    #pragma unroll
+                for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
+    #pragma unroll
+                for (uint32_t i = 0; i < kPerLane; ++i) sid[lane + 64 * i] = v[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // features of every block
+                for (uint32_t kk = 0; kk < nblk; ++kk) {
+                    const uint32_t nk = readfirst(min(kBlock, cnt - kk * kBlock));
+                    const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
+                    BlockRegs R;
+                    BlockStats S;
+                    if (nk == kBlock)
+                        analyze_block(va, vb, kBlock, lo, hi, lane, true, R, S, a.err);
+                    else
+                        analyze_block(va, vb, nk, lo, hi, lane, true, R, S, a.err);
+                    if (lane == 0) s_wmin[w][kk] = S.wmin;
+                    float f[8];
+                    block_features(S, n, level, f);
+                    float fv = f[0];
+    #pragma unroll
+                    for (int q = 1; q < 8; ++q) fv = lane == (uint32_t)q ? f[q] : fv;
+                    if (lane < 8) s_x[w][kk][lane] = f16bits(fv);
+                    if (lane == 0) s_span[w][kk] = S.span;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // the network on the unit's blocks
+                const uint32_t pred = unit_predict(s_w, s_x[w], nblk, lane);
+                // resolve and pack
+                uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+                uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
+                uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
+                for (uint32_t kk = 0; kk < nblk; ++kk) {
+                    const uint32_t nk = min(kBlock, cnt - kk * kBlock);
+                    const uint32_t va = sid[kk * kBlock + lane], vb = sid[kk * kBlock + 64 + lane];
+                    const uint32_t p = readlane(pred, kk);
+                    const bool bitmap_ok = s_span[w][kk] <= kBitmapMaxSpan;
+                    // resolved selection: -1 exhaustive, else the class to use
+                    const int sel = p == 255u ? kSelExhaustive
+                                    : p == kClsBitmap ? (bitmap_ok ? kSelBitmap : kSelExhaustive)
+                                    : p <= 33u ? kSelPlain : kSelPfor;
+                    uint32_t *dst = pay + run, d0, d1;
+                    if (nk == kBlock) {
+                        run += enc_full(va, vb, lo, hi, sel, d0, d1, dst, s_buf[w], lane, a.err, (int)s_wmin[w][kk]);
+                    } else {
+                        // the last block of a segment: the general routine with the
+                        // resolved class (BP at the minimal width is what plain picks)
+                        const int given = sel == kSelBitmap ? (int)kClsBitmap : sel == kSelPfor ? (int)kClsPfor : -1;
+                        const int mode = sel == kSelPlain ? BFSC_SEL_PLAIN_BP : BFSC_SEL_EXHAUSTIVE;
+                        run += enc_block<false, false>(va, vb, nk, lo, hi, mode, given, d0, d1, dst, s_buf[w], nullptr,
+                                                       nullptr, lane, a.err);
+                    }
+                    dirv = lane == 2 * kk ? d0 : lane == 2 * kk + 1 ? d1 : dirv;
+                }
+                if (lane < 2 * nblk) slot[2 * h * kHalf + lane] = dirv;
+            }
+            if (lane == 0) a.p.unit_words[2 * t + h] = run;
+        }
     }
 }
 
