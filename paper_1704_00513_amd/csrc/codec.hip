@@ -996,12 +996,17 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
     // wave index made scalar: the unit loop and the segment fields stay in
     // scalar registers
     const uint32_t lane = threadIdx.x & 63, w = readfirst(threadIdx.x >> 6);
-    const uint32_t units = 2 * readfirst(a.p.tile_base[a.nseg]);
+    const uint32_t tiles = readfirst(a.p.tile_base[a.nseg]);
+    // whole tiles per wave when every wave gets many (the segment is then
+    // found once for both halves), else half tiles so that the waves end
+    // evenly
+    const bool by_tile = (uint64_t)tiles >= 8ull * gridDim.x * WAVES;
     uint32_t *sid = s_ids[STAGE || kGrp ? w : 0];
-    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    UnitRange ur = unit_range(by_tile ? tiles : 2 * tiles, WAVES, w, a.strided);
     SegCursor c;
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
-        const uint32_t t = u >> 1, h = u & 1;
+        const uint32_t t = by_tile ? u : u >> 1;
+        const uint32_t h0 = by_tile ? 0u : (u & 1), h1 = by_tile ? 2u : h0 + 1;  // the halves to pack
         if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
             c.bb = readfirst(a.p.blk_base[c.r]);
             c.n = readfirst(a.p.seg_n[c.r]);
@@ -1012,65 +1017,69 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
             c.base = readfirst64(a.seg_off[c.r]);
         }
         // the tile's segment, for the place pass
-        if (h == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
+        if (h0 == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
         const uint32_t g = t - c.t_first;
         const uint32_t bb = c.bb, nb = c.nb;
-        const uint32_t k0 = g * kGroup + h * kHalf;
-        const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
-        uint32_t run = 0;  // payload words of the unit so far
-        if (nblk) {
-            const uint32_t n = c.n;
-            const uint32_t lo = c.lo, hi = c.hi;
-            const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
-            const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
-            uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-            if (kGrp && !a.classes && cnt == kIds) {
-                run = enc_unit_r(src, ((uintptr_t)src & 15) == 0, lo, hi,
-                                 a.mode == BFSC_SEL_PLAIN_BP ? kSelPlain : kSelExhaustive, nullptr,
-                                 slot + kSlotDirWords + h * kSlotHalfWords, slot + 2 * h * kHalf, sid, lane, a.err);
-                if (lane == 0) a.p.unit_words[u] = run;
-                continue;
-            }
-            const uint32_t cl = a.classes && lane < nblk ? (uint32_t)a.classes[bb + k0 + lane] : 0u;
-            uint32_t va = 0, vb = 0;
-            if constexpr (STAGE) {
-                uint32_t v[kPerLane];
-#pragma unroll
-                for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
-#pragma unroll
-                for (uint32_t i = 0; i < kPerLane; ++i) sid[lane + 64 * i] = v[i];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            } else {
-                fetch_block(src, min(kBlock, cnt), lane, va, vb);
-            }
-            uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
-            uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
-            for (uint32_t kk = 0; kk < nblk; ++kk) {
-                const uint32_t nk = min(kBlock, cnt - kk * kBlock);
-                uint32_t na = 0, nbv = 0;
+        for (uint32_t h = h0; h < h1; ++h) {
+            const uint32_t k0 = g * kGroup + h * kHalf;
+            const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
+            uint32_t run = 0;  // payload words of the unit so far
+            if (nblk) {
+                const uint32_t n = c.n;
+                const uint32_t lo = c.lo, hi = c.hi;
+                const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
+                const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+                uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
+                if (kGrp && !a.classes && cnt == kIds) {
+                    run = enc_unit_r(src, ((uintptr_t)src & 15) == 0, lo, hi,
+                                     a.mode == BFSC_SEL_PLAIN_BP ? kSelPlain : kSelExhaustive, nullptr,
+                                     slot + kSlotDirWords + h * kSlotHalfWords, slot + 2 * h * kHalf, sid, lane, a.err);
+                    if (lane == 0) a.p.unit_words[2 * t + h] = run;
+                    continue;
+                }
+                const uint32_t cl = a.classes && lane < nblk ? (uint32_t)a.classes[bb + k0 + lane] : 0u;
+                uint32_t va = 0, vb = 0;
                 if constexpr (STAGE) {
-                    va = sid[kk * kBlock + lane];
-                    vb = sid[kk * kBlock + 64 + lane];
-                } else if (kk + 1 < nblk) {
-                    fetch_block(src + (kk + 1) * kBlock, min(kBlock, cnt - (kk + 1) * kBlock), lane, na, nbv);
+                    uint32_t v[kPerLane];
+#pragma unroll
+                    for (uint32_t i = 0; i < kPerLane; ++i) v[i] = lane + 64 * i < cnt ? src[lane + 64 * i] : 0u;
+#pragma unroll
+                    for (uint32_t i = 0; i < kPerLane; ++i) sid[lane + 64 * i] = v[i];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                } else {
+                    fetch_block(src, min(kBlock, cnt), lane, va, vb);
                 }
-                const int given = a.classes ? (int)readlane(cl, kk) : -1;
-                uint32_t *dst = pay + run, d0, d1;
-                run += nk == kBlock
-                           ? enc_block<true, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, d0, d1, dst, s_buf[w],
-                                                       s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane, a.err)
-                           : enc_block<false, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, d0, d1, dst, s_buf[w],
-                                                        s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane, a.err);
-                dirv = lane == 2 * kk ? d0 : lane == 2 * kk + 1 ? d1 : dirv;
-                if constexpr (!STAGE) {
-                    va = na;
-                    vb = nbv;
+                uint32_t *pay = slot + kSlotDirWords + h * kSlotHalfWords;
+                uint32_t dirv = 0;  // lane 2k, 2k+1: directory entry of block k
+                for (uint32_t kk = 0; kk < nblk; ++kk) {
+                    const uint32_t nk = min(kBlock, cnt - kk * kBlock);
+                    uint32_t na = 0, nbv = 0;
+                    if constexpr (STAGE) {
+                        va = sid[kk * kBlock + lane];
+                        vb = sid[kk * kBlock + 64 + lane];
+                    } else if (kk + 1 < nblk) {
+                        fetch_block(src + (kk + 1) * kBlock, min(kBlock, cnt - (kk + 1) * kBlock), lane, na, nbv);
+                    }
+                    const int given = a.classes ? (int)readlane(cl, kk) : -1;
+                    uint32_t *dst = pay + run, d0, d1;
+                    run += nk == kBlock
+                               ? enc_block<true, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, d0, d1, dst, s_buf[w],
+                                                           s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane,
+                                                           a.err)
+                               : enc_block<false, SCANPACK>(va, vb, nk, lo, hi, a.mode, given, d0, d1, dst, s_buf[w],
+                                                            s_pj[SCANPACK ? w : 0], s_dj[SCANPACK ? w : 0], lane,
+                                                            a.err);
+                    dirv = lane == 2 * kk ? d0 : lane == 2 * kk + 1 ? d1 : dirv;
+                    if constexpr (!STAGE) {
+                        va = na;
+                        vb = nbv;
+                    }
                 }
+                if (lane < 2 * nblk) slot[2 * h * kHalf + lane] = dirv;
             }
-            if (lane < 2 * nblk) slot[2 * h * kHalf + lane] = dirv;
+            if (lane == 0) a.p.unit_words[2 * t + h] = run;
         }
-        if (lane == 0) a.p.unit_words[u] = run;
     }
 }
 
@@ -1253,8 +1262,9 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
-                    run = enc_unit_r(src, al16, lo, hi, kSelExhaustive, s_sel[w], slot + kSlotDirWords + h * kSlotHalfWords,
-                                     slot + 2 * h * kHalf, sid, lane, a.err);
+                    run = enc_unit_r(src, al16, lo, hi, kSelExhaustive, s_sel[w],
+                                     slot + kSlotDirWords + h * kSlotHalfWords, slot + 2 * h * kHalf, sid, lane,
+                                     a.err);
                     if (lane == 0) a.p.unit_words[2 * t + h] = run;
                     continue;
                 }
@@ -2787,12 +2797,17 @@ int launch_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, in
     if (fused_learned) {
         // staged units; at most 8 waves per workgroup (the network is staged
         // once per workgroup)
+#define BFSC_PACK_L(W)                                                                          \
+    hipLaunchKernelGGL((k_enc_pack_l<W>),                                                          \
+                       dim3(resident_grid(ctx, (const void *)k_enc_pack_l<W>, W * 64, per_cu, units)), \
+                       dim3(W * 64), 0, s, a)
         switch (waves) {
-            case 1: hipLaunchKernelGGL((k_enc_pack_l<1>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<1>, 64, per_cu, units)), dim3(64), 0, s, a); break;
-            case 2: hipLaunchKernelGGL((k_enc_pack_l<2>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<2>, 128, per_cu, units)), dim3(128), 0, s, a); break;
-            case 8: case 16: hipLaunchKernelGGL((k_enc_pack_l<8>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<8>, 512, per_cu, units)), dim3(512), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_enc_pack_l<4>), dim3(resident_grid(ctx, (const void *)k_enc_pack_l<4>, 256, per_cu, units)), dim3(256), 0, s, a); break;
+            case 1: BFSC_PACK_L(1); break;
+            case 2: BFSC_PACK_L(2); break;
+            case 8: case 16: BFSC_PACK_L(8); break;
+            default: BFSC_PACK_L(4); break;
         }
+#undef BFSC_PACK_L
     } else
     switch (waves) {
 #define BFSC_PACK_LAUNCH(K, W)                                                               \
