@@ -1086,13 +1086,13 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
 // The eight fp16 features (block_features) of a full unit's 8 blocks, one
 // block per 16-lane row in two passes as in enc_unit_r: x[k][0..7] and the
 // span of block k in span[k] (LDS).  The statistics are the ones
-// analyze_block computes for a block of 128 IDs.
-__device__ __forceinline__ void unit_features_r(const uint32_t *src, bool al16, uint32_t lo, uint32_t hi,
-                                                uint32_t seg_n, int32_t level, uint16_t (*x)[kIn],
-                                                uint32_t *span_out, uint32_t lane, uint32_t *err) {
+// analyze_block computes for a block of 128 IDs.  The IDs are not checked
+// here: the row packer that follows checks the same words and reports a
+// bad block (its stream is then void, whatever class was predicted).
+__device__ __forceinline__ void unit_features_r(const uint32_t *src, bool al16, uint32_t seg_n, int32_t level,
+                                                uint16_t (*x)[kIn], uint32_t *span_out, uint32_t lane) {
     constexpr uint32_t m = kBlock - 1;
     const uint32_t ri = lane & 15, r = lane >> 4;
-    const uint64_t all = ballot(true);
     const int32_t L = level < 0 ? 0 : (level > 63 ? 63 : level);
 #pragma unroll 1
     for (uint32_t p = 0; p < 2; ++p) {
@@ -1107,32 +1107,27 @@ __device__ __forceinline__ void unit_features_r(const uint32_t *src, bool al16, 
             for (uint32_t k = 0; k < 8; ++k) v[k] = ps[k];
         }
         const uint32_t pv = dpp<0x111>(v[0], v[7]);  // the row's first lane: its own first ID
-        uint64_t okm = ballot(ri == 0 || v[0] > pv);
         uint32_t dmax = v[0] - pv, dmin = ri ? v[0] - pv : 0xFFFFFFFFu;
 #pragma unroll
         for (uint32_t k = 1; k < 8; ++k) {
-            okm &= ballot(v[k] > v[k - 1]);
             dmax = max(dmax, v[k] - v[k - 1]);
             dmin = min(dmin, v[k] - v[k - 1]);
         }
         const uint32_t v0 = dpp<0x150>(v[0], v[0]), vl = dpp<0x15F>(v[7], v[7]);
-        okm &= ballot((v0 >= lo) & (vl < hi));
-        if (okm != all) {
-            if (lane == 0) raise_err(err, kErrInval);
-        }
         const uint32_t wmin = bitlen32(row_max(dmax)), mn = row_min(dmin), span = vl - v0;
-        float f[8];
-        f[0] = 1.0f;
-        f[1] = (float)bitlen32(mn) / 32.0f;
-        f[2] = (float)wmin / 32.0f;
-        f[3] = (float)bitlen32(span / m) / 32.0f;
-        f[4] = (float)bitlen32(span) / 32.0f;
-        f[5] = __fdiv_rn((float)kBlock, (float)((uint64_t)span + 1ull));
-        f[6] = (float)L / 64.0f;
-        f[7] = (float)bitlen32(seg_n) / 32.0f;
-        float fv = f[0];
-#pragma unroll
-        for (uint32_t q = 1; q < 8; ++q) fv = ri == q ? f[q] : fv;
+        // lane ri of the row produces feature ri: the five bit-length
+        // features share one conversion (a bit length over 32 is exact in
+        // fp32 either way)
+        const uint32_t bl = ri == 1 ? bitlen32(mn)
+                            : ri == 2 ? wmin
+                            : ri == 3 ? bitlen32(span / m)
+                            : ri == 4 ? bitlen32(span)
+                                      : bitlen32(seg_n);
+        float fv = (float)bl * (1.0f / 32.0f);
+        fv = ri == 0   ? 1.0f
+             : ri == 5 ? __fdiv_rn((float)kBlock, (float)((uint64_t)span + 1ull))
+             : ri == 6 ? (float)L / 64.0f
+                       : fv;
         if (ri < 8) x[4 * p + r][ri] = f16bits(fv);
         if (ri == 0) span_out[4 * p + r] = span;
     }
@@ -1212,8 +1207,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             const uint32_t *src = a.ids + c.base + (uint64_t)g * kGroup * kBlock;
             const bool al16 = ((uintptr_t)src & 15) == 0;
             for (uint32_t h = 0; h < 2; ++h)
-                unit_features_r(src + h * kIds, al16, lo, hi, n, level, s_x[w] + kHalf * h,
-                                s_span[w] + kHalf * h, lane, a.err);
+                unit_features_r(src + h * kIds, al16, n, level, s_x[w] + kHalf * h, s_span[w] + kHalf * h, lane);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
             const uint32_t pred = unit_predict(s_w, s_x[w], kGroup, lane);
@@ -1246,7 +1240,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
                 if (cnt == kIds) {
                     // full unit: features and packing one block per 16-lane row
                     const bool al16 = ((uintptr_t)src & 15) == 0;
-                    unit_features_r(src, al16, lo, hi, n, level, s_x[w], s_span[w], lane, a.err);
+                    unit_features_r(src, al16, n, level, s_x[w], s_span[w], lane);
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     const uint32_t pred = unit_predict(s_w, s_x[w], kHalf, lane);
