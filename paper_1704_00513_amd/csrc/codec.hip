@@ -1083,37 +1083,43 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
     }
 }
 
-// The eight fp16 features (block_features) of a full unit's 8 blocks, one
-// block per 16-lane row in two passes as in enc_unit_r: x[k][0..7] and the
-// span of block k in span[k] (LDS).  The statistics are the ones
-// analyze_block computes for a block of 128 IDs.  The IDs are not checked
-// here: the row packer that follows checks the same words and reports a
-// bad block (its stream is then void, whatever class was predicted).
+// The eight fp16 features (block_features) of NP x 4 full blocks (NP = 2:
+// a unit, 4: a tile), one block per 16-lane row in NP passes as in
+// enc_unit_r: x[k][0..7] and the span of block k in span[k] (LDS).  The
+// loads of every pass are issued before the first pass is worked on.  The
+// statistics are the ones analyze_block computes for a block of 128 IDs.
+// The IDs are not checked here: the row packer that follows checks the same
+// words and reports a bad block (its stream is then void, whatever class was
+// predicted).
+template <uint32_t NP>
 __device__ __forceinline__ void unit_features_r(const uint32_t *src, bool al16, uint32_t seg_n, int32_t level,
                                                 uint16_t (*x)[kIn], uint32_t *span_out, uint32_t lane) {
     constexpr uint32_t m = kBlock - 1;
     const uint32_t ri = lane & 15, r = lane >> 4;
     const int32_t L = level < 0 ? 0 : (level > 63 ? 63 : level);
-#pragma unroll 1
-    for (uint32_t p = 0; p < 2; ++p) {
-        uint32_t v[8];
+    uint32_t v[NP][8];
+#pragma unroll
+    for (uint32_t p = 0; p < NP; ++p) {
         const uint32_t *ps = src + 512 * p + 8 * lane;
         if (al16) {
             const uint4 x0 = ((const uint4 *)ps)[0], x1 = ((const uint4 *)ps)[1];
-            v[0] = x0.x, v[1] = x0.y, v[2] = x0.z, v[3] = x0.w;
-            v[4] = x1.x, v[5] = x1.y, v[6] = x1.z, v[7] = x1.w;
+            v[p][0] = x0.x, v[p][1] = x0.y, v[p][2] = x0.z, v[p][3] = x0.w;
+            v[p][4] = x1.x, v[p][5] = x1.y, v[p][6] = x1.z, v[p][7] = x1.w;
         } else {
 #pragma unroll
-            for (uint32_t k = 0; k < 8; ++k) v[k] = ps[k];
+            for (uint32_t k = 0; k < 8; ++k) v[p][k] = ps[k];
         }
-        const uint32_t pv = dpp<0x111>(v[0], v[7]);  // the row's first lane: its own first ID
-        uint32_t dmax = v[0] - pv, dmin = ri ? v[0] - pv : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (uint32_t p = 0; p < NP; ++p) {
+        const uint32_t pv = dpp<0x111>(v[p][0], v[p][7]);  // the row's first lane: its own first ID
+        uint32_t dmax = v[p][0] - pv, dmin = ri ? v[p][0] - pv : 0xFFFFFFFFu;
 #pragma unroll
         for (uint32_t k = 1; k < 8; ++k) {
-            dmax = max(dmax, v[k] - v[k - 1]);
-            dmin = min(dmin, v[k] - v[k - 1]);
+            dmax = max(dmax, v[p][k] - v[p][k - 1]);
+            dmin = min(dmin, v[p][k] - v[p][k - 1]);
         }
-        const uint32_t v0 = dpp<0x150>(v[0], v[0]), vl = dpp<0x15F>(v[7], v[7]);
+        const uint32_t v0 = dpp<0x150>(v[p][0], v[p][0]), vl = dpp<0x15F>(v[p][7], v[p][7]);
         const uint32_t wmin = bitlen32(row_max(dmax)), mn = row_min(dmin), span = vl - v0;
         // lane ri of the row produces feature ri: the five bit-length
         // features share one conversion (a bit length over 32 is exact in
@@ -1206,8 +1212,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             const uint32_t n = c.n, lo = c.lo, hi = c.hi;
             const uint32_t *src = a.ids + c.base + (uint64_t)g * kGroup * kBlock;
             const bool al16 = ((uintptr_t)src & 15) == 0;
-            for (uint32_t h = 0; h < 2; ++h)
-                unit_features_r(src + h * kIds, al16, n, level, s_x[w] + kHalf * h, s_span[w] + kHalf * h, lane);
+            unit_features_r<4>(src, al16, n, level, s_x[w], s_span[w], lane);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
             const uint32_t pred = unit_predict(s_w, s_x[w], kGroup, lane);
@@ -1240,7 +1245,7 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
                 if (cnt == kIds) {
                     // full unit: features and packing one block per 16-lane row
                     const bool al16 = ((uintptr_t)src & 15) == 0;
-                    unit_features_r(src, al16, n, level, s_x[w], s_span[w], lane);
+                    unit_features_r<2>(src, al16, n, level, s_x[w], s_span[w], lane);
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     const uint32_t pred = unit_predict(s_w, s_x[w], kHalf, lane);
@@ -1809,6 +1814,41 @@ __device__ __forceinline__ bool decode_vals(const uint32_t *buf, uint32_t bw, ui
             xa_out = v0 + sa;
             xb_out = v0 + sb;
             return !((zero != 0ull) | (last >= hi) | (has_next & (last >= nxt)));
+        }
+        if ((cls == kClsPfor) & (param + (aux >> 8) <= 24)) {
+            // PFOR whose deltas have at most 24 bits (b low bits, h high bits
+            // in the exceptions): as for the bit-pack case no prefix sum can
+            // wrap, so with every delta >= 1 only the last ID is checked; the
+            // exception positions are checked as always (inside the block,
+            // strictly increasing)
+            constexpr uint32_t m = kBlock - 1;
+            const uint32_t b = param, E = aux & 0xFFu, h = aux >> 8;
+            const uint32_t lw = cdiv32(m * b, 32), qw = cdiv32(E, 4);
+            uint32_t da = ((lane != 0) & (b != 0)) ? get_field(buf, (lane - 1) * b, b) : 0u;
+            uint32_t db = b ? get_field(buf, (63 + lane) * b, b) : 0u;
+            val[lane] = 0u;
+            val[lane + 64] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            uint32_t p = 0;
+            if (lane < E) {
+                p = (buf[lw + (lane >> 2)] >> (8 * (lane & 3))) & 0xFFu;
+                const uint32_t hv = h ? get_field(buf + lw + qw, lane * h, h) : 0u;
+                if (p < m) val[p + 1] = hv << b;
+            }
+            const uint32_t pp = lane_prev(p, 0u);
+            const bool badx = (lane < E) & ((p >= m) | ((lane > 0) & (p <= pp)));
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            da |= val[lane];
+            db |= val[lane + 64];
+            const uint64_t bad = ballot(badx) | ballot((lane != 0) & (da == 0u)) | ballot(db == 0u);
+            const uint32_t sa = wave_incl_scan(da);
+            const uint32_t sb = wave_incl_scan(db) + readlane(sa, 63);
+            const uint64_t last = (uint64_t)v0 + readlane(sb, 63);
+            xa_out = v0 + sa;
+            xb_out = v0 + sb;
+            return !((bad != 0ull) | (last >= hi) | (has_next & (last >= nxt)));
         }
     } else {
         nk = readfirst(nk);

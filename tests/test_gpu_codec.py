@@ -58,6 +58,12 @@ def batches():
     gaps[::137] = 1 << 27
     ids = np.concatenate([[5], 5 + np.cumsum(gaps)]).astype(np.uint32)
     out.append(("pfor", oracle.batch_from_frontier(ids, np.array([0, 0xFFFFFFFF], np.uint32), 4)))
+    # PFOR with narrow exceptions (low and high parts within 24 bits) over
+    # whole groups of full blocks
+    gaps = np.full(6000, 5, np.int64)
+    gaps[::97] = 1 << 19
+    ids = np.concatenate([[7], 7 + np.cumsum(gaps)]).astype(np.uint32)
+    out.append(("pfor24", oracle.batch_from_frontier(ids, np.array([0, 1 << 31], np.uint32), 4)))
     top = np.array([0, 1, 0xFFFFFF00, 0xFFFFFFF0, 0xFFFFFFFD], np.uint32)
     out.append(("top", Batch(top, [0, 5], [0], [0xFFFFFFFE], [0])))
     # all segments empty but one
@@ -181,7 +187,7 @@ def test_capacity_is_reported(ctx, dec_mode):
 def test_damaged_streams_agree_with_oracle(ctx, dec_mode):
     ctx.set_tune(dec_mode=dec_mode)
     rng = np.random.default_rng(9)
-    for name, b in [x for x in batches() if x[0] in ("clustered", "pfor", "s16-L3", "zipf256")]:
+    for name, b in [x for x in batches() if x[0] in ("clustered", "pfor", "pfor24", "s16-L3", "zipf256")]:
         stream, sbo = oracle.encode(b)
         log("damage case=%s bytes=%d" % (name, stream.size))
         for trial in range(60):
