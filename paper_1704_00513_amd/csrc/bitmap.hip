@@ -36,13 +36,14 @@ __host__ __device__ constexpr uint64_t bm_max_blocks(uint64_t max_words, uint32_
 struct BmWs {
     uint32_t *blk_base;  // [nseg+1] first block of each segment
     uint32_t *ne_base;   // [nseg+1] non-empty segments before each one
-    uint32_t *seg_pop;   // [nseg+1] set bits per segment (encode), seen bits (decode)
+    uint32_t *seg_pop;   // [nseg+1] set bits per segment (encode)
     uint64_t *out_off;   // [nseg+1] decode: output word offset of each segment (caller's array)
     uint32_t *carry;     // [4 x prep chunks] per chunk of segments: blocks, non-empty
                          // segments (encode) / blocks, words low, words high (decode)
     uint32_t *info;      // [2 x max blocks] class | width << 8 | count << 16, first
     uint32_t *pw;        // [max blocks + 1] payload words -> their exclusive prefix
     uint32_t *pw_chunk;  // [scan chunks]
+    uint32_t *bpop;      // [max blocks] set bits per block (encode: of the input, decode: of the output)
     uint32_t max_blocks;
 };
 
@@ -65,6 +66,8 @@ __host__ __device__ inline size_t bm_ws_layout(void *ws, uint64_t max_words, uin
     off = align256(off + (mb + 1) * 4);
     if (w) w->pw_chunk = (uint32_t *)(b + off);
     off = align256(off + ((mb + 1 + kBmScan - 1) / kBmScan) * 4);
+    if (w) w->bpop = (uint32_t *)(b + off);
+    off = align256(off + mb * 4);
     if (w) {
         w->max_blocks = (uint32_t)mb;
         w->out_off = nullptr;
@@ -192,7 +195,6 @@ __global__ __launch_bounds__(1024) void k_bm_plan_local(BmArgs a) {
         const uint64_t nw = bad ? 0ull : e - s;
         nb = (uint32_t)((nw + kBmBlk - 1) / kBmBlk);
         ne = nw ? 1u : 0u;
-        a.w.seg_pop[r] = 0u;
     }
     uint32_t tb, te;
     const uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_bm_size(BmArgs a) {
         if (lane == 0) {
             *(uint2 *)(a.w.info + 2 * (uint64_t)k) = make_uint2(ch.cls | ch.width << 8 | ch.count << 16, ch.first);
             a.w.pw[k] = ch.words;
-            atomicAdd(a.w.seg_pop + B.r, pop);
+            a.w.bpop[k] = pop;
         }
     }
 }
@@ -318,18 +320,31 @@ __global__ __launch_bounds__(1024) void k_bm_scan_fix(BmArgs a) {
 }
 
 // Byte offset of segment r: 16 bytes per non-empty segment, 12 per block and
-// 4 per payload word before it.
+// 4 per payload word before it.  The segment's set bits (its header field)
+// are the sum of its blocks' counts, taken by one wave per segment: counted
+// block by block into one word per segment, all of a segment's blocks would
+// have hit the same address.
 __device__ __forceinline__ uint64_t bm_seg_start(const BmArgs &a, uint32_t r) {
     const uint32_t b = min(a.w.blk_base[r], a.w.max_blocks);
     return 16ull * a.w.ne_base[r] + 12ull * b + 4ull * a.w.pw[b];
 }
 
-__global__ void k_bm_offsets(BmArgs a) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_bm_offsets(BmArgs a) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t r = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (r > a.nseg) return;
-    const uint64_t S = bm_seg_start(a, r);
-    a.seg_byte_off_out[r] = S;
-    if (r == a.nseg && S > a.out_cap) raise_err(a.err, kErrCapacity);
+    if (lane == 0) {
+        const uint64_t S = bm_seg_start(a, r);
+        a.seg_byte_off_out[r] = S;
+        if (r == a.nseg && S > a.out_cap) raise_err(a.err, kErrCapacity);
+    }
+    if (r == a.nseg) return;
+    const uint32_t b0 = min(readfirst(a.w.blk_base[r]), a.w.max_blocks);
+    const uint32_t b1 = min(readfirst(a.w.blk_base[r + 1]), a.w.max_blocks);
+    uint32_t sum = 0;
+    for (uint32_t k = b0 + lane; k < b1; k += 64) sum += a.w.bpop[k];
+    sum = wave_sum(sum);
+    if (lane == 0) a.w.seg_pop[r] = sum;
 }
 
 __device__ __forceinline__ void or_word(uint32_t *buf, uint32_t pos, uint32_t v) {
@@ -442,7 +457,6 @@ __global__ __launch_bounds__(1024) void k_bmd_plan_local(BmArgs a) {
             nw = 0;
             nb = 0;
         }
-        a.w.seg_pop[r] = 0u;
     }
     uint32_t tb;
     const uint32_t xb = wg_excl_scan(nb, s_tmp, &tb);
@@ -612,18 +626,26 @@ __global__ __launch_bounds__(WAVES * 64) void k_bmd_blocks(BmArgs a) {
         if (lane < n32 && o + lane < a.out_cap) a.out_words[o + lane] = xa;
         if (lane + 64 < n32 && o + 64 + lane < a.out_cap) a.out_words[o + 64 + lane] = xb;
         const uint32_t seen = wave_sum(__popc(xa) + __popc(xb));
-        if (lane == 0) atomicAdd(a.w.seg_pop + r, seen);
+        if (lane == 0) a.w.bpop[k] = seen;
     }
 }
 
-// Every compressed segment's popcount against its header.
-__global__ void k_bmd_final(BmArgs a) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+// Every compressed segment's popcount against its header: one wave per
+// segment adds up its blocks' counts.  (A block found damaged has left its
+// count unwritten, but it has reported the stream already.)
+__global__ __launch_bounds__(256) void k_bmd_final(BmArgs a) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t r = readfirst(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (r >= a.nseg) return;
-    const uint64_t s = a.seg_byte_off[r], e = a.seg_byte_off[r + 1];
-    if (e <= s || a.w.blk_base[r + 1] == a.w.blk_base[r]) return;
+    const uint64_t s = readfirst64(a.seg_byte_off[r]), e = readfirst64(a.seg_byte_off[r + 1]);
+    const uint32_t b0 = min(readfirst(a.w.blk_base[r]), a.w.max_blocks);
+    const uint32_t b1 = min(readfirst(a.w.blk_base[r + 1]), a.w.max_blocks);
+    if (e <= s || b1 <= b0) return;
+    uint32_t sum = 0;
+    for (uint32_t k = b0 + lane; k < b1; k += 64) sum += a.w.bpop[k];
+    sum = wave_sum(sum);
     const uint32_t *h = (const uint32_t *)(a.in + s);
-    if (h[1] != a.w.seg_pop[r]) raise_err(a.err, kErrCorrupt);
+    if (lane == 0 && h[1] != sum) raise_err(a.err, kErrCorrupt);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -661,7 +683,7 @@ int launch_bitmap_encode(bfsc_ctx *ctx, const uint32_t *bits, const uint64_t *se
     const uint32_t sc = (uint32_t)((a.w.max_blocks + 1ull + kBmScan - 1) / kBmScan);
     hipLaunchKernelGGL(k_bm_scan_local, dim3(sc), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_bm_scan_fix, dim3(sc), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_bm_offsets, dim3((nseg + 1 + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bm_offsets, dim3((nseg + 1 + 3) / 4), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_bm_pack<4>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
@@ -683,7 +705,7 @@ int launch_bitmap_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_b
     hipLaunchKernelGGL(k_bmd_plan_local, dim3(chunks), dim3(kPrepChunk), 0, s, a);
     hipLaunchKernelGGL(k_bmd_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
     hipLaunchKernelGGL(k_bmd_blocks<4>, dim3(bm_grid(ctx, a.w.max_blocks)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bmd_final, dim3((nseg + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bmd_final, dim3((nseg + 3) / 4), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 

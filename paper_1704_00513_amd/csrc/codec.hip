@@ -929,12 +929,7 @@ struct UnitRange {
     uint32_t begin, end, step;
 };
 __device__ __forceinline__ UnitRange unit_range(uint32_t units, uint32_t waves, uint32_t w, bool strided) {
-    // workgroup b runs on XCD b mod 8: the workgroups are numbered XCD by
-    // XCD, so that neighbouring units (which share lines at their ends) go to
-    // waves behind one L2
-    const uint32_t G = gridDim.x, b = blockIdx.x, x = b & 7u, q = G >> 3, r = G & 7u;
-    const uint32_t vb = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
-    const uint64_t W = (uint64_t)vb * waves + w, NW = (uint64_t)G * waves;
+    const uint64_t W = (uint64_t)blockIdx.x * waves + w, NW = (uint64_t)gridDim.x * waves;
     UnitRange ur;
     if (strided) {
         ur.begin = (uint32_t)W;
@@ -2373,27 +2368,28 @@ __device__ __forceinline__ void dec_raw(const uint32_t *src, uint32_t n, uint32_
 // unit's blocks in order.  STAGE: a unit is half a group (up to 8 blocks)
 // whose payload words (at most 1024, since every block holds at most 128)
 // are first staged in LDS with every load in flight at once.  Otherwise a
-// unit is a whole group: sixteen full blocks whose payload fits the LDS
-// window are decoded in one go (dec_full_unit), any other group half by half
-// (the same for a full half; else block by block, the next block's words in
-// flight while the current one decodes).  Whole groups read and check each
-// directory entry once.
-template <int WAVES, bool STAGE>
+// unit is a whole group (GROUP, chosen by the launcher when every wave gets
+// many) or half of one: sixteen full blocks whose payload fits the LDS
+// window are decoded in one go (dec_full_unit), any other group half by
+// half; a full half that fits goes to dec_full_unit, any other block by
+// block, the next block's words in flight while the current one decodes.
+// Whole groups read and check each directory entry once.
+template <int WAVES, bool STAGE, bool GROUP>
 __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
     constexpr uint32_t kWin = kHalf * kBlock;
     constexpr uint32_t kPerLane = kWin / 64;
-    constexpr uint32_t kUnitsPerTile = STAGE ? 2 : 1;
     __shared__ uint32_t s_win[WAVES][kWin + 4];
     __shared__ uint32_t s_val[WAVES][192];  // 128 IDs, 64 spare slots
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t units = kUnitsPerTile * readfirst(a.tile_base[a.nseg]);
+    const uint32_t tiles = readfirst(a.tile_base[a.nseg]);
+    constexpr bool by_group = GROUP && !STAGE;
     uint32_t *win = s_win[w];
     uint32_t *val = s_val[w];
-    UnitRange ur = unit_range(units, WAVES, w, a.strided);
+    UnitRange ur = unit_range(by_group ? tiles : 2 * tiles, WAVES, w, a.strided);
     SegCursor c;
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
-        const uint32_t t = STAGE ? u >> 1 : u;
-        const uint32_t h0 = STAGE ? (u & 1) : 0u, h1 = STAGE ? h0 + 1 : 2u;  // the halves to decode
+        const uint32_t t = by_group ? u : u >> 1;
+        const uint32_t h0 = by_group ? 0u : (u & 1), h1 = by_group ? 2u : h0 + 1;  // the halves to decode
         if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
             c.n = readfirst(a.seg_n[c.r]);
             c.form = readfirst(a.seg_form[c.r]);
@@ -2464,7 +2460,7 @@ __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
         }
         const uint32_t *pay = seg + metaw;
         uint32_t full_nb = 0;  // a whole group decoded in one go
-        if constexpr (!STAGE) {
+        if constexpr (by_group) {
             const uint64_t og = oo + (uint64_t)k0 * kBlock;
             if ((gblk == kGroup) & ((uint64_t)(k0 + kGroup) * kBlock <= n) & (og + kGroup * kBlock <= a.out_cap) &
                 (A > 0) & (A + 3 <= kWin)) {
@@ -2937,20 +2933,26 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     a.err = ctx->err;
     a.strided = (ctx->tune.dec_mode >> 1) & 1u;
     const uint64_t mt = plan_max_tiles(max_ids, nseg);
-    // decode units: whole groups in the default variant, halves in the others
-    const uint64_t units = (ctx->tune.dec_mode & 5u) == 1u ? mt : 2 * mt;
+    const uint64_t units = 2 * mt;  // at most (half groups)
     const uint32_t per_cu = ctx->tune.dec_wg_per_cu;
     const int slot = timed ? timing_begin(ctx, BFSC_OP_DECODE, s) : -1;
 #define BFSC_DEC_LAUNCH(K, W)                                                                \
     hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \
                        dim3(W * 64), 0, s, a)
-#define BFSC_DEC_CASE(W)                                                                   \
-    if (ctx->tune.dec_mode & 4u)                                                           \
-        BFSC_DEC_LAUNCH((k_decode_r<W>), W);                                               \
-    else if (ctx->tune.dec_mode & 1u)                                                      \
-        BFSC_DEC_LAUNCH((k_decode_u<W, false>), W);                                        \
-    else                                                                                   \
-        BFSC_DEC_LAUNCH((k_decode_u<W, true>), W);
+    // whole groups per unit when the batch can give every wave at least
+    // eight of them (as the pack passes do with tiles), else half groups
+#define BFSC_DEC_CASE(W)                                                                            \
+    if (ctx->tune.dec_mode & 4u) {                                                                  \
+        BFSC_DEC_LAUNCH((k_decode_r<W>), W);                                                        \
+    } else if (ctx->tune.dec_mode & 1u) {                                                           \
+        const uint32_t g = resident_grid(ctx, (const void *)k_decode_u<W, false, true>, W * 64, per_cu, units); \
+        if (max_ids / (kBlock * kGroup) >= 8ull * g * W)                                            \
+            hipLaunchKernelGGL((k_decode_u<W, false, true>), dim3(g), dim3(W * 64), 0, s, a);       \
+        else                                                                                        \
+            BFSC_DEC_LAUNCH((k_decode_u<W, false, false>), W);                                      \
+    } else {                                                                                        \
+        BFSC_DEC_LAUNCH((k_decode_u<W, true, false>), W);                                           \
+    }
     switch (ctx->tune.dec_waves) {
         case 1: BFSC_DEC_CASE(1) break;
         case 2: BFSC_DEC_CASE(2) break;
