@@ -184,6 +184,17 @@ __device__ __forceinline__ BmChoice bm_choose(uint32_t wa, uint32_t wb, uint32_t
 
 // ------------------------------------------------------------------ encode plan
 
+// The encode plan's totals at index nseg (blocks, non-empty segments); more
+// blocks than max_words allows: no block runs.
+__device__ __forceinline__ void bm_plan_end(const BmArgs &a, uint32_t tb, uint32_t te) {
+    const bool over = tb > a.w.max_blocks;
+    if (over) raise_err(a.err, kErrInval);
+    a.w.blk_base[a.nseg] = over ? 0u : tb;
+    a.w.ne_base[a.nseg] = te;
+}
+
+// Pass 1, one workgroup per chunk of segments; a batch of one chunk is then
+// complete (its pass 2 is not launched).
 __global__ __launch_bounds__(1024) void k_bm_plan_local(BmArgs a) {
     __shared__ uint32_t s_tmp[17];
     const uint32_t tid = threadIdx.x, c = blockIdx.x, r = c * kPrepChunk + tid;
@@ -204,6 +215,7 @@ __global__ __launch_bounds__(1024) void k_bm_plan_local(BmArgs a) {
         a.w.ne_base[r] = xe;
     }
     if (tid == 0) *(uint2 *)(a.w.carry + 4 * c) = make_uint2(tb, te);
+    if (gridDim.x == 1 && tid == 0) bm_plan_end(a, tb, te);
 }
 
 __global__ __launch_bounds__(1024) void k_bm_plan_fix(BmArgs a) {
@@ -231,12 +243,7 @@ __global__ __launch_bounds__(1024) void k_bm_plan_fix(BmArgs a) {
     }
     if (c + 1 == gridDim.x && tid == 0) {
         const uint2 own = *(const uint2 *)(a.w.carry + 4 * c);
-        const uint32_t tb = pb + own.x;
-        // more blocks than max_words allows: no block runs
-        const bool over = tb > a.w.max_blocks;
-        if (over) raise_err(a.err, kErrInval);
-        a.w.blk_base[a.nseg] = over ? 0u : tb;
-        a.w.ne_base[a.nseg] = pe + own.y;
+        bm_plan_end(a, pb + own.x, pe + own.y);
     }
 }
 
@@ -427,6 +434,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_bm_pack(BmArgs a) {
 
 // ------------------------------------------------------------------ decode
 
+// The decode plan's totals at index nseg (blocks, output words) and their
+// checks.
+__device__ __forceinline__ void bmd_plan_end(const BmArgs &a, uint32_t tb, uint64_t co) {
+    const bool over = tb > a.w.max_blocks;
+    if (over) raise_err(a.err, kErrCorrupt);
+    a.w.blk_base[a.nseg] = over ? 0u : tb;
+    a.w.out_off[a.nseg] = co;
+    if (co > a.out_cap) raise_err(a.err, kErrCapacity);
+}
+
 // Plan pass 1 over the headers: form (empty, or compressed when the header
 // checks), words and blocks per segment, their scans inside the chunk.
 __global__ __launch_bounds__(1024) void k_bmd_plan_local(BmArgs a) {
@@ -486,6 +503,7 @@ __global__ __launch_bounds__(1024) void k_bmd_plan_local(BmArgs a) {
         a.w.carry[4 * c] = tb;
         a.w.carry[4 * c + 1] = (uint32_t)s_c;
         a.w.carry[4 * c + 2] = (uint32_t)(s_c >> 32);
+        if (gridDim.x == 1) bmd_plan_end(a, tb, s_c);  // one chunk: complete, no pass 2
     }
 }
 
@@ -518,13 +536,8 @@ __global__ __launch_bounds__(1024) void k_bmd_plan_fix(BmArgs a) {
         a.w.out_off[r] += pn;
     }
     if (c + 1 == gridDim.x && tid == 0) {
-        const uint64_t co = pn + ((uint64_t)a.w.carry[4 * c + 1] | (uint64_t)a.w.carry[4 * c + 2] << 32);
-        const uint32_t tb = pb + a.w.carry[4 * c];
-        const bool over = tb > a.w.max_blocks;
-        if (over) raise_err(a.err, kErrCorrupt);
-        a.w.blk_base[a.nseg] = over ? 0u : tb;
-        a.w.out_off[a.nseg] = co;
-        if (co > a.out_cap) raise_err(a.err, kErrCapacity);
+        const uint64_t own = (uint64_t)a.w.carry[4 * c + 1] | (uint64_t)a.w.carry[4 * c + 2] << 32;
+        bmd_plan_end(a, pb + a.w.carry[4 * c], pn + own);
     }
 }
 
@@ -677,7 +690,7 @@ int launch_bitmap_encode(bfsc_ctx *ctx, const uint32_t *bits, const uint64_t *se
     bm_ws_layout(ws, max_words, nseg, &a.w);
     const uint32_t chunks = prep_chunks(nseg);
     hipLaunchKernelGGL(k_bm_plan_local, dim3(chunks), dim3(kPrepChunk), 0, s, a);
-    hipLaunchKernelGGL(k_bm_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
+    if (chunks > 1) hipLaunchKernelGGL(k_bm_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
     const uint32_t grid = bm_grid(ctx, a.w.max_blocks);
     hipLaunchKernelGGL(k_bm_size<4>, dim3(grid), dim3(256), 0, s, a);
     const uint32_t sc = (uint32_t)((a.w.max_blocks + 1ull + kBmScan - 1) / kBmScan);
@@ -703,7 +716,7 @@ int launch_bitmap_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_b
     a.w.out_off = out_off;
     const uint32_t chunks = prep_chunks(nseg);
     hipLaunchKernelGGL(k_bmd_plan_local, dim3(chunks), dim3(kPrepChunk), 0, s, a);
-    hipLaunchKernelGGL(k_bmd_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
+    if (chunks > 1) hipLaunchKernelGGL(k_bmd_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
     hipLaunchKernelGGL(k_bmd_blocks<4>, dim3(bm_grid(ctx, a.w.max_blocks)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_bmd_final, dim3((nseg + 3) / 4), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;

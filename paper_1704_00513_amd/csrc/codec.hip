@@ -36,6 +36,24 @@ struct PlanArgs {
 // group table and the payloads).  Pass 1, one workgroup per kPrepChunk
 // segments: the counts, their exclusive scans inside the chunk, and the
 // chunk's totals.
+// The batch totals at index nseg (blocks, groups, fixed words, tiles) from
+// the totals cb, cg, cf, ct of all chunks.  Inconsistent offsets (totals
+// beyond what max_ids allows) disable the batch: no tile runs, so nothing is
+// indexed past the workspace.
+__device__ __forceinline__ void plan_end(const PlanArgs &a, uint32_t cb, uint32_t cg, uint32_t ct, uint32_t cf) {
+    const uint64_t max_blocks = (a.max_ids + kBlock - 1) / kBlock + a.nseg;
+    const bool over = ct > a.p.max_tiles || cb > max_blocks;
+    if (over) raise_err(a.err, kErrInval);
+    a.p.blk_base[a.nseg] = cb;
+    a.p.grp_base[a.nseg] = cg;
+    a.p.fix_base[a.nseg] = cf;
+    a.p.tile_base[a.nseg] = over ? 0u : ct;
+    a.p.counter[0] = 0;
+}
+
+// Pass 1, one workgroup per chunk of kPrepChunk segments: the chunk-local
+// exclusive scans and the chunk's totals.  A batch of one chunk is then
+// complete (its pass 2 is not launched).
 __global__ __launch_bounds__(1024) void k_plan_local(PlanArgs a) {
     const uint32_t tid = threadIdx.x, c = blockIdx.x;
     __shared__ uint32_t s_tmp[17];
@@ -68,6 +86,7 @@ __global__ __launch_bounds__(1024) void k_plan_local(PlanArgs a) {
         a.p.fix_base[r] = xf;
     }
     if (tid == 0) *(uint4 *)(a.p.chunk_sums + 4 * c) = make_uint4(tb, tg, tt, tf);
+    if (gridDim.x == 1 && tid == 0) plan_end(a, tb, tg, tt, tf);
 }
 
 // Sum over workgroup threads of four values (up to 1024 threads).
@@ -108,17 +127,7 @@ __global__ __launch_bounds__(1024) void k_plan_fix(PlanArgs a) {
     }
     if (c + 1 == gridDim.x && tid == 0) {
         const uint4 own = cs[c];
-        const uint32_t cb = pre.x + own.x, cg = pre.y + own.y, ct = pre.z + own.z, cf = pre.w + own.w;
-        // inconsistent offsets (totals beyond what max_ids allows) disable
-        // the batch: no tile runs, so nothing is indexed past the workspace
-        const uint64_t max_blocks = (a.max_ids + kBlock - 1) / kBlock + a.nseg;
-        const bool over = ct > a.p.max_tiles || cb > max_blocks;
-        if (over) raise_err(a.err, kErrInval);
-        a.p.blk_base[a.nseg] = cb;
-        a.p.grp_base[a.nseg] = cg;
-        a.p.fix_base[a.nseg] = cf;
-        a.p.tile_base[a.nseg] = over ? 0u : ct;
-        a.p.counter[0] = 0;
+        plan_end(a, pre.x + own.x, pre.y + own.y, pre.z + own.z, pre.w + own.w);
     }
 }
 
@@ -1650,6 +1659,13 @@ struct DecPlanArgs {
 // chunk, and the chunk's totals.  A segment of L bytes is empty if L = 0;
 // raw if L < 16 or its words 1 and 2 increase (IDs strictly increase);
 // compressed if they decrease (header n, hi, lo, magic with hi > lo).
+// The batch totals at index nseg (tiles, output IDs) and the capacity check.
+__device__ __forceinline__ void dec_plan_end(const DecPlanArgs &a, uint32_t tiles, uint64_t ids) {
+    a.tile_base[a.nseg] = tiles;
+    a.out_off[a.nseg] = ids;
+    if (ids > a.out_cap) raise_err(a.err, kErrCapacity);
+}
+
 __global__ __launch_bounds__(1024) void k_dec_local(DecPlanArgs a) {
     __shared__ uint32_t s_tmp[17];
     __shared__ unsigned long long s_w[16];
@@ -1716,6 +1732,7 @@ __global__ __launch_bounds__(1024) void k_dec_local(DecPlanArgs a) {
     if (tid == 0) {
         a.chunk_t[c] = tt;
         a.chunk_n[c] = s_c;
+        if (gridDim.x == 1) dec_plan_end(a, tt, s_c);  // one chunk: complete, no pass 2
     }
 }
 
@@ -1749,12 +1766,7 @@ __global__ __launch_bounds__(1024) void k_dec_fix(DecPlanArgs a) {
         a.tile_base[r] += pt;
         a.out_off[r] += pn;
     }
-    if (c + 1 == gridDim.x && tid == 0) {
-        const uint64_t co = pn + a.chunk_n[c];
-        a.tile_base[a.nseg] = pt + a.chunk_t[c];
-        a.out_off[a.nseg] = co;
-        if (co > a.out_cap) raise_err(a.err, kErrCapacity);
-    }
+    if (c + 1 == gridDim.x && tid == 0) dec_plan_end(a, pt + a.chunk_t[c], pn + a.chunk_n[c]);
 }
 
 struct DecArgs {
@@ -2795,7 +2807,7 @@ int launch_plan_prep(const bfsc_batch *b, const Plan &p, uint32_t *err, bool zer
     a.err = err;
     const uint32_t chunks = prep_chunks(b->nseg);
     hipLaunchKernelGGL(k_plan_local, dim3(chunks), dim3(kPrepChunk), 0, s, a);
-    hipLaunchKernelGGL(k_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
+    if (chunks > 1) hipLaunchKernelGGL(k_plan_fix, dim3(chunks), dim3(kPrepChunk), 0, s, a);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
@@ -2919,7 +2931,7 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     pa.chunk_t = chunk_t;
     pa.err = ctx->err;
     hipLaunchKernelGGL(k_dec_local, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
-    hipLaunchKernelGGL(k_dec_fix, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
+    if (chunks > 1) hipLaunchKernelGGL(k_dec_fix, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
     DecArgs a;
     a.in = in;
     a.seg_byte_off = seg_byte_off;

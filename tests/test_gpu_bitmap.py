@@ -90,6 +90,11 @@ def synthetic_cases():
     sizes = np.arange(41)
     seg_w = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
     out.append(("small", random_bitmap(int(seg_w[-1]), 0.05, 4, runs=True), seg_w))
+    # more segments than one plan workgroup takes (1,024), empty ones among them
+    sizes = np.random.default_rng(21).integers(0, 300, 2500)
+    sizes[::7] = 0
+    seg_w = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    out.append(("many", random_bitmap(int(seg_w[-1]), 0.1, 21, runs=True), seg_w))
     return out
 
 
