@@ -1364,10 +1364,10 @@ __global__ __launch_bounds__(1024) void k_enc_scan(EncArgs a) {
     if (threadIdx.x == 0) a.p.chunk_words[blockIdx.x] = total;
 }
 
-// Payload words before the first `chunks` chunks (the whole wave).
-__device__ __forceinline__ uint64_t chunk_prefix(const uint32_t *chunk_words, uint32_t chunks, uint32_t lane) {
+// Payload words of chunks k0 .. k1-1 (the whole wave).
+__device__ __forceinline__ uint64_t chunk_prefix(const uint32_t *chunk_words, uint32_t k0, uint32_t k1, uint32_t lane) {
     uint64_t s = 0;
-    for (uint32_t k = lane; k < chunks; k += 64) s += chunk_words[k];
+    for (uint32_t k = k0 + lane; k < k1; k += 64) s += chunk_words[k];
     return wave_sum64(s);
 }
 
@@ -1376,21 +1376,40 @@ __device__ __forceinline__ uint64_t chunk_prefix(const uint32_t *chunk_words, ui
 // start offset (written by its first tile), then for a compressed segment
 // its header (first tile), the tile's directory entries, group-table entry
 // and payload words, copied from the two halves of its slot to their final
-// position; for a raw segment its IDs, copied from the input.
+// position; for a raw segment its IDs, copied from the input.  A wave waits
+// on memory twice before its stores: for everything that depends on the
+// tile index alone (the tile count, the tile's segment record, unit sizes
+// and offset, and the payload totals of the chunks of units before it, four
+// per lane), then for the segment's fields, the offset of its first unit,
+// the directory and the payload words.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
-    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t total = readfirst(a.p.tile_base[a.nseg]);
+    constexpr uint32_t kCw = 4;  // chunk totals held per lane
+    const uint32_t lane = threadIdx.x & 63, w = readfirst(threadIdx.x >> 6);
     const uint32_t t = blockIdx.x * WAVES + w;
+    if (t >= a.p.max_tiles) return;
+    // first round: reads inside the plan's arrays for any t < max_tiles
+    // (a tile past the batch's count reads stale words and drops them)
+    const uint32_t total = a.p.tile_base[a.nseg];
+    const uint2 ts = a.p.tile_seg[t];
+    const uint32_t A0 = a.p.unit_words[2 * t], A1 = a.p.unit_words[2 * t + 1];
+    const uint32_t ot = a.p.unit_off[2 * t];
+    const uint32_t ct = 2 * t / kScanChunk;
+    uint32_t cw[kCw];
+#pragma unroll
+    for (uint32_t i = 0; i < kCw; ++i) {
+        const uint32_t k = lane + 64 * i;
+        cw[i] = k < ct ? a.p.chunk_words[k] : 0u;
+    }
+    // every first-round value is needed here, so all of its loads are in
+    // flight together before the one wait
+    asm volatile("" ::"s"(total), "s"(ts.x), "s"(ts.y), "s"(A0), "s"(A1), "s"(ot), "v"(cw[0]), "v"(cw[1]),
+                 "v"(cw[2]), "v"(cw[3]));
     if (t >= total) return;
     const uint64_t capw = a.out_cap >> 2;
-    // segment and its first tile as recorded by the pack pass (no search)
-    const uint2 ts = a.p.tile_seg[t];
-    // what depends on t alone is loaded first, so that the slot's words are
-    // in flight while the offsets are worked out.  Up to 512 payload words
-    // and the directory words are held in registers; every index stays
-    // inside the tile's slot whatever the unit sizes read
-    const uint32_t A0 = readfirst(a.p.unit_words[2 * t]), A1 = readfirst(a.p.unit_words[2 * t + 1]);
+    // second round: up to 512 payload words held in registers (every index
+    // stays inside the tile's slot whatever the unit sizes read), the
+    // directory words and the segment's fields
     const uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
     constexpr uint32_t kC = 8;
     const uint32_t nw = A0 + A1;
@@ -1404,25 +1423,39 @@ __global__ __launch_bounds__(WAVES * 64) void k_enc_place(EncArgs a) {
         x[i] = q < nw ? slot[src(q)] : 0u;
     }
     const uint32_t dirw = lane < kSlotDirWords ? slot[lane] : 0u;
-    const uint32_t r = readfirst(ts.x);
-    const uint32_t t_first = readfirst(ts.y);
-    const uint32_t n = readfirst(a.p.seg_n[r]);
-    const uint32_t bb = readfirst(a.p.blk_base[r]);
-    const uint32_t nb = readfirst(a.p.blk_base[r + 1]) - bb;
-    const uint32_t gb = readfirst(a.p.grp_base[r]);
-    const uint32_t ng = readfirst(a.p.grp_base[r + 1]) - gb;
-    const uint32_t fb = readfirst(a.p.fix_base[r]);
-    // payload words before the segment and before the tile (unit 2t)
-    const uint32_t cf = 2 * t_first / kScanChunk, ct = 2 * t / kScanChunk;
-    const uint64_t Pf = chunk_prefix(a.p.chunk_words, cf, lane);
-    const uint64_t P = Pf + readfirst(a.p.unit_off[2 * t_first]);
-    const uint64_t Pt = (ct == cf ? Pf : chunk_prefix(a.p.chunk_words, ct, lane)) + readfirst(a.p.unit_off[2 * t]);
+    const uint32_t r = ts.x;
+    const uint32_t t_first = ts.y;
+    const uint32_t n = a.p.seg_n[r];
+    const uint32_t bb = a.p.blk_base[r];
+    const uint32_t nb = a.p.blk_base[r + 1] - bb;
+    const uint32_t gb = a.p.grp_base[r];
+    const uint32_t ng = a.p.grp_base[r + 1] - gb;
+    const uint32_t fb = a.p.fix_base[r];
+    const uint32_t of = a.p.unit_off[2 * t_first];
+    asm volatile("" ::"v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(x[6]), "v"(x[7]),
+                 "v"(dirw));
+    // payload words before the segment (chunks before cf, then units of
+    // chunk cf before its first) and before the tile (chunks before ct)
+    const uint32_t cf = 2 * t_first / kScanChunk;
+    uint32_t sf = 0, st = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kCw; ++i) {
+        st += cw[i];
+        sf += lane + 64 * i < cf ? cw[i] : 0u;
+    }
+    uint64_t Pf = wave_sum(sf), Pc = wave_sum(st);  // 256 chunks of at most 2^22 words
+    if (ct > 64 * kCw) {
+        Pf += chunk_prefix(a.p.chunk_words, 64 * kCw, cf, lane);
+        Pc += chunk_prefix(a.p.chunk_words, 64 * kCw, ct, lane);
+    }
+    const uint64_t P = Pf + of;
+    const uint64_t Pt = Pc + ot;
     const uint64_t sw = (uint64_t)fb + gb + P;
     const uint32_t g = t - t_first;
     if (t == 0) {
         // the batch end, from the totals of all chunks
         const uint32_t units = 2 * total;
-        const uint64_t words = chunk_prefix(a.p.chunk_words, (units + kScanChunk - 1) / kScanChunk, lane);
+        const uint64_t words = chunk_prefix(a.p.chunk_words, 0, (units + kScanChunk - 1) / kScanChunk, lane);
         if (lane == 0) {
             const uint64_t end = 4ull * ((uint64_t)a.p.fix_base[a.nseg] + a.p.grp_base[a.nseg] + words);
             a.seg_byte_off[a.nseg] = end;
