@@ -332,7 +332,10 @@ int bfsc_encode(bfsc_ctx *ctx, const bfsc_batch *b, const uint8_t *classes, int 
  * Writes the IDs back to back into out_ids (capacity out_cap IDs) and
  * out_off u64[nseg+1] (segment r -> out_ids[out_off[r] .. out_off[r+1])).
  * Validates while decoding; a damaged stream latches BFSC_E_CORRUPT and never
- * reads or writes outside the given buffers.  max_ids bounds the total. */
+ * reads or writes outside the given buffers.  max_ids bounds the total: a
+ * stream that holds more IDs than max_ids or out_cap latches
+ * BFSC_E_CAPACITY.  The workspace (bfsc_workspace_size with BFSC_OP_DECODE)
+ * holds the per-segment plan and the segment of every tile. */
 int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                 uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
                 void *ws, void *stream);
@@ -343,7 +346,8 @@ int bfsc_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, 
  * behaviour as bfsc_decode.  The decoder's per-segment plan lives in a
  * fixed array of the library (about 0.8 MB per GPU, held until the process
  * ends), so nseg is limited to BFSC_DECODE_NOALLOC_MAX_SEGS (BFSC_E_INVAL
- * beyond it).  The call allocates nothing and records no timing events.
+ * beyond it); the per-tile map is not kept there, and each tile's segment
+ * is found by search instead.  The call allocates nothing and records no timing events.
  * All calls on one GPU share that array: calls that overlap on one GPU (two
  * streams, or two contexts of the same device) race and must be serialised
  * by the caller. */

@@ -423,13 +423,14 @@ int bfsc_decode_noalloc(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_by
                         void *stream) {
     if (!ctx || !in || !seg_byte_off || !out_ids || !out_off || nseg == 0) return BFSC_E_INVAL;
     if (nseg > BFSC_DECODE_NOALLOC_MAX_SEGS || (uintptr_t)in & 3) return BFSC_E_INVAL;
-    if (decode_ws_bytes(max_ids, nseg) > kNoAllocScratchBytes || !ctx->noalloc_scratch) return BFSC_E_INVAL;
+    if (dec_ws_bytes(nseg) > kNoAllocScratchBytes || !ctx->noalloc_scratch) return BFSC_E_INVAL;
     if (set_device(ctx)) return BFSC_E_HIP;
     // every word of the plan that the decoder reads is written by its first
     // kernel, so the array needs no clearing between calls; no timing events
-    // either (creating one may allocate)
+    // either (creating one may allocate); the array holds the per-segment
+    // plan only, so the decoder finds each tile's segment by search
     return launch_decode(ctx, in, seg_byte_off, nseg, max_ids, out_ids, out_cap, out_off, ctx->noalloc_scratch,
-                         S(stream), false);
+                         S(stream), false, false);
 }
 
 int bfsc_bitmap_encode_bound(uint64_t n_words, uint32_t nseg, size_t *bytes) {

@@ -51,9 +51,38 @@ __device__ __forceinline__ void plan_end(const PlanArgs &a, uint32_t cb, uint32_
     a.p.counter[0] = 0;
 }
 
+// Groups of a segment of n IDs (none for a raw one, n below the threshold
+// T), and its tiles: one per group, or one for a segment without groups.
+__device__ __forceinline__ uint32_t plan_seg_groups(uint32_t n, uint32_t T) {
+    const uint32_t nb = (n >> 7) + ((n & 127u) != 0u);
+    return n < T ? 0u : (nb >> 4) + ((nb & 15u) != 0u);
+}
+__device__ __forceinline__ uint32_t plan_seg_tiles(uint32_t n, uint32_t T) { return max(1u, plan_seg_groups(n, T)); }
+
+// Every tile's segment and that segment's first tile: tile_seg[tb + q] =
+// (r, tb) for q < nt.  A segment of up to 64 tiles is written by its own
+// lane; longer ones by the whole wave, one after another, their tiles
+// across the lanes.  Nothing is written at or past max_tiles (plan_end then
+// refuses the batch).  Only the encoder's plan keeps the map (tile_seg is
+// NULL in the selection pass's).
+__device__ __forceinline__ void plan_tile_map(const PlanArgs &a, uint32_t r, uint32_t tb, uint32_t nt,
+                                              uint32_t lane) {
+    const bool own = nt <= 64u;
+    if (own)
+        for (uint32_t q = 0; q < nt && (uint64_t)tb + q < a.p.max_tiles; ++q) a.p.tile_seg[tb + q] = make_uint2(r, tb);
+    uint64_t m = ballot(!own);
+    while (m) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t rj = readlane(r, j), tj = readlane(tb, j), nj = readlane(nt, j);
+        for (uint32_t q = lane; q < nj && (uint64_t)tj + q < a.p.max_tiles; q += 64)
+            a.p.tile_seg[tj + q] = make_uint2(rj, tj);
+    }
+}
+
 // Pass 1, one workgroup per chunk of kPrepChunk segments: the chunk-local
 // exclusive scans and the chunk's totals.  A batch of one chunk is then
-// complete (its pass 2 is not launched).
+// complete (its pass 2 is not launched) and the pass writes the tile map.
 __global__ __launch_bounds__(1024) void k_plan_local(PlanArgs a) {
     const uint32_t tid = threadIdx.x, c = blockIdx.x;
     __shared__ uint32_t s_tmp[17];
@@ -68,9 +97,9 @@ __global__ __launch_bounds__(1024) void k_plan_local(PlanArgs a) {
         if (bad) raise_err(a.err, kErrInval);
         a.p.seg_n[r] = n;
         const bool raw = n < T;  // (an empty segment too: no groups)
-        nb = cdiv32(n, kBlock);
-        ng = raw ? 0u : cdiv32(nb, kGroup);
-        nt = ng ? ng : 1u;
+        nb = (n >> 7) + ((n & 127u) != 0u);
+        ng = plan_seg_groups(n, T);
+        nt = plan_seg_tiles(n, T);
         nf = raw ? n : 4u + 2u * nb;
         if (n == 0) nf = 0;
     }
@@ -87,6 +116,7 @@ __global__ __launch_bounds__(1024) void k_plan_local(PlanArgs a) {
     }
     if (tid == 0) *(uint4 *)(a.p.chunk_sums + 4 * c) = make_uint4(tb, tg, tt, tf);
     if (gridDim.x == 1 && tid == 0) plan_end(a, tb, tg, tt, tf);
+    if (gridDim.x == 1 && a.p.tile_seg) plan_tile_map(a, r, xt, nt, tid & 63);
 }
 
 // Sum over workgroup threads of four values (up to 1024 threads).
@@ -106,8 +136,9 @@ __device__ __forceinline__ uint4 wg_sum4(uint4 v, uint4 *s_red /*[16]*/) {
     return t;
 }
 
-// Pass 2, one workgroup per chunk: adds the totals of the chunks before it;
-// the last workgroup writes the batch totals at index nseg.
+// Pass 2, one workgroup per chunk: adds the totals of the chunks before it
+// and writes the tile map; the last workgroup writes the batch totals at
+// index nseg.
 __global__ __launch_bounds__(1024) void k_plan_fix(PlanArgs a) {
     const uint32_t tid = threadIdx.x, c = blockIdx.x;
     __shared__ uint4 s_red[16];
@@ -119,16 +150,20 @@ __global__ __launch_bounds__(1024) void k_plan_fix(PlanArgs a) {
     }
     const uint4 pre = wg_sum4(q, s_red);
     const uint32_t r = c * kPrepChunk + tid;
+    uint32_t tb = 0, nt = 0;
     if (r < a.nseg) {
         a.p.blk_base[r] += pre.x;
         a.p.grp_base[r] += pre.y;
-        a.p.tile_base[r] += pre.z;
+        tb = a.p.tile_base[r] + pre.z;
+        a.p.tile_base[r] = tb;
         a.p.fix_base[r] += pre.w;
+        nt = plan_seg_tiles(a.p.seg_n[r], a.p.raw_below);
     }
     if (c + 1 == gridDim.x && tid == 0) {
         const uint4 own = cs[c];
         plan_end(a, pre.x + own.x, pre.y + own.y, pre.z + own.z, pre.w + own.w);
     }
+    if (a.p.tile_seg) plan_tile_map(a, r, tb, nt, tid & 63);
 }
 
 // ------------------------------------------------------------------ block analysis
@@ -1007,32 +1042,31 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
     const bool by_tile = (uint64_t)tiles >= 8ull * gridDim.x * WAVES;
     uint32_t *sid = s_ids[STAGE || kGrp ? w : 0];
     UnitRange ur = unit_range(by_tile ? tiles : 2 * tiles, WAVES, w, a.strided);
-    SegCursor c;
+    // the tile's segment from the plan's tile map, loaded one unit ahead;
+    // the segment's fields are loaded again for every unit (from the cache),
+    // so that nothing is carried from unit to unit and they all stay scalar
+    uint2 tsn = make_uint2(0u, 0u);
+    if (ur.begin < ur.end) tsn = a.p.tile_seg[by_tile ? ur.begin : ur.begin >> 1];
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
         const uint32_t t = by_tile ? u : u >> 1;
         const uint32_t h0 = by_tile ? 0u : (u & 1), h1 = by_tile ? 2u : h0 + 1;  // the halves to pack
-        if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
-            c.bb = readfirst(a.p.blk_base[c.r]);
-            c.n = readfirst(a.p.seg_n[c.r]);
-            // a raw segment's IDs are copied by the place pass: no blocks
-            c.nb = c.n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[c.r + 1]) - c.bb;
-            c.lo = readfirst(a.seg_lo[c.r]);
-            c.hi = readfirst(a.seg_hi[c.r]);
-            c.base = readfirst64(a.seg_off[c.r]);
-        }
-        // the tile's segment, for the place pass
-        if (h0 == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
-        const uint32_t g = t - c.t_first;
-        const uint32_t bb = c.bb, nb = c.nb;
+        const uint32_t r = readfirst(tsn.x), t_first = readfirst(tsn.y);
+        const uint64_t un = (uint64_t)u + ur.step;
+        if (un < ur.end) tsn = a.p.tile_seg[by_tile ? (uint32_t)un : (uint32_t)(un >> 1)];
+        const uint32_t bb = readfirst(a.p.blk_base[r]);
+        const uint32_t n = readfirst(a.p.seg_n[r]);
+        // a raw segment's IDs are copied by the place pass: no blocks
+        const uint32_t nb = n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[r + 1]) - bb;
+        const uint32_t lo = readfirst(a.seg_lo[r]), hi = readfirst(a.seg_hi[r]);
+        const uint64_t base = readfirst64(a.seg_off[r]);
+        const uint32_t g = t - t_first;
         for (uint32_t h = h0; h < h1; ++h) {
             const uint32_t k0 = g * kGroup + h * kHalf;
             const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
             uint32_t run = 0;  // payload words of the unit so far
             if (nblk) {
-                const uint32_t n = c.n;
-                const uint32_t lo = c.lo, hi = c.hi;
                 const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
-                const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+                const uint32_t *src = a.ids + base + (uint64_t)k0 * kBlock;
                 uint32_t *slot = a.p.slots + (uint64_t)t * kSlotWords;
                 if (kGrp && !a.classes && cnt == kIds) {
                     run = enc_unit_r(src, ((uintptr_t)src & 15) == 0, lo, hi,
@@ -1191,30 +1225,29 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
     const bool by_tile = (uint64_t)tiles >= 8ull * gridDim.x * WAVES;
     uint32_t *sid = s_ids[w];
     UnitRange ur = unit_range(by_tile ? tiles : 2 * tiles, WAVES, w, a.strided);
-    SegCursor c;
-    int32_t level = 0;
+    // the tile's segment from the plan's tile map, loaded one unit ahead;
+    // the segment's fields are loaded again for every unit (from the cache),
+    // so that nothing is carried from unit to unit and they all stay scalar
+    uint2 tsn = make_uint2(0u, 0u);
+    if (ur.begin < ur.end) tsn = a.p.tile_seg[by_tile ? ur.begin : ur.begin >> 1];
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
         const uint32_t t = by_tile ? u : u >> 1;
         const uint32_t h0 = by_tile ? 0u : (u & 1), h1 = by_tile ? 2u : h0 + 1;  // the halves to pack
-        if (c.seek(a.p.tile_base, a.nseg, t, lane, a.strided)) {
-            c.bb = readfirst(a.p.blk_base[c.r]);
-            c.n = readfirst(a.p.seg_n[c.r]);
-            // a raw segment's IDs are copied by the place pass: no blocks
-            c.nb = c.n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[c.r + 1]) - c.bb;
-            c.lo = readfirst(a.seg_lo[c.r]);
-            c.hi = readfirst(a.seg_hi[c.r]);
-            c.base = readfirst64(a.seg_off[c.r]);
-            level = a.seg_level ? (int32_t)readfirst((uint32_t)a.seg_level[c.r]) : 0;
-        }
-        // the tile's segment, for the place pass
-        if (h0 == 0 && lane == 0) a.p.tile_seg[t] = make_uint2(c.r, c.t_first);
-        const uint32_t g = t - c.t_first;
-        const uint32_t nb = c.nb;
-        if (by_tile && nb >= (g + 1) * kGroup && (uint64_t)(g + 1) * kGroup * kBlock <= c.n) {
+        const uint32_t r = readfirst(tsn.x), t_first = readfirst(tsn.y);
+        const uint64_t un = (uint64_t)u + ur.step;
+        if (un < ur.end) tsn = a.p.tile_seg[by_tile ? (uint32_t)un : (uint32_t)(un >> 1)];
+        const uint32_t bb = readfirst(a.p.blk_base[r]);
+        const uint32_t n = readfirst(a.p.seg_n[r]);
+        // a raw segment's IDs are copied by the place pass: no blocks
+        const uint32_t nb = n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[r + 1]) - bb;
+        const uint32_t lo = readfirst(a.seg_lo[r]), hi = readfirst(a.seg_hi[r]);
+        const uint64_t base = readfirst64(a.seg_off[r]);
+        const int32_t level = a.seg_level ? (int32_t)readfirst((uint32_t)a.seg_level[r]) : 0;
+        const uint32_t g = t - t_first;
+        if (by_tile && nb >= (g + 1) * kGroup && (uint64_t)(g + 1) * kGroup * kBlock <= n) {
             // sixteen full blocks: features of both halves, one evaluation of
             // the network, then the row packer on each half
-            const uint32_t n = c.n, lo = c.lo, hi = c.hi;
-            const uint32_t *src = a.ids + c.base + (uint64_t)g * kGroup * kBlock;
+            const uint32_t *src = a.ids + base + (uint64_t)g * kGroup * kBlock;
             const bool al16 = ((uintptr_t)src & 15) == 0;
             unit_features_r<4>(src, al16, n, level, s_x[w], s_span[w], lane);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1243,9 +1276,8 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
             const uint32_t nblk = nb > k0 ? min(kHalf, nb - k0) : 0u;
             uint32_t run = 0;
             if (nblk) {
-                const uint32_t n = c.n, lo = c.lo, hi = c.hi;
                 const uint32_t cnt = min(n - k0 * kBlock, nblk * kBlock);
-                const uint32_t *src = a.ids + c.base + (uint64_t)k0 * kBlock;
+                const uint32_t *src = a.ids + base + (uint64_t)k0 * kBlock;
                 if (cnt == kIds) {
                     // full unit: features and packing one block per 16-lane row
                     const bool al16 = ((uintptr_t)src & 15) == 0;
@@ -1683,8 +1715,35 @@ struct DecPlanArgs {
     uint32_t *tile_base;  // [nseg+1]
     uint64_t *chunk_n;    // [prep chunks] IDs of every kPrepChunk segments
     uint32_t *chunk_t;    // [prep chunks] tiles of every kPrepChunk segments
+    uint32_t *tile_seg;   // [map_cap] segment of every tile (NULL: not kept)
+    uint64_t map_cap;
+    uint64_t max_ids;
     uint32_t *err;
 };
+
+// Tiles of a compressed segment of n IDs: groups of 16 blocks of 128.
+__device__ __forceinline__ uint32_t dec_seg_tiles(uint32_t n) {
+    const uint32_t nb = (n >> 7) + ((n & 127u) != 0u);
+    return (nb >> 4) + ((nb & 15u) != 0u);
+}
+
+// The segment of every tile: tile_seg[tb + q] = r for q < ng.  A segment of
+// up to 64 tiles is written by its own lane; longer ones by the whole wave,
+// one after another, their tiles across the lanes.  Tiles at or past
+// map_cap are not written (the decoder then searches instead).
+__device__ __forceinline__ void dec_tile_map(const DecPlanArgs &a, uint32_t r, uint32_t tb, uint32_t ng,
+                                             uint32_t lane) {
+    const bool own = ng <= 64u;
+    if (own)
+        for (uint32_t q = 0; q < ng && (uint64_t)tb + q < a.map_cap; ++q) a.tile_seg[tb + q] = r;
+    uint64_t m = ballot(!own);
+    while (m) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t rj = readlane(r, j), tj = readlane(tb, j), nj = readlane(ng, j);
+        for (uint32_t q = lane; q < nj && (uint64_t)tj + q < a.map_cap; q += 64) a.tile_seg[tj + q] = rj;
+    }
+}
 
 // Pass 1 of the decoder's plan, one workgroup per kPrepChunk segments: each
 // segment's form, ID count and tiles (a group of 16 blocks of a compressed
@@ -1692,11 +1751,13 @@ struct DecPlanArgs {
 // chunk, and the chunk's totals.  A segment of L bytes is empty if L = 0;
 // raw if L < 16 or its words 1 and 2 increase (IDs strictly increase);
 // compressed if they decrease (header n, hi, lo, magic with hi > lo).
-// The batch totals at index nseg (tiles, output IDs) and the capacity check.
+// The batch totals at index nseg (tiles, output IDs) and the capacity check
+// (against the output's capacity and against max_ids);
+// with a single chunk the pass is complete and also writes the tile map.
 __device__ __forceinline__ void dec_plan_end(const DecPlanArgs &a, uint32_t tiles, uint64_t ids) {
     a.tile_base[a.nseg] = tiles;
     a.out_off[a.nseg] = ids;
-    if (ids > a.out_cap) raise_err(a.err, kErrCapacity);
+    if (ids > a.out_cap || ids > a.max_ids) raise_err(a.err, kErrCapacity);
 }
 
 __global__ __launch_bounds__(1024) void k_dec_local(DecPlanArgs a) {
@@ -1720,11 +1781,11 @@ __global__ __launch_bounds__(1024) void k_dec_local(DecPlanArgs a) {
                 form = 1;
             } else {
                 const uint32_t hn = h[0], hi = h[1], lo = h[2], mg = h[3];
-                const uint64_t nb = cdiv32(hn, kBlock) + 0ull;
+                const uint64_t nb = (uint64_t)(hn >> 7) + ((hn & 127u) != 0u);
                 const uint64_t meta = 16ull + 8ull * nb + 4ull * ((nb + kGroup - 1) / kGroup);
                 bad = mg != kMagic || lo >= hi || hn == 0 || hn > hi - lo || meta > L;
                 n = hn;
-                ng = (uint32_t)((nb + kGroup - 1) / kGroup);
+                ng = dec_seg_tiles(hn);
                 form = 2;
             }
         }
@@ -1767,10 +1828,12 @@ __global__ __launch_bounds__(1024) void k_dec_local(DecPlanArgs a) {
         a.chunk_n[c] = s_c;
         if (gridDim.x == 1) dec_plan_end(a, tt, s_c);  // one chunk: complete, no pass 2
     }
+    if (gridDim.x == 1 && a.tile_seg) dec_tile_map(a, r, xt, ng, lane);
 }
 
-// Pass 2: adds the totals of the chunks before each chunk; the last
-// workgroup writes the batch totals at index nseg and checks the capacity.
+// Pass 2: adds the totals of the chunks before each chunk and writes the
+// tile map; the last workgroup writes the batch totals at index nseg and
+// checks the capacity.
 __global__ __launch_bounds__(1024) void k_dec_fix(DecPlanArgs a) {
     __shared__ unsigned long long s_n[16];
     __shared__ uint32_t s_t[16];
@@ -1795,11 +1858,16 @@ __global__ __launch_bounds__(1024) void k_dec_fix(DecPlanArgs a) {
         pt += s_t[i];
     }
     const uint32_t r = c * kPrepChunk + tid;
+    uint32_t tb = 0, ng = 0;
     if (r < a.nseg) {
-        a.tile_base[r] += pt;
+        tb = a.tile_base[r] + pt;
+        a.tile_base[r] = tb;
         a.out_off[r] += pn;
+        const uint32_t form = a.seg_form[r];
+        ng = form == 1 ? 1u : form == 2 ? dec_seg_tiles(a.seg_n[r]) : 0u;
     }
     if (c + 1 == gridDim.x && tid == 0) dec_plan_end(a, pt + a.chunk_t[c], pn + a.chunk_n[c]);
+    if (a.tile_seg) dec_tile_map(a, r, tb, ng, lane);
 }
 
 struct DecArgs {
@@ -1814,6 +1882,8 @@ struct DecArgs {
     uint64_t out_cap;
     uint32_t *err;
     uint32_t strided;       // unit order of the staged decoder (else contiguous per wave)
+    const uint32_t *tile_seg;  // segment of every tile (NULL: found by search)
+    uint64_t map_cap;          // tiles the map holds
 };
 
 // w-bit field at bit pos of the staged words (funnel shift of two words).
@@ -1828,6 +1898,14 @@ __device__ __forceinline__ uint32_t block_words(uint32_t cls, uint32_t param, ui
     if (cls <= 33) return cdiv32(m * (cls - 1), 32);
     const uint32_t E = aux & 0xFFu;
     return cdiv32(m * param, 32) + cdiv32(E, 4) + cdiv32(E * (aux >> 8), 32);
+}
+
+// Whether a block's last ID, v0 + s (s < 2^32), reaches hi or the next
+// block's first ID: in 32-bit scalar arithmetic, a sum that wraps being past
+// both (each below 2^32).
+__device__ __forceinline__ bool last_past(uint32_t v0, uint32_t s, uint32_t hi, bool has_next, uint32_t nxt) {
+    const uint32_t l = v0 + s;
+    return (l < v0) | (l >= hi) | (has_next & (l >= nxt));
 }
 
 // The IDs of one block (lane: xa = ID lane, xb = ID 64 + lane) and whether
@@ -1850,10 +1928,9 @@ __device__ __forceinline__ bool decode_vals(const uint32_t *buf, uint32_t bw, ui
             const uint64_t zero = ballot((lane != 0) & (da == 0u)) | ballot(db == 0u);
             const uint32_t sa = wave_incl_scan(da);
             const uint32_t sb = wave_incl_scan(db) + readlane(sa, 63);
-            const uint64_t last = (uint64_t)v0 + readlane(sb, 63);
             xa_out = v0 + sa;
             xb_out = v0 + sb;
-            return !((zero != 0ull) | (last >= hi) | (has_next & (last >= nxt)));
+            return !((zero != 0ull) | last_past(v0, readlane(sb, 63), hi, has_next, nxt));
         }
         if ((cls == kClsPfor) & (param + (aux >> 8) <= 24)) {
             // PFOR whose deltas have at most 24 bits (b low bits, h high bits
@@ -1885,10 +1962,9 @@ __device__ __forceinline__ bool decode_vals(const uint32_t *buf, uint32_t bw, ui
             const uint64_t bad = ballot(badx) | ballot((lane != 0) & (da == 0u)) | ballot(db == 0u);
             const uint32_t sa = wave_incl_scan(da);
             const uint32_t sb = wave_incl_scan(db) + readlane(sa, 63);
-            const uint64_t last = (uint64_t)v0 + readlane(sb, 63);
             xa_out = v0 + sa;
             xb_out = v0 + sb;
-            return !((bad != 0ull) | (last >= hi) | (has_next & (last >= nxt)));
+            return !((bad != 0ull) | last_past(v0, readlane(sb, 63), hi, has_next, nxt));
         }
     } else {
         nk = readfirst(nk);
@@ -2196,18 +2272,17 @@ __device__ __forceinline__ void dec_full_unit(uint32_t NB, const uint32_t *pu, u
             __builtin_amdgcn_wave_barrier();
             xa = val[lane];
             xb = val[lane + 64];
-            if (ok) {
-                const uint32_t lst = readlane(xb, 63);
-                ok = !((uint64_t)v0 + (lst - v0) >= (uint64_t)hi || (has_next && lst >= nxt));
-            }
+            if (ok) ok = !last_past(v0, readlane(xb, 63) - v0, hi, has_next, nxt);
         } else {
             ok = decode_vals<true>(bm, 0u, val, cls, (e1 >> 8) & 0xFFu, aux, v0, kBlock, hi, has_next, nxt, lane,
                                    xa, xb);
         }
-        if (ok) {
+        // a scalar branch, both sides uniform (the compiler issues the
+        // atomic from one lane)
+        if (readfirst(ok ? 1u : 0u)) {
             dst[kk * kBlock + lane] = xa;
             dst[kk * kBlock + 64 + lane] = xb;
-        } else if (lane == 0) {
+        } else {
             raise_err(err, kErrCorrupt);
         }
         __builtin_amdgcn_wave_barrier();
@@ -2419,58 +2494,81 @@ __device__ __forceinline__ void dec_raw(const uint32_t *src, uint32_t n, uint32_
 // half; a full half that fits goes to dec_full_unit, any other block by
 // block, the next block's words in flight while the current one decodes.
 // Whole groups read and check each directory entry once.
-template <int WAVES, bool STAGE, bool GROUP>
+template <int WAVES, bool STAGE, bool GROUP, bool MAP>
 __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
     constexpr uint32_t kWin = kHalf * kBlock;
     constexpr uint32_t kPerLane = kWin / 64;
     __shared__ uint32_t s_win[WAVES][kWin + 4];
     __shared__ uint32_t s_val[WAVES][192];  // 128 IDs, 64 spare slots
-    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t tiles = readfirst(a.tile_base[a.nseg]);
+    // wave index made scalar: units, tiles and groups are scalar values
+    const uint32_t lane = threadIdx.x & 63, w = readfirst(threadIdx.x >> 6);
+    const uint32_t tiles = ldc(a.tile_base + a.nseg);
     constexpr bool by_group = GROUP && !STAGE;
     uint32_t *win = s_win[w];
     uint32_t *val = s_val[w];
     UnitRange ur = unit_range(by_group ? tiles : 2 * tiles, WAVES, w, a.strided);
-    SegCursor c;
+    // The segment of the wave's next unit is found while the current one
+    // decodes: from the plan's tile map (MAP), else by search.  Nothing about
+    // the segment is carried from one unit to the next (its fields are
+    // loaded again, from the cache), so that they all stay scalar values to
+    // the compiler.  The plan, the map and the stream's headers and group
+    // table come by scalar loads: the wave waits on them without waiting for
+    // its stores of the unit before.  A batch of more tiles than the map
+    // holds claims more than max_ids IDs, which the plan has reported: it is
+    // not decoded.
+    if (MAP && tiles > a.map_cap) return;
+    auto seg_of = [&](uint32_t uu) -> uint32_t {
+        const uint32_t tt = by_group ? uu : uu >> 1;
+        if constexpr (MAP) return ldc(a.tile_seg + tt);
+        else return wave_find(a.tile_base, a.nseg, tt, lane);
+    };
+    uint32_t rn = ur.begin < ur.end ? seg_of(ur.begin) : 0u;
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
         const uint32_t t = by_group ? u : u >> 1;
         const uint32_t h0 = by_group ? 0u : (u & 1), h1 = by_group ? 2u : h0 + 1;  // the halves to decode
-        if (c.seek(a.tile_base, a.nseg, t, lane, a.strided)) {
-            c.n = readfirst(a.seg_n[c.r]);
-            c.form = readfirst(a.seg_form[c.r]);
-            c.S = readfirst64(a.seg_byte_off[c.r]);
-            c.bytes = readfirst64(a.seg_byte_off[c.r + 1]) - c.S;
-            c.base = readfirst64(a.out_off[c.r]);
-            if (c.form == 2) {
-                const uint32_t *sg = (const uint32_t *)(a.in + c.S);
-                c.hi = readfirst(sg[1]);
-                c.lo = readfirst(sg[2]);
-            }
-        }
-        if (c.form != 2) {
+        // this unit's segment, and the next one's (the last unit's again at
+        // the end: the load is unconditional, so that it stays in flight)
+        const uint32_t r = rn;
+        rn = seg_of(min(u + ur.step, ur.end - 1));
+        const uint32_t t_first = ldc(a.tile_base + r);
+        const uint32_t n = ldc(a.seg_n + r);
+        const uint32_t form = ldc(a.seg_form + r);
+        const uint64_t S = ldc(a.seg_byte_off + r);
+        const uint64_t bytes = ldc(a.seg_byte_off + r + 1) - S;
+        const uint64_t oo = ldc(a.out_off + r);
+        asm volatile("" ::"s"(t_first), "s"(n), "s"(form), "s"(S), "s"(bytes), "s"(oo));  // one round
+        const uint32_t *seg = (const uint32_t *)(a.in + S);
+        if (form != 2) {
             // a raw segment's one tile (empty segments have none)
-            if (h0 == 0) dec_raw((const uint32_t *)(a.in + c.S), c.n, a.out, c.base, a.out_cap, a.err, lane);
+            if (h0 == 0) dec_raw(seg, n, a.out, oo, a.out_cap, a.err, lane);
             continue;
         }
-        const uint32_t g = t - c.t_first;
-        const uint32_t n = c.n;
+        const uint32_t g = t - t_first;
         const uint32_t nb = cdiv32(n, kBlock), ng = cdiv32(nb, kGroup);
         const uint32_t k0 = g * kGroup;
         const uint32_t gblk = min(kGroup, nb - k0);
         if (h0 * kHalf >= gblk) continue;
-        const uint64_t bytes = c.bytes;
-        const uint32_t *seg = (const uint32_t *)(a.in + c.S);
-        const uint32_t lo = c.lo, hi = c.hi;
         const uint32_t metaw = 4 + 2 * nb + ng;
         const uint64_t availw = bytes / 4 - metaw;
-        const uint64_t oo = c.base;
-        // lane i < gblk: block k0+i of the group; lane gblk: the next block's first value
-        bool bad = false;
-        uint32_t words = 0, cls = 0, param = 0, aux = 0, first = 0, e1v = 0;
+        // one round of loads: the header's bounds and the group-table entries
+        // (scalar), the directory entries (lane i < gblk: block k0+i of the
+        // group; lane gblk: the next block's first value)
+        const uint32_t hi = ldc(seg + 1), lo = ldc(seg + 2);
+        const bool last_g = g + 1 >= ng;
+        const uint32_t gt = ldc(seg + 4 + 2 * nb + g);
+        const uint32_t gtn = last_g ? 0u : ldc(seg + 4 + 2 * nb + g + 1);
+        uint32_t first = 0, e1v = 0;
         if (lane <= gblk && k0 + lane < nb) {
             first = seg[4 + 2 * (k0 + lane)];
-            const uint32_t e1 = seg[4 + 2 * (k0 + lane) + 1];
-            e1v = e1;
+            e1v = seg[4 + 2 * (k0 + lane) + 1];
+        }
+        // the round lands here on every path (no load left in flight into
+        // the next unit, where a register's reuse would wait for all stores)
+        asm volatile("" ::"v"(first), "v"(e1v), "s"(hi), "s"(lo), "s"(gt), "s"(gtn));
+        bool bad = false;
+        uint32_t words = 0, cls = 0, param = 0, aux = 0;
+        if (lane <= gblk && k0 + lane < nb) {
+            const uint32_t e1 = e1v;
             if (lane < gblk) {
                 cls = e1 & 0xFFu;
                 param = (e1 >> 8) & 0xFFu;
@@ -2493,14 +2591,16 @@ __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
         }
         const uint32_t incl = wave_incl_scan(lane < gblk ? words : 0u);
         const uint32_t A = readlane(incl, 63);
-        const uint32_t gt = readfirst(seg[4 + 2 * nb + g]);
         const uint32_t off = gt + incl - words;
-        bool ok = ballot(bad) == 0ull;
-        ok = ok && (uint64_t)gt + A <= availw;
-        if (g + 1 < ng) ok = ok && seg[4 + 2 * nb + g + 1] == gt + A;
-        else ok = ok && (uint64_t)gt + A == availw;
-        if (!ok) {
-            if (lane == 0) raise_err(a.err, kErrCorrupt);
+        const uint64_t endw = (uint64_t)gt + A;
+        // the group's checks combined without short-circuit branches and
+        // taken as a scalar: a 64-bit comparison is a vector instruction,
+        // and a branch on its lane mask would make the rest of the loop
+        // divergent in the compiler's eyes (the cursor and the bounds copied
+        // to vector registers, the block loop exec-masked)
+        const bool ok = (ballot(bad) == 0ull) & (endw <= availw) & (last_g ? endw == availw : gtn == gt + A);
+        if (!readfirst(ok ? 1u : 0u)) {
+            raise_err(a.err, kErrCorrupt);
             continue;
         }
         const uint32_t *pay = seg + metaw;
@@ -2935,14 +3035,38 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }
 
+// The decoding pass for the tuned unit shape: k_decode_r, or k_decode_u
+// with whole groups per unit when the batch can give every wave at least
+// eight of them (as the pack passes do with tiles), else half groups.
+template <int W, bool MAP>
+static void launch_dec_units(const bfsc_ctx *ctx, const DecArgs &a, uint32_t per_cu, uint64_t units,
+                             uint64_t max_ids, hipStream_t s) {
+    if (ctx->tune.dec_mode & 4u) {
+        const uint32_t g = resident_grid(ctx, (const void *)k_decode_r<W>, W * 64, per_cu, units);
+        hipLaunchKernelGGL((k_decode_r<W>), dim3(g), dim3(W * 64), 0, s, a);
+    } else if (ctx->tune.dec_mode & 1u) {
+        const uint32_t g = resident_grid(ctx, (const void *)k_decode_u<W, false, true, MAP>, W * 64, per_cu, units);
+        if (max_ids / (kBlock * kGroup) >= 8ull * g * W) {
+            hipLaunchKernelGGL((k_decode_u<W, false, true, MAP>), dim3(g), dim3(W * 64), 0, s, a);
+        } else {
+            const uint32_t gh =
+                resident_grid(ctx, (const void *)k_decode_u<W, false, false, MAP>, W * 64, per_cu, units);
+            hipLaunchKernelGGL((k_decode_u<W, false, false, MAP>), dim3(gh), dim3(W * 64), 0, s, a);
+        }
+    } else {
+        const uint32_t g = resident_grid(ctx, (const void *)k_decode_u<W, true, false, MAP>, W * 64, per_cu, units);
+        hipLaunchKernelGGL((k_decode_u<W, true, false, MAP>), dim3(g), dim3(W * 64), 0, s, a);
+    }
+}
+
+// The per-segment plan, then the segment of every tile (u32 per tile).
 size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg) {
-    (void)max_ids;
-    return dec_ws_bytes(nseg);
+    return dec_ws_bytes(nseg) + align256(plan_max_tiles(max_ids, nseg) * 4);
 }
 
 int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                   uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
-                  void *ws, hipStream_t s, bool timed) {
+                  void *ws, hipStream_t s, bool timed, bool tile_map) {
     char *wb = (char *)ws;
     const size_t arr = align256(((size_t)nseg + 1) * 4);
     uint32_t *seg_n = (uint32_t *)wb;
@@ -2962,6 +3086,10 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     pa.tile_base = tile_base;
     pa.chunk_n = chunk_n;
     pa.chunk_t = chunk_t;
+    const uint64_t mt = plan_max_tiles(max_ids, nseg);
+    pa.tile_seg = tile_map ? (uint32_t *)(wb + dec_ws_bytes(nseg)) : nullptr;
+    pa.map_cap = tile_map ? mt : 0;
+    pa.max_ids = max_ids;
     pa.err = ctx->err;
     hipLaunchKernelGGL(k_dec_local, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
     if (chunks > 1) hipLaunchKernelGGL(k_dec_fix, dim3(chunks), dim3(kPrepChunk), 0, s, pa);
@@ -2977,36 +3105,22 @@ int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off
     a.out_cap = out_cap;
     a.err = ctx->err;
     a.strided = (ctx->tune.dec_mode >> 1) & 1u;
-    const uint64_t mt = plan_max_tiles(max_ids, nseg);
+    a.tile_seg = pa.tile_seg;
+    a.map_cap = pa.map_cap;
     const uint64_t units = 2 * mt;  // at most (half groups)
     const uint32_t per_cu = ctx->tune.dec_wg_per_cu;
     const int slot = timed ? timing_begin(ctx, BFSC_OP_DECODE, s) : -1;
-#define BFSC_DEC_LAUNCH(K, W)                                                                \
-    hipLaunchKernelGGL(K, dim3(resident_grid(ctx, (const void *)K, W * 64, per_cu, units)), \
-                       dim3(W * 64), 0, s, a)
-    // whole groups per unit when the batch can give every wave at least
-    // eight of them (as the pack passes do with tiles), else half groups
-#define BFSC_DEC_CASE(W)                                                                            \
-    if (ctx->tune.dec_mode & 4u) {                                                                  \
-        BFSC_DEC_LAUNCH((k_decode_r<W>), W);                                                        \
-    } else if (ctx->tune.dec_mode & 1u) {                                                           \
-        const uint32_t g = resident_grid(ctx, (const void *)k_decode_u<W, false, true>, W * 64, per_cu, units); \
-        if (max_ids / (kBlock * kGroup) >= 8ull * g * W)                                            \
-            hipLaunchKernelGGL((k_decode_u<W, false, true>), dim3(g), dim3(W * 64), 0, s, a);       \
-        else                                                                                        \
-            BFSC_DEC_LAUNCH((k_decode_u<W, false, false>), W);                                      \
-    } else {                                                                                        \
-        BFSC_DEC_LAUNCH((k_decode_u<W, true, false>), W);                                           \
+    if (tile_map) {
+        switch (ctx->tune.dec_waves) {
+            case 1: launch_dec_units<1, true>(ctx, a, per_cu, units, max_ids, s); break;
+            case 2: launch_dec_units<2, true>(ctx, a, per_cu, units, max_ids, s); break;
+            case 8: launch_dec_units<8, true>(ctx, a, per_cu, units, max_ids, s); break;
+            case 16: launch_dec_units<16, true>(ctx, a, per_cu, units, max_ids, s); break;
+            default: launch_dec_units<4, true>(ctx, a, per_cu, units, max_ids, s); break;
+        }
+    } else {
+        launch_dec_units<4, false>(ctx, a, per_cu, units, max_ids, s);
     }
-    switch (ctx->tune.dec_waves) {
-        case 1: BFSC_DEC_CASE(1) break;
-        case 2: BFSC_DEC_CASE(2) break;
-        case 8: BFSC_DEC_CASE(8) break;
-        case 16: BFSC_DEC_CASE(16) break;
-        default: BFSC_DEC_CASE(4) break;
-    }
-#undef BFSC_DEC_LAUNCH
-#undef BFSC_DEC_CASE
     timing_end(ctx, slot, s);
     return hipGetLastError() == hipSuccess ? BFSC_OK : BFSC_E_HIP;
 }

@@ -61,6 +61,15 @@ __device__ __forceinline__ uint64_t readfirst64(uint64_t v) {
     return ((uint64_t)readfirst((uint32_t)(v >> 32)) << 32) | readfirst((uint32_t)v);
 }
 
+// A load from memory that no kernel writes while the calling one runs,
+// through the constant address space: with a wave-uniform address the
+// compiler issues a scalar load, which the wave waits on with lgkmcnt and so
+// never behind its own outstanding vector stores.
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)(uintptr_t)p;
+}
+
 __device__ __forceinline__ uint32_t shfl_up(uint32_t v, int d) { return __shfl_up(v, d, 64); }
 __device__ __forceinline__ uint32_t shfl_down(uint32_t v, int d) { return __shfl_down(v, d, 64); }
 __device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int d) { return __shfl_xor(v, d, 64); }
@@ -340,7 +349,7 @@ int launch_select(bfsc_ctx *ctx, const bfsc_batch *b, int mode, uint8_t *classes
                   uint64_t *fallbacks, uint16_t *feat, const Plan &p, hipStream_t s);
 int launch_decode(bfsc_ctx *ctx, const uint8_t *in, const uint64_t *seg_byte_off, uint32_t nseg,
                   uint64_t max_ids, uint32_t *out_ids, uint64_t out_cap, uint64_t *out_off,
-                  void *ws, hipStream_t s, bool timed = true);
+                  void *ws, hipStream_t s, bool timed = true, bool tile_map = true);
 size_t decode_ws_bytes(uint64_t max_ids, uint32_t nseg);
 int launch_partition(const uint32_t *ids, const uint32_t *n_dev, const uint32_t *bounds,
                      uint32_t nseg, uint64_t *seg_off, hipStream_t s);

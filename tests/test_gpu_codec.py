@@ -178,9 +178,16 @@ def test_capacity_is_reported(ctx, dec_mode):
     ctx.set_tune(dec_mode=dec_mode)
     try:
         st, _, _ = gpu_decode(ctx, stream, sbo, max_ids=b.n_ids, out_cap=b.n_ids // 2)
+        assert st == 2
+        # a stream holding more IDs than max_ids, with room in the output
+        st, _, _ = gpu_decode(ctx, stream, sbo, max_ids=b.n_ids - 1, out_cap=b.n_ids)
+        assert st == 2
+        # and the exact bound is fine
+        st, ids, _ = gpu_decode(ctx, stream, sbo, max_ids=b.n_ids, out_cap=b.n_ids)
+        assert st == 0
+        np.testing.assert_array_equal(ids, b.ids)
     finally:
         ctx.set_tune(dec_mode=3)
-    assert st == 2
 
 
 @pytest.mark.parametrize("dec_mode", [0, 1, 2, 3, 4, 6])
