@@ -1042,23 +1042,27 @@ __global__ __launch_bounds__(WAVES * 64, 6) void k_enc_pack_u(EncArgs a) {
     const bool by_tile = (uint64_t)tiles >= 8ull * gridDim.x * WAVES;
     uint32_t *sid = s_ids[STAGE || kGrp ? w : 0];
     UnitRange ur = unit_range(by_tile ? tiles : 2 * tiles, WAVES, w, a.strided);
-    // the tile's segment from the plan's tile map, loaded one unit ahead;
-    // the segment's fields are loaded again for every unit (from the cache),
-    // so that nothing is carried from unit to unit and they all stay scalar
-    uint2 tsn = make_uint2(0u, 0u);
-    if (ur.begin < ur.end) tsn = a.p.tile_seg[by_tile ? ur.begin : ur.begin >> 1];
+    // the tile's segment from the plan's tile map, loaded one unit ahead
+    // (the last unit's again at the end: the load is unconditional, so that
+    // it stays in flight); the segment's fields are loaded again for every
+    // unit (from the cache), so that nothing is carried from unit to unit
+    // and they all stay scalar.  All by scalar loads, in one round: the wave
+    // waits on them without waiting for its stores of the unit before.
+    uint64_t tsn = 0;  // (segment, its first tile) of a tile, as one word
+    if (ur.begin < ur.end) tsn = ldc((const uint64_t *)(a.p.tile_seg + (by_tile ? ur.begin : ur.begin >> 1)));
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
         const uint32_t t = by_tile ? u : u >> 1;
         const uint32_t h0 = by_tile ? 0u : (u & 1), h1 = by_tile ? 2u : h0 + 1;  // the halves to pack
-        const uint32_t r = readfirst(tsn.x), t_first = readfirst(tsn.y);
-        const uint64_t un = (uint64_t)u + ur.step;
-        if (un < ur.end) tsn = a.p.tile_seg[by_tile ? (uint32_t)un : (uint32_t)(un >> 1)];
-        const uint32_t bb = readfirst(a.p.blk_base[r]);
-        const uint32_t n = readfirst(a.p.seg_n[r]);
+        const uint32_t r = (uint32_t)tsn, t_first = (uint32_t)(tsn >> 32);
+        const uint32_t un = min(u + ur.step, ur.end - 1);
+        tsn = ldc((const uint64_t *)(a.p.tile_seg + (by_tile ? un : un >> 1)));
+        const uint32_t bb = ldc(a.p.blk_base + r), be = ldc(a.p.blk_base + r + 1);
+        const uint32_t n = ldc(a.p.seg_n + r);
+        const uint32_t lo = ldc(a.seg_lo + r), hi = ldc(a.seg_hi + r);
+        const uint64_t base = ldc(a.seg_off + r);
+        asm volatile("" ::"s"(bb), "s"(be), "s"(n), "s"(lo), "s"(hi), "s"(base));
         // a raw segment's IDs are copied by the place pass: no blocks
-        const uint32_t nb = n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[r + 1]) - bb;
-        const uint32_t lo = readfirst(a.seg_lo[r]), hi = readfirst(a.seg_hi[r]);
-        const uint64_t base = readfirst64(a.seg_off[r]);
+        const uint32_t nb = n < a.p.raw_below ? 0u : be - bb;
         const uint32_t g = t - t_first;
         for (uint32_t h = h0; h < h1; ++h) {
             const uint32_t k0 = g * kGroup + h * kHalf;
@@ -1218,31 +1222,30 @@ __global__ __launch_bounds__(WAVES * 64, 4) void k_enc_pack_l(EncArgs a) {
     __shared__ uint32_t s_span[WAVES][kGroup];
     __shared__ uint32_t s_wmin[WAVES][kHalf];
     __shared__ uint8_t s_sel[WAVES][kGroup];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = readfirst(tid >> 6);  // scalar wave index: units and tiles are scalar
     mlp_mfma_stage(&s_w, a.w, tid, WAVES * 64);
     __syncthreads();
-    const uint32_t tiles = readfirst(a.p.tile_base[a.nseg]);
+    const uint32_t tiles = ldc(a.p.tile_base + a.nseg);
     const bool by_tile = (uint64_t)tiles >= 8ull * gridDim.x * WAVES;
     uint32_t *sid = s_ids[w];
     UnitRange ur = unit_range(by_tile ? tiles : 2 * tiles, WAVES, w, a.strided);
-    // the tile's segment from the plan's tile map, loaded one unit ahead;
-    // the segment's fields are loaded again for every unit (from the cache),
-    // so that nothing is carried from unit to unit and they all stay scalar
-    uint2 tsn = make_uint2(0u, 0u);
-    if (ur.begin < ur.end) tsn = a.p.tile_seg[by_tile ? ur.begin : ur.begin >> 1];
+    // the tile's segment and its fields as in k_enc_pack_u
+    uint64_t tsn = 0;  // (segment, its first tile) of a tile, as one word
+    if (ur.begin < ur.end) tsn = ldc((const uint64_t *)(a.p.tile_seg + (by_tile ? ur.begin : ur.begin >> 1)));
     for (uint32_t u = ur.begin; u < ur.end; u += ur.step) {
         const uint32_t t = by_tile ? u : u >> 1;
         const uint32_t h0 = by_tile ? 0u : (u & 1), h1 = by_tile ? 2u : h0 + 1;  // the halves to pack
-        const uint32_t r = readfirst(tsn.x), t_first = readfirst(tsn.y);
-        const uint64_t un = (uint64_t)u + ur.step;
-        if (un < ur.end) tsn = a.p.tile_seg[by_tile ? (uint32_t)un : (uint32_t)(un >> 1)];
-        const uint32_t bb = readfirst(a.p.blk_base[r]);
-        const uint32_t n = readfirst(a.p.seg_n[r]);
+        const uint32_t r = (uint32_t)tsn, t_first = (uint32_t)(tsn >> 32);
+        const uint32_t un = min(u + ur.step, ur.end - 1);
+        tsn = ldc((const uint64_t *)(a.p.tile_seg + (by_tile ? un : un >> 1)));
+        const uint32_t bb = ldc(a.p.blk_base + r), be = ldc(a.p.blk_base + r + 1);
+        const uint32_t n = ldc(a.p.seg_n + r);
+        const uint32_t lo = ldc(a.seg_lo + r), hi = ldc(a.seg_hi + r);
+        const uint64_t base = ldc(a.seg_off + r);
+        const int32_t level = a.seg_level ? ldc(a.seg_level + r) : 0;
+        asm volatile("" ::"s"(bb), "s"(be), "s"(n), "s"(lo), "s"(hi), "s"(base), "s"(level));
         // a raw segment's IDs are copied by the place pass: no blocks
-        const uint32_t nb = n < a.p.raw_below ? 0u : readfirst(a.p.blk_base[r + 1]) - bb;
-        const uint32_t lo = readfirst(a.seg_lo[r]), hi = readfirst(a.seg_hi[r]);
-        const uint64_t base = readfirst64(a.seg_off[r]);
-        const int32_t level = a.seg_level ? (int32_t)readfirst((uint32_t)a.seg_level[r]) : 0;
+        const uint32_t nb = n < a.p.raw_below ? 0u : be - bb;
         const uint32_t g = t - t_first;
         if (by_tile && nb >= (g + 1) * kGroup && (uint64_t)(g + 1) * kGroup * kBlock <= n) {
             // sixteen full blocks: features of both halves, one evaluation of
@@ -2500,8 +2503,10 @@ __global__ __launch_bounds__(WAVES * 64, DEC_OCC) void k_decode_u(DecArgs a) {
     constexpr uint32_t kPerLane = kWin / 64;
     __shared__ uint32_t s_win[WAVES][kWin + 4];
     __shared__ uint32_t s_val[WAVES][192];  // 128 IDs, 64 spare slots
-    // wave index made scalar: units, tiles and groups are scalar values
-    const uint32_t lane = threadIdx.x & 63, w = readfirst(threadIdx.x >> 6);
+    // (a scalar wave index, which makes units, tiles and groups scalar
+    // values, moves address and loop arithmetic onto the scalar unit that
+    // the block loop keeps busy: 0.96 against 0.89 ms at scale 26)
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t tiles = ldc(a.tile_base + a.nseg);
     constexpr bool by_group = GROUP && !STAGE;
     uint32_t *win = s_win[w];
