@@ -241,8 +241,11 @@ struct Plan {
 // tile it gets (the selection pass covers them tile by tile).
 constexpr uint32_t kMaxRawBelow = kBlock * kGroup;
 
+// The most tiles a batch of max_ids IDs in nseg segments can have: a
+// segment of n IDs has at most floor(n / 2048) + 1 (a raw or an empty one
+// has one), and the floors sum to at most floor(max_ids / 2048).
 __host__ __device__ inline uint64_t plan_max_tiles(uint64_t max_ids, uint32_t nseg) {
-    return max_ids / (kBlock * kGroup) + 2ull * nseg + 2;
+    return max_ids / (kBlock * kGroup) + nseg + 1;
 }
 
 __host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
