@@ -8,9 +8,10 @@
 // Work decomposition: a tile is one group of <= 16 blocks of one segment.
 // One wave handles one 128-ID block at a time, two IDs per lane (lane l holds
 // IDs l and 64+l, so loads and stores are fully coalesced); cross-lane steps
-// use DPP.  Encode = pack pass (every tile into a private slot; the last
-// workgroup to finish scans the tile sizes) + place pass.  Decode is one pass:
-// the group table gives every tile its payload offset.
+// use DPP.  Encode = plan passes (per-segment counts and offsets, and every
+// tile's segment) + pack pass (every tile into a private slot) + offset scan
+// + place pass.  Decode = plan passes (the same from the stream's headers) +
+// one decoding pass: the group table gives every tile its payload offset.
 #include "common.hpp"
 #include "mlp_mfma.hpp"
 

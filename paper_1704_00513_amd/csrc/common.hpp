@@ -229,7 +229,7 @@ struct Plan {
     uint32_t *unit_off;   // [2 max_tiles] exclusive prefix of unit_words within the unit's chunk
     uint32_t *chunk_words;  // [chunks] payload words of every chunk of kScanChunk units
     uint2 *tile_seg;      // [max_tiles] segment of each tile and the segment's first tile,
-                          // written by the pack pass (encode only)
+                          // written by the plan passes (encode only)
     uint32_t *slots;      // [max_tiles][kSlotWords] (encode only)
     uint8_t *cls_buf;     // [max blocks] a class vector (encode only: the learned choice
                           // with literal widths runs as a separate pass into it)
